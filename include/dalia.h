@@ -1,0 +1,212 @@
+/*
+ * dalia.h -- C ABI of libdalia_hip.so: evaluation of the INLA objective
+ * f_obj(theta) for spatio-temporal (optionally coregional) latent Gaussian
+ * models on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Gaedke-Merzhaeuser et al., "Accelerated Spatio-Temporal
+ * Bayesian Modeling for Multivariate Gaussian Processes"):
+ *   - Q_p(theta): prior precision of the latent field, SPDE space (x) AR1 time
+ *     (Section II-A), mixed over responses by the coregional form Eq. 11, with
+ *     fixed effects appended (Eq. 2);
+ *   - Q_c(theta) = Q_p + A^T D A (Eq. 4), block tridiagonal with arrowhead
+ *     (BTA) once permuted time-major (Section III-B);
+ *   - f_obj(theta) = log p(theta) + log l(y|theta,x) + log p(x|theta)
+ *                    - log p_G(x|theta,y)                         (Eq. 8)
+ *     which needs log|Q_p|, log|Q_c| (Cholesky, Eq. 1, 3), the conditional
+ *     mean mu (triangular solves) and, for marginal variances, selected
+ *     entries of Q_c^{-1} (selected inversion, Section III).
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named *_dev are device pointers owned by the caller; pointers
+ *     named *_host are host pointers read synchronously during the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; scalar results are written to
+ *     device memory.  One workspace must not be used by two streams at once.
+ *   - Vectors are in BTA order: variable (t, j, s) -- time step t, response j,
+ *     spatial node s -- is at t*b + j*ns + s with b = nv*ns; the fixed effect
+ *     (j, r) is at nt*b + j*nr + r.  N = nt*b + nv*nr.
+ *   - Argument and state errors return synchronously (DL_EINVAL, DL_ESTATE,
+ *     DL_ENOMEM, DL_EHIP).  Numerical failure (a non-positive pivot) is
+ *     reported through info_dev: 0 = ok, k > 0 = first bad pivot at BTA row
+ *     k-1 (LAPACK style); f_obj is then -inf.
+ *   - Nothing is allocated after dl_ws_create; no C++ exception crosses the
+ *     ABI.
+ */
+#ifndef DALIA_H
+#define DALIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DL_OK = 0,
+  DL_EINVAL = 1,   /* bad argument                                   */
+  DL_ENOMEM = 2,   /* device allocation failed                       */
+  DL_ENOTSPD = 3,  /* (reserved: numerical failure goes to info_dev)  */
+  DL_EHIP = 4,     /* a HIP runtime call failed                      */
+  DL_ESTATE = 5,   /* call order violated (e.g. selinv before factor) */
+  DL_ENOTCONV = 6  /* iterative refinement did not converge          */
+} dl_status;
+
+typedef enum { DL_QP = 0, DL_QC = 1, DL_BOTH = 2 } dl_which;
+
+typedef struct dl_model dl_model;  /* theta-independent data on the device */
+typedef struct dl_ws dl_ws;        /* dense BTA workspace for one model    */
+
+/* Host description of a model (all host pointers, read during create).
+ * Mesh: regular nx*nx grid, unit spacing; node (ix, iy) has index iy*nx+ix.
+ * Observation row i of response j lies at time step obs_t[j][i] on the mesh
+ * triangle obs_nodes[j][3i..3i+2] with barycentric weights obs_w[j][3i..],
+ * has covariates obs_x[j][i*nr .. i*nr+nr-1] (row-major) and value y[j][i]. */
+typedef struct dl_model_desc {
+  int32_t nx, nt, nv, nr;
+  int64_t m[3];
+  const int32_t* obs_t[3];
+  const int32_t* obs_nodes[3];
+  const double* obs_w[3];
+  const double* obs_x[3];
+  const double* y[3];
+  const double* theta_prior_mean; /* dim_theta values                     */
+  double theta_prior_sd;          /* sd of the Gaussian prior on theta    */
+  double prior_fixed;             /* precision of each fixed effect       */
+} dl_model_desc;
+
+/* Parts of f_obj (Eq. 8) written by fobj_eval, one record per theta. */
+typedef struct dl_fobj_parts {
+  double f;          /* f_obj(theta)                                   */
+  double logdet_p;   /* log|Q_p|                                       */
+  double logdet_c;   /* log|Q_c|                                       */
+  double quad_p;     /* mu^T Q_p mu                                    */
+  double quad_obs;   /* (y - A mu)^T D (y - A mu)                      */
+  double log_prior;  /* log p(theta)                                   */
+  double log_lik_const; /* sum_j m_j/2 log tau_j - m/2 log(2 pi)      */
+  double reserved;
+} dl_fobj_parts;
+
+/* Number of hyperparameters: 4 for nv = 1, 4*nv + nv(nv-1)/2 otherwise.
+ * theta layout, univariate: [log kappa, phi, log tau_u, log tau_y];
+ * coregional: [log kappa_i (nv), phi_i (nv), log sigma_i (nv),
+ * lambda_k (nv(nv-1)/2), log tau_y_j (nv)], rho = tanh(phi/2). */
+int32_t dl_theta_dim(int32_t nv);
+
+/* Upload a model.  Builds the spatial pattern (Section II-A, SPDE FEM) and
+ * per-(response, time, node) observation index lists on the host (integer
+ * work only) and copies all arrays to the device.  nv in {1,2,3}; nx >= 2;
+ * nt >= 1; nr >= 0; every obs_t < nt and every node < nx*nx. */
+dl_status dl_model_create(const dl_model_desc* desc_host, dl_model** out);
+void dl_model_destroy(dl_model* model);
+
+/* Dimensions: n = nt blocks, b = nv*ns, a = nv*nr, N = n*b + a; bp is the
+ * padded block size used in device storage. */
+dl_status dl_model_dims(const dl_model* model, int64_t* n, int64_t* b,
+                        int64_t* a, int64_t* N, int64_t* bp);
+
+/* Allocate the dense BTA workspace for Q_p and Q_c of `model` (flags: bit 0
+ * = keep storage for selected inversion).  All device memory of the
+ * evaluation path is allocated here. */
+dl_status dl_ws_create(const dl_model* model, int32_t flags, dl_ws** out);
+void dl_ws_destroy(dl_ws* ws);
+/* Device bytes held by the workspace. */
+size_t dl_ws_bytes(const dl_ws* ws);
+
+/* bta_assemble -- step a1+a2: theta (dim_theta doubles, device) ->
+ * coefficient table and log p(theta), then the dense BTA blocks of Q_p and/or
+ * Q_c (Eq. 4, Eq. 11, time-major permutation of Section III-B) and the
+ * right-hand side A^T D y.  Only the lower triangle of each diagonal block
+ * is stored. */
+dl_status bta_assemble(dl_ws* ws, const double* theta_dev, dl_which which,
+                       void* stream);
+
+/* bta_factor -- steps a3+a4: BTA Cholesky of Q_p and/or Q_c in place (per
+ * time step: POTRF of the diagonal block, its inverse, TRSM of the
+ * sub-diagonal and arrow blocks, SYRK/GEMM updates of the next diagonal
+ * block, the arrow and the tip; finally POTRF of the tip).  Writes
+ * log|Q| to logdet_dev[0] (and logdet_dev[1] for DL_BOTH: [Q_p, Q_c]) and
+ * the first bad pivot to info_dev[0] (info_dev[1] for DL_BOTH). */
+dl_status bta_factor(dl_ws* ws, dl_which which, double* logdet_dev,
+                     int64_t* info_dev, void* stream);
+
+/* bta_solve -- step a6: solves Q_c x = rhs with the factor of Q_c, in place
+ * on rhs_inout_dev (N doubles, BTA order).  rhs_inout_dev may be NULL: then
+ * the assembled A^T D y is solved and the mean mu is kept in the
+ * workspace (read it with dl_ws_mean). */
+dl_status bta_solve(dl_ws* ws, double* rhs_inout_dev, void* stream);
+
+/* bta_selinv -- step a7: Takahashi selected inversion of Q_c from its factor
+ * (backward in time); writes diag(Q_c^{-1}) to diag_out_dev (N doubles, BTA
+ * order).  Requires flags bit 0 at dl_ws_create and a prior bta_factor of
+ * Q_c; otherwise DL_ESTATE. */
+dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
+
+/* fobj_eval -- steps a1..a8: f_obj (Eq. 8) for ntheta hyperparameter vectors
+ * (theta_dev: ntheta x dim_theta, row-major).  fobj_dev[k], parts_dev[k]
+ * (may be NULL) and info_dev[2k..2k+1] (Q_p, Q_c pivots; may be NULL)
+ * receive the results.  mu of the last theta stays in the workspace. */
+dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
+                    double* fobj_dev, dl_fobj_parts* parts_dev,
+                    int64_t* info_dev, void* stream);
+
+/* Copy the conditional mean of the last solve (N doubles, BTA order). */
+dl_status dl_ws_mean(dl_ws* ws, double* out_dev, void* stream);
+
+/* Copy one assembled (or factored) block to out_dev, column-major, for
+ * inspection: kind 0 = diagonal block D_t (b x b, lower triangle), 1 =
+ * sub-diagonal block B_t (b x b, rows t+1, cols t), 2 = arrow block R_t
+ * (a x b), 3 = tip (a x a, lower triangle), 4 = right-hand side (N). */
+dl_status dl_ws_get_block(dl_ws* ws, dl_which which, int32_t kind, int32_t t,
+                          double* out_dev, void* stream);
+
+/* ---- dense FP64 block kernels (the building blocks of bta_factor) ------- */
+
+/* C = alpha * op(A) * op(B) + beta * C, column-major, op = transpose when
+ * the flag is set; lower != 0 restricts C to its lower triangle. */
+dl_status dl_dgemm(int32_t transa, int32_t transb, int32_t lower, int64_t M,
+                   int64_t Nn, int64_t K, double alpha, const double* A_dev,
+                   int64_t lda, const double* B_dev, int64_t ldb, double beta,
+                   double* C_dev, int64_t ldc, void* stream);
+
+/* In-place Cholesky of an n x n SPD matrix (lower, column-major): on exit
+ * the lower triangle holds L^{-1} when want_inverse != 0, else L; the
+ * strict upper triangle is zeroed.  logdet_dev[0] = log|A|; info_dev[0] =
+ * first bad pivot (1-based) or 0.  n must be a multiple of 64. */
+dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
+                    double* logdet_dev, int64_t* info_dev, void* stream);
+
+/* ---- launch profiling ------------------------------------------------------
+ * Launch categories of the evaluation path.  With profiling enabled for a
+ * category mask, every launch of those categories is bracketed by HIP events
+ * on the stream it runs on; dl_ws_profile_end waits for them and returns,
+ * per category, the summed kernel time, the number of launches and the
+ * algorithmic floating-point operations and HBM bytes of those launches
+ * (unpadded block sizes; operations that exist only because of padding or
+ * of the inverse-based triangular solve are not counted).  For measurement
+ * only; not for use while the workspace runs in two streams. */
+enum {
+  DL_CAT_POTRF_TILE = 0,  /* 64x64 diagonal-tile Cholesky + inverse       */
+  DL_CAT_PANEL_TRSM = 1,  /* tiles below a diagonal tile times its inverse */
+  DL_CAT_PANEL_SYRK = 2,  /* trailing update inside a diagonal block       */
+  DL_CAT_TRTRI = 3,       /* inverse of the diagonal-block factor          */
+  DL_CAT_TRSM = 4,        /* [B_t; R_t] L_tt^{-T}                          */
+  DL_CAT_UPDATE = 5,      /* D_{t+1}, R_{t+1}, tip Schur updates           */
+  DL_CAT_SOLVE = 6,       /* block forward/backward substitution           */
+  DL_CAT_SELINV = 7,      /* selected-inversion block products             */
+  DL_CAT_ASSEMBLE = 8,    /* sparse-to-dense assembly                      */
+  DL_CAT_OTHER = 9,
+  DL_NCAT = 10
+};
+dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
+                              int32_t max_launches);
+dl_status dl_ws_profile_end(dl_ws* ws, double* ms_by_cat,
+                            int64_t* launches_by_cat, double* flops_by_cat,
+                            double* bytes_by_cat);
+
+const char* dl_status_string(dl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DALIA_H */

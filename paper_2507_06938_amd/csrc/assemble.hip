@@ -1,0 +1,499 @@
+// theta -> coefficients, sparse-to-dense BTA assembly of Q_p and Q_c, the
+// right-hand side A^T D y, quadratic forms and the f_obj combination.
+#include <math.h>
+
+#include "model.hpp"
+
+namespace dl {
+
+// ---- a1: theta -> model coefficients ------------------------------------------
+//
+// Parameters (internal theta): univariate [log kappa, phi, log tau_u,
+// log tau_y]; coregional [log kappa_i, phi_i, log sigma_i, lambda_k,
+// log tau_y_j], rho = tanh(phi/2).  Lambda is the lower-triangular matrix of
+// Eq. 5; the joint precision has blocks (k, j) = sum_i (Lambda^-1)_{ik}
+// (Lambda^-1)_{ij} Q^i (Eq. 11).  Q^i = T^i (x) Q_s^i, Q_s = kappa^4 C +
+// 2 kappa^2 G + G C^-1 G, T the unit-variance AR1 precision.
+__global__ void k_theta_coeffs(ModelDev m, const double* __restrict__ theta,
+                               double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int nv = m.nv;
+  double kap[3], rho[3], tau[3], Li[3][3];
+  double Mw[3][3][3];
+  int bad = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      Li[i][j] = 0.0;
+      for (int k = 0; k < 3; ++k) Mw[i][j][k] = 0.0;
+    }
+  if (nv == 1) {
+    kap[0] = exp(theta[0]);
+    rho[0] = tanh(0.5 * theta[1]);
+    const double tau_u = exp(theta[2]);
+    tau[0] = exp(theta[3]);
+    Mw[0][0][0] = tau_u;
+  } else {
+    const int nl = nv * (nv - 1) / 2;
+    double sg[3], lam[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < nv; ++i) {
+      kap[i] = exp(theta[i]);
+      rho[i] = tanh(0.5 * theta[nv + i]);
+      sg[i] = exp(theta[2 * nv + i]);
+      tau[i] = exp(theta[3 * nv + nl + i]);
+    }
+    for (int k = 0; k < nl; ++k) lam[k] = theta[3 * nv + k];
+    // Lambda of Eq. 5 (nv = 2 keeps its leading 2x2 block)
+    double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    L[0][0] = sg[0];
+    L[1][0] = lam[0] * sg[0];
+    L[1][1] = sg[1];
+    if (nv == 3) {
+      L[2][0] = (lam[2] + lam[0] * lam[1]) * sg[0];
+      L[2][1] = lam[1] * sg[1];
+      L[2][2] = sg[2];
+    }
+    // inverse of the lower-triangular Lambda, column by column
+    for (int c = 0; c < nv; ++c) {
+      for (int r = 0; r < nv; ++r) {
+        if (r < c) { Li[r][c] = 0.0; continue; }
+        double acc = (r == c) ? 1.0 : 0.0;
+        for (int k = c; k < r; ++k) acc -= L[r][k] * Li[k][c];
+        Li[r][c] = acc / L[r][r];
+      }
+    }
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j)
+        for (int k = 0; k < nv; ++k) Mw[i][j][k] = Li[i][j] * Li[i][k];
+  }
+  double q[3][3], Tend[3], Tmid[3], Toff[3];
+  for (int i = 0; i < nv; ++i) {
+    const double k2 = kap[i] * kap[i];
+    q[i][0] = k2 * k2;
+    q[i][1] = 2.0 * k2;
+    q[i][2] = 1.0;
+    const double r = rho[i];
+    const double den = 1.0 - r * r;
+    if (!(den > 0.0) || !isfinite(kap[i]) || !isfinite(tau[i])) bad = 1;
+    Tend[i] = 1.0 / den;
+    Tmid[i] = (1.0 + r * r) / den;
+    Toff[i] = -r / den;
+  }
+  for (int tt = 0; tt < 3; ++tt)
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < 3; ++j)
+        for (int c = 0; c < 3; ++c) {
+          double v = 0.0;
+          if (k < nv && j < nv)
+            for (int i = 0; i < nv; ++i) {
+              const double tv = tt == 0 ? Tend[i] : (tt == 1 ? Tmid[i] : 1.0);
+              v += Mw[i][k][j] * tv * q[i][c];
+            }
+          coef[C_D + ((tt * 3 + k) * 3 + j) * 3 + c] = v;
+        }
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+        if (k < nv && j < nv)
+          for (int i = 0; i < nv; ++i) v += Mw[i][k][j] * Toff[i] * q[i][c];
+        coef[C_B + (k * 3 + j) * 3 + c] = v;
+      }
+  const double two_pi = 6.283185307179586476925286766559;
+  double lp = 0.0;
+  const double sd = m.theta_prior_sd;
+  for (int d = 0; d < m.dim_theta; ++d) {
+    const double z = (theta[d] - m.theta_prior_mean[d]) / sd;
+    lp += -0.5 * log(two_pi * sd * sd) - 0.5 * z * z;
+  }
+  double llc = 0.0;
+  for (int j = 0; j < nv; ++j) {
+    const double mj = (double)(m.m_off[j + 1] - m.m_off[j]);
+    llc += 0.5 * mj * log(tau[j]) - 0.5 * mj * log(two_pi);
+    coef[C_TAU + j] = tau[j];
+  }
+  for (int d = 0; d < m.dim_theta; ++d)
+    if (!isfinite(theta[d])) bad = 1;
+  coef[C_LOGPRIOR] = lp;
+  coef[C_LLCONST] = llc;
+  coef[C_BAD] = bad ? 1.0 : 0.0;
+}
+
+hipError_t launch_theta_coeffs(const ModelDev& m, const double* theta,
+                               double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_coeffs, dim3(1), dim3(64), 0, s, m, theta, coef);
+  return hipGetLastError();
+}
+
+// ---- a2: sparse -> dense BTA assembly --------------------------------------------
+//
+// One workgroup builds column c of time step t in LDS and writes it, whole
+// and coalesced, to the dense blocks: the diagonal block D_t (lower triangle;
+// rows above c are written as zero), the sub-diagonal block B_t of rows t+1,
+// and for Q_c the arrow block R_t.  Q_c's column is Q_p's plus the
+// observation terms tau_j w w^T (Eq. 4), added by one thread in a fixed order
+// so the result does not depend on scheduling.  Padding columns c >= b
+// (up to the padded block size bp) carry a unit diagonal, which leaves the
+// log-determinant unchanged.
+__global__ __launch_bounds__(256) void k_assemble_cols(
+    ModelDev m, const double* __restrict__ coef, AssembleOut o) {
+  extern __shared__ double lds[];
+  const int c = blockIdx.x;
+  const int t = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int bp = m.bp, ap = m.ap, ns = m.ns, nv = m.nv;
+  const int64_t ldbr = bp + ap;
+  double* colD = lds;            // bp
+  double* colB = lds + bp;       // bp
+  double* colR = lds + 2 * bp;   // ap (<= 64)
+  __shared__ double rhs_s;
+  const bool hasB = t + 1 < m.nt;
+  const int64_t dofs = (int64_t)t * bp * bp + (int64_t)c * bp;
+  const int64_t bofs = (int64_t)t * bp * bp + (int64_t)c * bp;
+  const int64_t brofs = (int64_t)t * ldbr * bp + (int64_t)c * ldbr;
+
+  if (c >= m.b) {
+    for (int r = tid; r < bp; r += 256) {
+      const double v = (r == c) ? 1.0 : 0.0;
+      if (o.Dp) { o.Dp[dofs + r] = v; o.Bp[bofs + r] = 0.0; }
+      if (o.Dc) o.Dc[dofs + r] = v;
+    }
+    if (o.Dc)
+      for (int r = tid; r < bp + ap; r += 256) o.BRc[brofs + r] = 0.0;
+    if (tid == 0) o.rhs[(int64_t)t * bp + c] = 0.0;
+    return;
+  }
+  const int j = c / ns;
+  const int s = c - j * ns;
+  for (int r = tid; r < 2 * bp + ap; r += 256) lds[r] = 0.0;
+  __syncthreads();
+  const int tt = (m.nt == 1) ? 2 : ((t == 0 || t == m.nt - 1) ? 0 : 1);
+  const int e0 = m.sp_ptr[s], e1 = m.sp_ptr[s + 1];
+  const int ne = (e1 - e0) * nv;
+  for (int idx = tid; idx < ne; idx += 256) {
+    const int e = e0 + idx / nv;
+    const int k = idx % nv;
+    const int r = k * ns + m.sp_col[e];
+    const double pc = m.sp_C[e], pg = m.sp_G[e], pg2 = m.sp_G2[e];
+    const double* cd = coef + C_D + ((tt * 3 + k) * 3 + j) * 3;
+    colD[r] = cd[0] * pc + cd[1] * pg + cd[2] * pg2;
+    if (hasB) {
+      const double* cb = coef + C_B + (k * 3 + j) * 3;
+      colB[r] = cb[0] * pc + cb[1] * pg + cb[2] * pg2;
+    }
+  }
+  __syncthreads();
+  if (o.Dp) {
+    for (int r = tid; r < bp; r += 256) {
+      o.Dp[dofs + r] = (r >= c) ? colD[r] : 0.0;
+      o.Bp[bofs + r] = colB[r];
+    }
+  }
+  if (!o.Dc) return;
+  __syncthreads();
+  if (tid == 0) {
+    const double tau = coef[C_TAU + j];
+    const int64_t key = ((int64_t)j * m.nt + t) * ns + s;
+    double racc = 0.0;
+    const int nr = m.nr;
+    for (int64_t p = m.no_ptr[key]; p < m.no_ptr[key + 1]; ++p) {
+      const int64_t row = m.no_row[p];
+      const int qs = m.no_q[p];
+      const double wq = m.obs_w[row * 3 + qs];
+      for (int q2 = 0; q2 < 3; ++q2) {
+        const int r = j * ns + m.obs_nodes[row * 3 + q2];
+        colD[r] += tau * m.obs_w[row * 3 + q2] * wq;
+      }
+      for (int rr = 0; rr < nr; ++rr)
+        colR[j * nr + rr] += tau * m.obs_x[row * nr + rr] * wq;
+      racc += tau * wq * m.obs_y[row];
+    }
+    rhs_s = racc;
+  }
+  __syncthreads();
+  for (int r = tid; r < bp; r += 256) {
+    o.Dc[dofs + r] = (r >= c) ? colD[r] : 0.0;
+    o.BRc[brofs + r] = colB[r];
+  }
+  for (int r = tid; r < ap; r += 256) o.BRc[brofs + bp + r] = colR[r];
+  if (tid == 0) o.rhs[(int64_t)t * bp + c] = rhs_s;
+}
+
+// Tips (a x a, identity-padded to ap) and the fixed-effect part of the
+// right-hand side.  Workgroup 0 writes every tip entry outside the
+// per-response covariate blocks; workgroup 1 + e computes one covariate
+// Gram entry (response j, r >= r2) or one right-hand-side entry, summing
+// the response's rows with a fixed reduction tree.
+__global__ __launch_bounds__(256) void k_assemble_tip(
+    ModelDev m, const double* __restrict__ coef, AssembleOut o) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const int nr = m.nr, nv = m.nv, ap = m.ap, a = m.a;
+  const int ngram = nv * nr * nr;
+  if (blockIdx.x == 0) {
+    for (int idx = tid; idx < ap * ap; idx += 256) {
+      const int r = idx % ap, cc = idx / ap;
+      double vp = 0.0;
+      if (r == cc) vp = (r < a) ? m.prior_fixed : 1.0;
+      if (o.Pp) o.Pp[idx] = (r >= cc) ? vp : 0.0;
+      const bool own = r < a && cc < a && (r / (nr > 0 ? nr : 1)) ==
+                                              (cc / (nr > 0 ? nr : 1));
+      if (o.Pc && !(own && r >= cc)) o.Pc[idx] = (r >= cc) ? vp : 0.0;
+    }
+    if (o.Pc)
+      for (int i = a + tid; i < ap; i += 256) o.rhs[(int64_t)m.nt * m.bp + i] = 0.0;
+    return;
+  }
+  if (!o.Pc) return;
+  int e = blockIdx.x - 1;
+  int j, r, r2;
+  bool gram = e < ngram;
+  if (gram) {
+    j = e / (nr * nr);
+    const int rem = e % (nr * nr);
+    r = rem / nr;
+    r2 = rem % nr;
+    if (r2 > r) return;
+  } else {
+    e -= ngram;
+    j = e / nr;
+    r = e % nr;
+    r2 = 0;
+  }
+  const int64_t b0 = m.m_off[j], b1 = m.m_off[j + 1];
+  double acc = 0.0;
+  for (int64_t row = b0 + tid; row < b1; row += 256) {
+    const double xr = m.obs_x[row * nr + r];
+    acc += gram ? xr * m.obs_x[row * nr + r2] : xr * m.obs_y[row];
+  }
+  sh[tid] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) sh[tid] += sh[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double tau = coef[C_TAU + j];
+    if (gram) {
+      const int rr = j * nr + r, cc = j * nr + r2;
+      o.Pc[rr + (int64_t)cc * ap] = tau * sh[0] + (rr == cc ? m.prior_fixed : 0.0);
+    } else {
+      o.rhs[(int64_t)m.nt * m.bp + j * nr + r] = tau * sh[0];
+    }
+  }
+}
+
+hipError_t launch_assemble(const ModelDev& m, const double* coef,
+                           const AssembleOut& o, hipStream_t s) {
+  const size_t shmem = (size_t)(2 * m.bp + m.ap) * sizeof(double);
+  if (shmem > 65536) {
+    hipError_t a = hipFuncSetAttribute(
+        (const void*)k_assemble_cols,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (a != hipSuccess) return a;
+  }
+  hipLaunchKernelGGL(k_assemble_cols, dim3(m.bp, m.nt), dim3(256), shmem, s, m,
+                     coef, o);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (m.ap > 0) {
+    const int nblk = 1 + m.nv * m.nr * m.nr + m.nv * m.nr;
+    hipLaunchKernelGGL(k_assemble_tip, dim3(nblk), dim3(256), 0, s, m, coef, o);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+// ---- a8: quadratic forms --------------------------------------------------------
+//
+// mu^T Q_p mu with Q_p applied from its stencil (no dense blocks): row
+// (t, k, s') of Q_p mu = sum over time neighbours t' in {t-1, t, t+1},
+// responses j and spatial neighbours s of coef(t,t')_{kj} . (C, G, GC^-1G)
+// at (s', s) times mu(t', j, s); fixed effects add prior_fixed * |mu_f|^2.
+// (y - A mu)^T D (y - A mu) row by row.  Both are reduced with a fixed tree
+// per block, then over blocks in order.
+__device__ __forceinline__ double blk_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+constexpr int QF_BLOCKS = 512;
+
+__global__ __launch_bounds__(256) void k_quad_prior(
+    ModelDev m, const double* __restrict__ coef, const double* __restrict__ mu,
+    double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int64_t nrows = (int64_t)m.nt * m.b;
+  const int ns = m.ns, nv = m.nv, bp = m.bp;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nrows;
+       i += (int64_t)gridDim.x * 256) {
+    const int t = (int)(i / m.b);
+    const int rl = (int)(i - (int64_t)t * m.b);
+    const int k = rl / ns, sp = rl - k * ns;
+    const int tt = (m.nt == 1) ? 2 : ((t == 0 || t == m.nt - 1) ? 0 : 1);
+    double qmu = 0.0;
+    for (int dt = -1; dt <= 1; ++dt) {
+      const int t2 = t + dt;
+      if (t2 < 0 || t2 >= m.nt) continue;
+      for (int j = 0; j < nv; ++j) {
+        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * 3
+                                     : coef + C_B + (k * 3 + j) * 3;
+        const double* x = mu + (int64_t)t2 * bp + j * ns;
+        for (int e = m.sp_ptr[sp]; e < m.sp_ptr[sp + 1]; ++e) {
+          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e];
+          qmu += qv * x[m.sp_col[e]];
+        }
+      }
+    }
+    acc += mu[(int64_t)t * bp + rl] * qmu;
+  }
+  if (blockIdx.x == 0)
+    for (int f = threadIdx.x; f < m.a; f += 256) {
+      const double v = mu[(int64_t)m.nt * bp + f];
+      acc += m.prior_fixed * v * v;
+    }
+  const double s = blk_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_quad_obs(
+    ModelDev m, const double* __restrict__ coef, const double* __restrict__ mu,
+    double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int ns = m.ns, nr = m.nr, bp = m.bp;
+  double acc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < m.m_total;
+       row += (int64_t)gridDim.x * 256) {
+    int j = 0;
+    while (j + 1 < m.nv && row >= m.m_off[j + 1]) ++j;
+    const int t = m.obs_t[row];
+    const double* x = mu + (int64_t)t * bp + j * ns;
+    double pred = 0.0;
+    for (int q = 0; q < 3; ++q) pred += m.obs_w[row * 3 + q] * x[m.obs_nodes[row * 3 + q]];
+    const double* xf = mu + (int64_t)m.nt * bp + j * nr;
+    for (int r = 0; r < nr; ++r) pred += m.obs_x[row * nr + r] * xf[r];
+    const double res = m.obs_y[row] - pred;
+    acc += coef[C_TAU + j] * res * res;
+  }
+  const double s = blk_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_quad_final(const double* partial,
+                                                    double* out2) {
+  __shared__ double sh[256];
+  for (int w = 0; w < 2; ++w) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < QF_BLOCKS; i += 256) acc += partial[w * QF_BLOCKS + i];
+    const double s = blk_sum(acc, sh);
+    if (threadIdx.x == 0) out2[w] = s;
+  }
+}
+
+// out2[0] = mu^T Q_p mu, out2[1] = (y - A mu)^T D (y - A mu);
+// partial needs 2 * QF_BLOCKS doubles.
+hipError_t launch_quadforms(const ModelDev& m, const double* coef,
+                            const double* mu, double* partial, double* out2,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_quad_prior, dim3(QF_BLOCKS), dim3(256), 0, s, m, coef, mu,
+                     partial);
+  hipLaunchKernelGGL(k_quad_obs, dim3(QF_BLOCKS), dim3(256), 0, s, m, coef, mu,
+                     partial + QF_BLOCKS);
+  hipLaunchKernelGGL(k_quad_final, dim3(1), dim3(256), 0, s, partial, out2);
+  return hipGetLastError();
+}
+
+// f_obj of Eq. 8 at x = mu, where the Gaussian p_G term has zero quadratic
+// part and the (2 pi)^{-N/2} factors of Eq. 1 and Eq. 3 cancel:
+// f = log p(theta) + [sum_j m_j/2 log tau_j - m/2 log 2pi - 1/2 quad_obs]
+//     + 1/2 log|Q_p| - 1/2 mu^T Q_p mu - 1/2 log|Q_c|.
+__global__ void k_combine(const double* __restrict__ coef,
+                          const double* __restrict__ logdet2,
+                          const int64_t* __restrict__ info2,
+                          const double* __restrict__ quad2, double* f,
+                          dl_fobj_parts* parts, int64_t* info_out) {
+  if (threadIdx.x != 0) return;
+  const double lp = coef[C_LOGPRIOR];
+  const double llc = coef[C_LLCONST];
+  double v = lp + llc - 0.5 * quad2[1] + 0.5 * logdet2[0] - 0.5 * quad2[0] -
+             0.5 * logdet2[1];
+  const bool fail = info2[0] != 0 || info2[1] != 0 || coef[C_BAD] != 0.0 ||
+                    !isfinite(v);
+  if (fail) v = -__builtin_inf();
+  if (f) f[0] = v;
+  if (parts) {
+    parts->f = v;
+    parts->logdet_p = logdet2[0];
+    parts->logdet_c = logdet2[1];
+    parts->quad_p = quad2[0];
+    parts->quad_obs = quad2[1];
+    parts->log_prior = lp;
+    parts->log_lik_const = llc;
+    parts->reserved = 0.0;
+  }
+  if (info_out) {
+    info_out[0] = info2[0];
+    info_out[1] = info2[1];
+  }
+}
+
+hipError_t launch_combine(const ModelDev& m, const double* coef,
+                          const double* logdet2, const int64_t* info2,
+                          const double* quad2, double* f, dl_fobj_parts* parts,
+                          int64_t* info_out, hipStream_t s) {
+  (void)m;
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, s, coef, logdet2, info2,
+                     quad2, f, parts, info_out);
+  return hipGetLastError();
+}
+
+// padded (t*bp + i, arrow at nt*bp) <-> packed (t*b + i, arrow at nt*b)
+__global__ void k_pack(ModelDev m, const double* __restrict__ in,
+                       double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m.N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = i / m.b;
+    const int64_t src = (t < m.nt) ? t * m.bp + (i - t * m.b)
+                                   : (int64_t)m.nt * m.bp + (i - (int64_t)m.nt * m.b);
+    out[i] = in[src];
+  }
+}
+
+__global__ void k_unpack(ModelDev m, const double* __restrict__ in,
+                         double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m.Np;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = i / m.bp;
+    double v = 0.0;
+    if (t < m.nt) {
+      const int64_t r = i - t * m.bp;
+      if (r < m.b) v = in[t * m.b + r];
+    } else {
+      const int64_t r = i - (int64_t)m.nt * m.bp;
+      if (r < m.a) v = in[(int64_t)m.nt * m.b + r];
+    }
+    out[i] = v;
+  }
+}
+
+hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(1024), dim3(256), 0, s, m, padded, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const ModelDev& m, const double* in, double* padded,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3(1024), dim3(256), 0, s, m, in, padded);
+  return hipGetLastError();
+}
+
+}  // namespace dl

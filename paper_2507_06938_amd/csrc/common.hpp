@@ -1,0 +1,99 @@
+// Shared host/device definitions of libdalia_hip (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+
+#include "../../include/dalia.h"
+
+#define DL_HIP_CHECK(expr)                                   \
+  do {                                                       \
+    hipError_t e__ = (expr);                                 \
+    if (e__ != hipSuccess) return DL_EHIP;                   \
+  } while (0)
+
+namespace dl {
+
+// ---- dense tile GEMM task ------------------------------------------------------
+//
+// C(MxN) = alpha * op(A) * op(B) + beta * C, column-major.
+//   op(A) = A (M x K, lda) or A^T (A stored K x M) when F_TA;
+//   op(B) = B (K x N, ldb) or B^T (B stored N x K) when F_TB.
+// Flags restricting work at tile granularity (operands that are triangular
+// hold exact zeros outside their triangle, so the restriction only skips
+// work):
+//   F_LOWER   : only tiles/elements with row >= col of C are computed;
+//   F_KLO_COL : k >= first column of the C tile; F_KHI_COL : k < last col+1;
+//   F_KLO_ROW : k >= first row of the C tile;    F_KHI_ROW : k < last row+1.
+enum : int {
+  F_TA = 1,
+  F_TB = 2,
+  F_LOWER = 4,
+  F_KLO_COL = 8,
+  F_KHI_COL = 16,
+  F_KLO_ROW = 32,
+  F_KHI_ROW = 64,
+  F_BETA0 = 128,   // ignore beta and the previous C (C may hold NaN)
+};
+
+struct GemmTask {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int32_t M, N, K, flags;
+  double alpha, beta;
+  int32_t tiles_m, tiles_n;  // filled by finalize_tasks
+  int32_t tile_begin;        // first linear tile of this task in its launch
+  int32_t ntiles;
+};
+
+constexpr int GEMM_BM = 64;
+constexpr int GEMM_BN = 64;
+
+// Fill tiles_m/n, ntiles, tile_begin; return total tiles.
+int finalize_tasks(GemmTask* t, int n);
+
+// Launch a batch of tasks already resident in device memory (tasks_dev) with
+// `total_tiles` workgroups.
+hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
+                             int total_tiles, hipStream_t s);
+
+// Convenience: copy host tasks to a device buffer, then launch.  Used by
+// the dense ABI entry points and by plan building (never inside timed
+// evaluation loops, where task arrays are prebuilt).
+struct DeviceTasks {
+  GemmTask* dev = nullptr;
+  int ntask = 0;
+  int total = 0;
+};
+
+// ---- 64x64 diagonal-tile Cholesky ------------------------------------------
+// Factor the nb x nb (nb = 64) SPD tile at A (lda) in place: lower = L, upper
+// zeroed; write L^{-1} to Ginv (64 x 64, ld 64) when Ginv != nullptr;
+// logdiag[i] = log L_ii; on a non-positive pivot set *info = row0 + i + 1
+// (first failure only).  `ntiles` tiles are processed, tile k at
+// A + k*(tile_stride) etc.  The tile has only `valid` leading rows that are
+// real; the rest must be identity-padded by the caller.
+struct PotrfTileArgs {
+  double* A;
+  int64_t lda;
+  double* Ginv;
+  double* logdiag;
+  int64_t* info;
+  int64_t row0;  // global row of the tile's first row (for info)
+};
+hipError_t launch_potrf_tile(const PotrfTileArgs& a, hipStream_t s);
+
+hipError_t launch_copy_tile64(const double* src, int64_t lds, double* dst,
+                              int64_t ldd, int ntiles, int64_t src_tile_stride,
+                              int64_t dst_tile_stride, hipStream_t s);
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_zero_upper_tiles(double* A, int64_t ld, int n, hipStream_t s);
+hipError_t launch_sum_log(const double* logdiag, int64_t n, double scale,
+                          double* out, double* partial, hipStream_t s);
+
+}  // namespace dl

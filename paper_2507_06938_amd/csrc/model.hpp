@@ -1,0 +1,79 @@
+// Device-side model description and per-theta coefficient table layout.
+#pragma once
+#include "common.hpp"
+
+namespace dl {
+
+// Coefficient table written by k_theta_coeffs (FP64, device):
+//   [C_LOGPRIOR]        log p(theta)
+//   [C_LLCONST]         sum_j m_j/2 log tau_j - m/2 log 2pi
+//   [C_BAD]             1 if theta maps outside the model (NaN, |rho| = 1)
+//   [C_TAU + j]         tau_y of response j
+//   [C_D + ((tt*3 + k)*3 + j)*3 + c]
+//                       weight of FEM piece c (0: C, 1: G, 2: G C^-1 G) in
+//                       block (k, j) of a diagonal block; tt = 0 first/last
+//                       time step, 1 interior step, 2 single step (nt = 1)
+//   [C_B + (k*3 + j)*3 + c]  the same for a sub-diagonal block
+enum : int {
+  C_LOGPRIOR = 0,
+  C_LLCONST = 1,
+  C_BAD = 2,
+  C_TAU = 4,
+  C_D = 8,
+  C_B = 8 + 81,
+  C_SIZE = 8 + 81 + 27 + 4
+};
+
+struct ModelDev {
+  int nx, nt, nv, nr, ns, b, a, bp, ap, dim_theta;
+  int64_t N, Np;          // unpadded and padded vector lengths
+  // 13-point spatial pattern of Q_s, CSR over nodes, with FEM pieces
+  const int* sp_ptr;
+  const int* sp_col;
+  const double* sp_C;
+  const double* sp_G;
+  const double* sp_G2;
+  // observations of all responses, concatenated
+  int64_t m_total;
+  int64_t m_off[4];
+  const int* obs_t;
+  const int* obs_nodes;   // m x 3
+  const double* obs_w;    // m x 3
+  const double* obs_x;    // m x nr
+  const double* obs_y;    // m
+  // per (response j, time t, node s): observation rows touching the node
+  const int64_t* no_ptr;  // nv*nt*ns + 1
+  const int* no_row;
+  const int* no_q;
+  const double* theta_prior_mean;
+  double theta_prior_sd;
+  double prior_fixed;
+};
+
+struct AssembleOut {
+  double* Dp;   // nt x (bp x bp), ld bp       (nullptr: skip Q_p)
+  double* Bp;   // slots of bp x bp, ld bp     (slot t for time t)
+  double* Dc;   // nt x (bp x bp)              (nullptr: skip Q_c)
+  double* BRc;  // slots of (bp+ap) x bp, ld bp+ap
+  double* Pp;   // ap x ap (tip of Q_p), ld ap
+  double* Pc;   // ap x ap (tip of Q_c)
+  double* rhs;  // Np
+};
+
+hipError_t launch_theta_coeffs(const ModelDev& m, const double* theta,
+                               double* coef, hipStream_t s);
+hipError_t launch_assemble(const ModelDev& m, const double* coef,
+                           const AssembleOut& o, hipStream_t s);
+hipError_t launch_quadforms(const ModelDev& m, const double* coef,
+                            const double* mu, double* partial, double* out2,
+                            hipStream_t s);
+hipError_t launch_combine(const ModelDev& m, const double* coef,
+                          const double* logdet2, const int64_t* info2,
+                          const double* quad2, double* f, dl_fobj_parts* parts,
+                          int64_t* info_out, hipStream_t s);
+hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
+                       hipStream_t s);
+hipError_t launch_unpack(const ModelDev& m, const double* in, double* padded,
+                         hipStream_t s);
+
+}  // namespace dl

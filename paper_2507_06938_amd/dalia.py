@@ -1,0 +1,297 @@
+"""Thin ctypes binding of libdalia_hip.so.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensors on a ROCm
+device) and the current stream.  If the shared library is missing this
+module raises at import-time use; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
+
+DL_QP, DL_QC, DL_BOTH = 0, 1, 2
+CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
+              "update", "solve", "selinv", "assemble", "other")
+STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
+          3: "not positive definite", 4: "HIP runtime error",
+          5: "call order violated", 6: "refinement did not converge"}
+
+PARTS_FIELDS = ("f", "logdet_p", "logdet_c", "quad_p", "quad_obs",
+                "log_prior", "log_lik_const", "reserved")
+
+
+class DaliaError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nt", C.c_int32), ("nv", C.c_int32),
+                ("nr", C.c_int32), ("m", C.c_int64 * 3),
+                ("obs_t", C.c_void_p * 3), ("obs_nodes", C.c_void_p * 3),
+                ("obs_w", C.c_void_p * 3), ("obs_x", C.c_void_p * 3),
+                ("y", C.c_void_p * 3), ("theta_prior_mean", C.c_void_p),
+                ("theta_prior_sd", C.c_double), ("prior_fixed", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the shared library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2507_06938_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "dl_theta_dim": (i32, [i32]),
+            "dl_model_create": (i32, [vp, C.POINTER(vp)]),
+            "dl_model_destroy": (None, [vp]),
+            "dl_model_dims": (i32, [vp] + [C.POINTER(i64)] * 5),
+            "dl_ws_create": (i32, [vp, i32, C.POINTER(vp)]),
+            "dl_ws_destroy": (None, [vp]),
+            "dl_ws_bytes": (C.c_size_t, [vp]),
+            "bta_assemble": (i32, [vp, vp, i32, vp]),
+            "bta_factor": (i32, [vp, i32, vp, vp, vp]),
+            "bta_solve": (i32, [vp, vp, vp]),
+            "bta_selinv": (i32, [vp, vp, vp]),
+            "fobj_eval": (i32, [vp, vp, i32, vp, vp, vp, vp]),
+            "dl_ws_mean": (i32, [vp, vp, vp]),
+            "dl_ws_get_block": (i32, [vp, i32, i32, i32, vp, vp]),
+            "dl_dgemm": (i32, [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp,
+                               i64, dbl, vp, i64, vp]),
+            "dl_dpotrf": (i32, [i64, vp, i64, i32, vp, vp, vp]),
+            "dl_status_string": (C.c_char_p, [i32]),
+            "dl_ws_profile_begin": (i32, [vp, i32, i32]),
+            "dl_ws_profile_end": (i32, [vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn, code):
+    if code != 0:
+        raise DaliaError(fn, code)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def theta_dim(nv: int) -> int:
+    return int(lib().dl_theta_dim(nv))
+
+
+class Model:
+    """Model data on the device (theta-independent)."""
+
+    def __init__(self, nx: int, nt: int, nv: int, nr: int,
+                 responses: Sequence, theta_prior_mean, theta_prior_sd=1.0,
+                 prior_fixed=1e-3):
+        L = lib()
+        self.nx, self.nt, self.nv, self.nr = nx, nt, nv, nr
+        d = _Desc()
+        d.nx, d.nt, d.nv, d.nr = nx, nt, nv, nr
+        keep = []
+        for j, r in enumerate(responses):
+            t, nodes, w, X, y = r
+            arrs = [np.ascontiguousarray(t, np.int32),
+                    np.ascontiguousarray(nodes, np.int32).reshape(-1),
+                    np.ascontiguousarray(w, np.float64).reshape(-1),
+                    np.ascontiguousarray(X, np.float64).reshape(-1),
+                    np.ascontiguousarray(y, np.float64)]
+            keep.extend(arrs)
+            d.m[j] = arrs[4].shape[0]
+            d.obs_t[j] = arrs[0].ctypes.data
+            d.obs_nodes[j] = arrs[1].ctypes.data
+            d.obs_w[j] = arrs[2].ctypes.data
+            d.obs_x[j] = arrs[3].ctypes.data if arrs[3].size else None
+            d.y[j] = arrs[4].ctypes.data
+        pm = np.ascontiguousarray(theta_prior_mean, np.float64)
+        keep.append(pm)
+        d.theta_prior_mean = pm.ctypes.data
+        d.theta_prior_sd = float(theta_prior_sd)
+        d.prior_fixed = float(prior_fixed)
+        h = C.c_void_p()
+        _check("dl_model_create", L.dl_model_create(C.byref(d), C.byref(h)))
+        self.h = h
+        vals = [C.c_int64() for _ in range(5)]
+        _check("dl_model_dims", L.dl_model_dims(h, *[C.byref(v) for v in vals]))
+        self.n, self.b, self.a, self.N, self.bp = [v.value for v in vals]
+        self.dim_theta = theta_dim(nv)
+
+    @classmethod
+    def from_workload(cls, wl) -> "Model":
+        resp = [(r.t, r.nodes, r.w, r.X, r.y) for r in wl.responses]
+        return cls(wl.nx, wl.nt, wl.nv, wl.nr, resp, wl.theta_prior_mean,
+                   wl.theta_prior_sd, wl.prior_fixed)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dl_model_destroy(self.h)
+            self.h = None
+
+
+class Workspace:
+    """Dense BTA workspace of Q_p and Q_c for one model."""
+
+    def __init__(self, model: Model, selinv: bool = False):
+        self.model = model
+        h = C.c_void_p()
+        _check("dl_ws_create",
+               lib().dl_ws_create(model.h, 1 if selinv else 0, C.byref(h)))
+        self.h = h
+        self.dev = torch.device("cuda")
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().dl_ws_bytes(self.h))
+
+    def _theta(self, theta) -> torch.Tensor:
+        t = torch.as_tensor(theta, dtype=torch.float64)
+        return t.to(self.dev).contiguous()
+
+    def assemble(self, theta, which=DL_BOTH):
+        th = self._theta(theta)
+        _check("bta_assemble", lib().bta_assemble(self.h, _ptr(th), which, _stream()))
+        self._keep = th
+
+    def factor(self, which=DL_BOTH):
+        k = 2 if which == DL_BOTH else 1
+        ld = torch.empty(k, dtype=torch.float64, device=self.dev)
+        info = torch.empty(k, dtype=torch.int64, device=self.dev)
+        _check("bta_factor", lib().bta_factor(self.h, which, _ptr(ld), _ptr(info),
+                                              _stream()))
+        return ld, info
+
+    def solve(self, rhs: Optional[torch.Tensor] = None):
+        if rhs is None:
+            _check("bta_solve", lib().bta_solve(self.h, None, _stream()))
+            return self.mean()
+        _check("bta_solve", lib().bta_solve(self.h, _ptr(rhs), _stream()))
+        return rhs
+
+    def mean(self) -> torch.Tensor:
+        out = torch.empty(self.model.N, dtype=torch.float64, device=self.dev)
+        _check("dl_ws_mean", lib().dl_ws_mean(self.h, _ptr(out), _stream()))
+        return out
+
+    def selinv(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.model.N, dtype=torch.float64, device=self.dev)
+        _check("bta_selinv", lib().bta_selinv(self.h, _ptr(out), _stream()))
+        return out
+
+    def fobj(self, thetas, out=None):
+        """f_obj for each row of thetas; `out` = (f, parts, info) device
+        tensors to write into (no allocation on the call)."""
+        th = thetas if isinstance(thetas, torch.Tensor) and thetas.is_cuda \
+            else torch.as_tensor(thetas, dtype=torch.float64)
+        if th.dim() == 1:
+            th = th[None]
+        th = th.to(self.dev).contiguous()
+        n = th.shape[0]
+        if out is None:
+            f = torch.empty(n, dtype=torch.float64, device=self.dev)
+            parts = torch.empty((n, 8), dtype=torch.float64, device=self.dev)
+            info = torch.empty((n, 2), dtype=torch.int64, device=self.dev)
+        else:
+            f, parts, info = out
+        _check("fobj_eval", lib().fobj_eval(self.h, _ptr(th), n, _ptr(f),
+                                            _ptr(parts), _ptr(info), _stream()))
+        return f, parts, info
+
+    def profile_begin(self, categories=CATEGORIES, max_launches=200000):
+        mask = 0
+        for c in categories:
+            mask |= 1 << CATEGORIES.index(c)
+        _check("dl_ws_profile_begin",
+               lib().dl_ws_profile_begin(self.h, mask, int(max_launches)))
+
+    def profile_end(self) -> dict:
+        n = len(CATEGORIES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        fl = (C.c_double * n)()
+        by = (C.c_double * n)()
+        _check("dl_ws_profile_end", lib().dl_ws_profile_end(self.h, ms, cnt, fl, by))
+        return {c: dict(ms=ms[i], launches=cnt[i], flops=fl[i], bytes=by[i])
+                for i, c in enumerate(CATEGORIES) if cnt[i]}
+
+    def get_block(self, which: int, kind: int, t: int = 0) -> torch.Tensor:
+        m = self.model
+        shape = {0: (m.b, m.b), 1: (m.b, m.b), 2: (m.b, m.a), 3: (m.a, m.a),
+                 4: (m.N,)}[kind]
+        out = torch.empty(shape, dtype=torch.float64, device=self.dev)
+        _check("dl_ws_get_block", lib().dl_ws_get_block(self.h, which, kind, t,
+                                                        _ptr(out), _stream()))
+        # column-major storage -> logical matrix
+        return out.T if out.dim() == 2 else out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            torch.cuda.synchronize()
+            _lib.dl_ws_destroy(self.h)
+            self.h = None
+
+
+# ---- dense kernels -----------------------------------------------------------------
+
+def dgemm(A: torch.Tensor, B: torch.Tensor, C_: torch.Tensor, *, transa=False,
+          transb=False, lower=False, alpha=1.0, beta=0.0):
+    """C = alpha op(A) op(B) + beta C on column-major views: pass tensors
+    whose transpose is contiguous (x.T.contiguous().T), i.e. Fortran order."""
+    def fcol(x):
+        assert x.dtype == torch.float64 and x.is_cuda
+        assert x.stride(0) == 1, "column-major tensor expected"
+        return x.stride(1) if x.dim() == 2 and x.shape[1] > 1 else max(1, x.shape[0])
+    M, N = C_.shape
+    K = (A.shape[0] if transa else A.shape[1])
+    _check("dl_dgemm", lib().dl_dgemm(int(transa), int(transb), int(lower), M, N,
+                                      K, float(alpha), C.c_void_p(A.data_ptr()),
+                                      fcol(A), C.c_void_p(B.data_ptr()), fcol(B),
+                                      float(beta), C.c_void_p(C_.data_ptr()),
+                                      fcol(C_), _stream()))
+    return C_
+
+
+def dpotrf(A: torch.Tensor, inverse: bool = False):
+    """In-place Cholesky (lower, column-major) of a square n x n (n % 64 == 0)
+    tensor; returns (logdet, info) device tensors."""
+    n = A.shape[0]
+    assert A.stride(0) == 1
+    ld = torch.empty(1, dtype=torch.float64, device=A.device)
+    info = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check("dl_dpotrf", lib().dl_dpotrf(n, C.c_void_p(A.data_ptr()), A.stride(1),
+                                        int(inverse), _ptr(ld), _ptr(info),
+                                        _stream()))
+    return ld, info
+
+
+def fortran(x: torch.Tensor) -> torch.Tensor:
+    """Column-major copy of a 2-D tensor (same logical values)."""
+    return x.T.contiguous().T
