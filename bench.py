@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""f_obj throughput on one MI355X.
+
+One step = one full pass of the evaluation path for one hyperparameter
+vector of the production univariate workload (45x45 mesh, b = 2025,
+nt = 100, 4 fixed effects, 200,000 observations): theta -> coefficients,
+assembly of Q_p and Q_c into dense BTA blocks, BTA Cholesky of both,
+log-determinants, forward/backward solve for the conditional mean, the
+quadratic forms and f_obj, then the selected inversion of Q_c for all
+marginal variances.  Inputs are seeded and synthetic and already resident on
+the device when the timed region starts.
+
+Prints one JSON line.  Besides the metric it reports the BTA Cholesky
+TFLOP/s of Q_c alone, the log-determinant error against the FP64 CPU oracle
+(stored values written by tests/golden/make_golden.py), the live roofline of
+the dominant kernel (HIP events around its launches during the timed steps)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("f_obj evals/s + BTA Cholesky TFLOP/s (ns=2000,nt=100); "
+          "logdet rel err vs FP64")
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def fac_flops(n, b, a):
+    """Algorithmic FLOPs of one BTA Cholesky (LAPACK counts: POTRF b^3/3,
+    TRSM m n^2, SYRK n^2 k, GEMM 2mnk)."""
+    return (n * (b ** 3 / 3 + a * b * b + a * a * b)
+            + (n - 1) * (2 * b ** 3 + 2 * a * b * b) + a ** 3 / 3)
+
+
+def cpu_baseline(nt_sample: int = 20, var_samples: int = 8):
+    """The CPU oracle on a bounded sample of the same workload: the same
+    generator and mesh with nt_sample time steps (2,000 observations per
+    step), scaled linearly in nt (banded Cholesky cost is linear in N for a
+    fixed bandwidth), plus var_samples unit-vector variance solves scaled to
+    all N diagonal entries."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import workloads as W
+    from oracle import fobj as OF
+    wl = W.make_univariate("c1_sample", 45, nt_sample, 4, 2000 * nt_sample,
+                           seed=0)
+    t0 = time.perf_counter()
+    p = OF.fobj_parts(wl, wl.theta, method="banded", return_factors=True)
+    t1 = time.perf_counter()
+    idx = np.random.default_rng(0).choice(wl.N, var_samples, replace=False)
+    p["Fc"].inv_diag(idx, chunk=1)
+    t2 = time.perf_counter()
+    scale = 100.0 / nt_sample
+    t_fobj = (t1 - t0) * scale
+    N_full = 100 * 2025 + 4
+    t_var = (t2 - t1) / var_samples * N_full * scale
+    threads = max((i.get("num_threads", 1) for i in threadpool_info()),
+                  default=1)
+    return {
+        "value": 1.0 / (t_fobj + t_var), "unit": "evals/s", "cores": threads,
+        "kind": "oracle",
+        "fobj_only_evals_per_s": 1.0 / t_fobj,
+        "sample": (f"oracle (RCM + LAPACK banded Cholesky) f_obj of the same "
+                   f"generator at nt={nt_sample} ({t1 - t0:.1f} s) scaled x"
+                   f"{scale:g} to nt=100, plus {var_samples} unit-vector "
+                   f"variance solves ({t2 - t1:.1f} s) scaled to all N="
+                   f"{N_full} diagonal entries"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nt", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the "
+              "evaluation path is single-GPU; see DESIGN.md for how it would "
+              "shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_06938_amd import dalia as D
+    if not os.path.exists(D.LIB_PATH):
+        from paper_2507_06938_amd import build as B
+        B.build(verbose=False)
+    import workloads as W
+
+    wl = W.config1()
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True)
+    dev = torch.device("cuda")
+    theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    parts = torch.empty((1, 8), dtype=torch.float64, device=dev)
+    info = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    var = torch.empty(model.N, dtype=torch.float64, device=dev)
+
+    def step():
+        ws.fobj(theta, out=(f, parts, info))
+        ws.selinv(out=var)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region; the FP64 MFMA GEMM kernel's launches are bracketed by
+    # HIP events on the stream they run on
+    gemm_cats = ("panel_trsm", "panel_syrk", "trtri", "trsm", "update",
+                 "selinv")
+    ws.profile_begin(gemm_cats, max_launches=40000 * max(1, args.steps),
+                     by_kernel=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ws.profile_end()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = args.steps / (t1 - t0)
+
+    # f_obj alone (no selected inversion), and the BTA Cholesky of Q_c
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        ws.fobj(theta, out=(f, parts, info))
+    e1.record()
+    torch.cuda.synchronize()
+    fobj_ms = e0.elapsed_time(e1) / 3
+    fac_ms = []
+    for _ in range(3):
+        ws.assemble(theta, D.DL_QC)
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        ld, inf = ws.factor(D.DL_QC)
+        a1.record()
+        torch.cuda.synchronize()
+        fac_ms.append(a0.elapsed_time(a1))
+    fac_ms = sorted(fac_ms)[1]
+    F = fac_flops(wl.nt, wl.b, wl.a)
+    ws.fobj(theta, out=(f, parts, info))
+    torch.cuda.synchronize()
+    pr = parts.cpu().numpy()[0]
+
+    golden_path = os.path.join(ROOT, "tests", "golden", "c1_golden.json")
+    err = None
+    if os.path.exists(golden_path):
+        g = json.load(open(golden_path))
+        err = {"logdet_p": abs(pr[1] - g["logdet_p"]) / abs(g["logdet_p"]),
+               "logdet_c": abs(pr[2] - g["logdet_c"]) / abs(g["logdet_c"]),
+               "f_abs": abs(pr[0] - g["f"])}
+
+    gk = prof.get("k_gemm_tasks", {"ms": 0.0, "launches": 0, "flops": 0.0})
+    achieved = gk["flops"] / (gk["ms"] * 1e-3) / 1e12 if gk["ms"] else 0.0
+    roofline = {
+        "kernel": "k_gemm_tasks (FP64 MFMA 16x16x4 tile GEMM)",
+        "bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+        "traffic": None,
+        "launches": gk["launches"],
+        "avg_launch_us": 1000.0 * gk["ms"] / max(1, gk["launches"]),
+        "alg_flops_per_launch": gk["flops"] / max(1, gk["launches"]),
+    }
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "ns": wl.ns, "nt": wl.nt,
+                   "nb": wl.a, "m": wl.m, "b": wl.b, "N": wl.N,
+                   "step": "fobj_eval + bta_selinv (all marginal variances)"},
+        "fobj_only_evals_per_s": 1000.0 / fobj_ms,
+        "bta_cholesky_tflops": F / (fac_ms * 1e-3) / 1e12,
+        "bta_cholesky_ms": fac_ms,
+        "logdet_rel_err_vs_fp64_oracle": err,
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    del ws
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,17 @@ enum {
   DL_CAT_OTHER = 9,
   DL_NCAT = 10
 };
+/* With DL_PROFILE_BY_KERNEL or-ed into category_mask, launches of the
+ * selected categories are aggregated by kernel instead (index = one of the
+ * DL_KERNEL_* values below) -- the grouping a kernel-level profiler uses. */
+enum {
+  DL_PROFILE_BY_KERNEL = 1 << 16,
+  DL_KERNEL_GEMM = 0,        /* the FP64 MFMA tile GEMM                  */
+  DL_KERNEL_POTRF_TILE = 1,  /* 64x64 Cholesky + inverse                 */
+  DL_KERNEL_GEMV = 2,        /* solve matrix-vector products             */
+  DL_KERNEL_ASSEMBLE = 3,    /* assembly                                 */
+  DL_KERNEL_OTHER = 4
+};
 dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
                               int32_t max_launches);
 dl_status dl_ws_profile_end(dl_ws* ws, double* ms_by_cat,

@@ -136,8 +136,13 @@ static void collect_nodes(int lo, int hi, int depth,
   collect_nodes(mid, hi, depth + 1, lv);
 }
 
+// `breal`: unpadded size for the algorithmic operation count (0: the
+// inverse is not part of the algorithm being counted).
 static void add_trtri(PlanBuilder& pb, double* A, int64_t ld, int n,
-                      const double* Gd, double* temp) {
+                      const double* Gd, double* temp, int breal = 0) {
+  auto ext = [&](int lo, int hi) {
+    return (double)std::max(0, std::min(hi * 64, breal) - lo * 64);
+  };
   const int nbk = n / 64;
   Op cp;
   cp.kind = OP_COPY_TILES;
@@ -146,10 +151,12 @@ static void add_trtri(PlanBuilder& pb, double* A, int64_t ld, int n,
   cp.n = nbk;
   cp.cat = DL_CAT_TRTRI;
   pb.push(cp);
+  // (the 64x64 diagonal inverses come from the tile factorisation)
   std::vector<std::vector<int>> lv;
   collect_nodes(0, nbk, 0, lv);
   for (int d = (int)lv.size() - 1; d >= 0; --d) {
     std::vector<GemmTask> tT, tG;
+    double fT = 0.0, fG = 0.0;
     for (size_t q = 0; q < lv[d].size(); q += 2) {
       const int lo = lv[d][q], hi = lv[d][q + 1];
       const int mid = lo + (hi - lo) / 2;
@@ -162,9 +169,12 @@ static void add_trtri(PlanBuilder& pb, double* A, int64_t ld, int n,
                       1.0, 0.0));
       tG.push_back(mk(G22, ld, T, n, L21, ld, n2, n1, n2, F_KHI_ROW | F_BETA0,
                       -1.0, 0.0));
+      const double r1 = ext(lo, mid), r2 = ext(mid, hi);
+      fT += r2 * r1 * r1;   // full times triangular
+      fG += r1 * r2 * r2;
     }
-    pb.gemm(tT, DL_CAT_TRTRI, 0.0);
-    pb.gemm(tG, DL_CAT_TRTRI, 0.0);
+    pb.gemm(tT, DL_CAT_TRTRI, fT);
+    pb.gemm(tG, DL_CAT_TRTRI, fG);
   }
 }
 
@@ -227,14 +237,15 @@ struct dl_ws {
   std::vector<int> prof_cat;
   std::vector<double> prof_flops, prof_bytes;
   int prof_used = 0;
+  int prof_by_kernel = 0;  // aggregate by kernel kind instead of category
 };
 
-static int prof_begin(dl_ws* W, int cat, hipStream_t s) {
+static int prof_begin(dl_ws* W, int cat, hipStream_t s, int kind = DL_KERNEL_OTHER) {
   if (!W->prof_mask || !((W->prof_mask >> cat) & 1)) return -1;
   if (W->prof_used >= (int)W->prof_cat.size()) return -1;
   const int k = W->prof_used++;
   if (hipEventRecord(W->prof_ev[2 * k], s) != hipSuccess) return -1;
-  W->prof_cat[k] = cat;
+  W->prof_cat[k] = W->prof_by_kernel ? kind : cat;
   return k;
 }
 
@@ -472,7 +483,11 @@ static void build_factor_plan(dl_ws* W, int which,
     double* Dt = Q.D + (int64_t)t * bp * bp;
     add_potrf(pb, Dt, bp, bp, W->Gd[which], W->logdiag[which] + (int64_t)t * bp,
               W->info2 + which, (int64_t)t * m.b, m.b);
-    add_trtri(pb, Dt, bp, bp, W->Gd[which], W->ttemp[which]);
+    // L_tt^{-1} is algorithmic work of the selected inversion (Q_c with
+    // selected inversion enabled); otherwise it only serves the
+    // inverse-based triangular solves and is not counted.
+    add_trtri(pb, Dt, bp, bp, W->Gd[which], W->ttemp[which],
+              (which == 1 && W->sel) ? m.b : 0);
     const bool last = (t + 1 == m.nt);
     const int rows_lo = last ? bp : 0;
     const int M = (last ? 0 : bp) + apr;
@@ -656,7 +671,11 @@ static hipError_t run_plan(dl_ws* W, const Plan& P, hipStream_t s) {
   const ModelDev& m = W->m;
   for (const Op& op : P.ops) {
     hipError_t e = hipSuccess;
-    const int pk = prof_begin(W, op.cat, s);
+    int kind = DL_KERNEL_OTHER;
+    if (op.kind == OP_GEMM) kind = DL_KERNEL_GEMM;
+    else if (op.kind == OP_POTRF_TILE) kind = DL_KERNEL_POTRF_TILE;
+    else if (op.kind == OP_GEMV_N || op.kind == OP_GEMV_T) kind = DL_KERNEL_GEMV;
+    const int pk = prof_begin(W, op.cat, s, kind);
     switch (op.kind) {
       case OP_GEMM:
         e = launch_gemm_tasks(W->tasks_dev + op.task_off, op.ntask, op.ntiles, s);
@@ -765,8 +784,10 @@ static void prof_free(dl_ws* W) {
 
 extern "C" dl_status dl_ws_profile_begin(dl_ws* W, int32_t mask,
                                          int32_t max_launches) {
-  if (!W || max_launches <= 0 || mask == 0) return DL_EINVAL;
+  if (!W || max_launches <= 0 || (mask & 0xffff) == 0) return DL_EINVAL;
   prof_free(W);
+  W->prof_by_kernel = (mask & DL_PROFILE_BY_KERNEL) ? 1 : 0;
+  mask &= 0xffff;
   W->prof_ev.resize(2 * (size_t)max_launches);
   for (auto& e : W->prof_ev)
     if (hipEventCreate(&e) != hipSuccess) {
@@ -832,7 +853,7 @@ extern "C" dl_status bta_assemble(dl_ws* W, const double* theta_dev,
   if (!W || !theta_dev || which < DL_QP || which > DL_BOTH) return DL_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   DL_HIP_CHECK(launch_theta_coeffs(W->m, theta_dev, W->coef, s));
-  const int pk = prof_begin(W, DL_CAT_ASSEMBLE, s);
+  const int pk = prof_begin(W, DL_CAT_ASSEMBLE, s, DL_KERNEL_ASSEMBLE);
   DL_HIP_CHECK(launch_assemble(W->m, W->coef, assemble_out(W, which), s));
   {
     // dense workspace written (unpadded): diagonal and sub-diagonal blocks,

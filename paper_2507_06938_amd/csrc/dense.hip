@@ -9,64 +9,97 @@ constexpr int NB = 64;
 constexpr int SLD = NB + 1;  // padded LDS stride
 }
 
-// One workgroup factors one 64x64 SPD tile (right-looking, column by
-// column, in LDS), then forms L^{-1} by forward elimination on the identity.
-__global__ __launch_bounds__(256) void k_potrf_tile(PotrfTileArgs a) {
-  __shared__ double S[NB * SLD];   // S[r*SLD + c]
-  __shared__ double G[NB * SLD];
-  __shared__ int bad;
-  const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    S[r * SLD + c] = a.A[(int64_t)r + (int64_t)c * a.lda];
-    G[r * SLD + c] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
 
-  for (int k = 0; k < NB; ++k) {
-    const double dkk = S[k * SLD + k];
-    const bool ok = dkk > 0.0;  // false for NaN too
-    const double d = ok ? sqrt(dkk) : __builtin_nan("");
-    if (t > k && t < NB) S[t * SLD + k] = S[t * SLD + k] / d;
-    __syncthreads();
-    if (t == 0) {
-      S[k * SLD + k] = d;
-      if (a.logdiag) a.logdiag[k] = log(d);
-      if (!ok && bad == 0) {
-        bad = 1;
-        if (a.info)
-          atomicCAS((unsigned long long*)a.info, 0ull,
-                    (unsigned long long)(a.row0 + k + 1));
+// One workgroup of 4 waves factors one 64x64 SPD tile.  Lane i of wave w
+// keeps row i, columns 16w..16w+15, in registers.  At column k the wave that
+// owns it reads the pivot from lane k, scales its column and publishes it to
+// LDS; after one barrier every wave applies the rank-1 update to its own
+// columns (the FP64 work of a step is spread over the 4 SIMDs).  L^{-1} is
+// formed the same way with lane c owning column c of the inverse.  The 16
+// steps of one owner wave are unrolled (register indices stay static); the
+// loop over the 4 owners is not, which keeps the code within the
+// instruction cache.
+constexpr int CW = 16;  // columns per wave
+
+__global__ __launch_bounds__(256) void k_potrf_tile(PotrfTileArgs a) {
+  __shared__ double Lc[NB][SLD];   // Lc[k][i] = L(i, k)
+  __shared__ double Gk[NB][SLD];   // Gk[k][c] = L^{-1}(k, c)
+  __shared__ int sbad;
+  const int i = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) sbad = NB;
+  double r[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q)
+    r[q] = a.A[(int64_t)i + (int64_t)(CW * w + q) * a.lda];
+#pragma unroll 1
+  for (int kb = 0; kb < NB / CW; ++kb) {
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int k = kb * CW + q;
+      if (w == kb) {
+        const double dkk = readlane_f64(r[q], k);
+        const bool ok = dkk > 0.0;  // false for NaN too
+        if (!ok && i == 0) atomicMin(&sbad, k);
+        const double d = ok ? sqrt(dkk) : __builtin_nan("");
+        const double lik = (i > k) ? r[q] / d : (i == k ? d : 0.0);
+        r[q] = lik;
+        Lc[k][i] = lik;
+      }
+      __syncthreads();
+      if (w > kb) {
+        const double lik = Lc[k][i];
+#pragma unroll
+        for (int qq = 0; qq < CW; ++qq) r[qq] -= lik * Lc[k][CW * w + qq];
+      } else if (w == kb) {
+        const double lik = r[q];
+#pragma unroll
+        for (int qq = q + 1; qq < CW; ++qq) r[qq] -= lik * Lc[k][CW * w + qq];
       }
     }
-    const int w = NB - 1 - k;  // trailing order
-    for (int idx = t; idx < w * w; idx += 256) {
-      const int i = k + 1 + idx / w;
-      const int j = k + 1 + idx % w;
-      if (j <= i) S[i * SLD + j] -= S[i * SLD + k] * S[j * SLD + k];
-    }
-    __syncthreads();
   }
-
-  // L G = I by elimination: scale row k, eliminate it from rows below.
-  for (int k = 0; k < NB; ++k) {
-    const double lkk = S[k * SLD + k];
-    if (t <= k) G[k * SLD + t] = G[k * SLD + t] / lkk;
-    __syncthreads();
-    const int rows = NB - 1 - k, cols = k + 1;
-    for (int idx = t; idx < rows * cols; idx += 256) {
-      const int i = k + 1 + idx / cols;
-      const int j = idx % cols;
-      G[i * SLD + j] -= S[i * SLD + k] * G[k * SLD + j];
+#pragma unroll
+  for (int q = 0; q < CW; ++q)
+    a.A[(int64_t)i + (int64_t)(CW * w + q) * a.lda] = r[q];
+  if (w == 0 && a.logdiag) a.logdiag[i] = log(Lc[i][i]);
+  if (threadIdx.x == 0 && sbad < NB && a.info)
+    atomicCAS((unsigned long long*)a.info, 0ull,
+              (unsigned long long)(a.row0 + sbad + 1));
+  if (!a.Ginv) return;
+  const int c = i;
+  double g[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) g[q] = (CW * w + q == c) ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int kb = 0; kb < NB / CW; ++kb) {
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int k = kb * CW + q;
+      if (w == kb) {
+        g[q] = g[q] / Lc[k][k];
+        Gk[k][c] = g[q];
+      }
+      __syncthreads();
+      if (w > kb) {
+        const double gk = Gk[k][c];
+#pragma unroll
+        for (int qq = 0; qq < CW; ++qq) g[qq] -= Lc[k][CW * w + qq] * gk;
+      } else if (w == kb) {
+        const double gk = g[q];
+#pragma unroll
+        for (int qq = q + 1; qq < CW; ++qq) g[qq] -= Lc[k][CW * w + qq] * gk;
+      }
     }
-    __syncthreads();
   }
-
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    a.A[(int64_t)r + (int64_t)c * a.lda] = (r >= c) ? S[r * SLD + c] : 0.0;
-    if (a.Ginv) a.Ginv[r + c * NB] = (r >= c) ? G[r * SLD + c] : 0.0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
+    const int rr = idx & 63, cc = idx >> 6;
+    a.Ginv[rr + cc * NB] = (rr >= cc) ? Gk[rr][cc] : 0.0;
   }
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
 DL_QP, DL_QC, DL_BOTH = 0, 1, 2
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
+KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other")
 STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
           3: "not positive definite", 4: "HIP runtime error",
           5: "call order violated", 6: "refinement did not converge"}
@@ -225,10 +226,16 @@ class Workspace:
                                             _ptr(parts), _ptr(info), _stream()))
         return f, parts, info
 
-    def profile_begin(self, categories=CATEGORIES, max_launches=200000):
+    def profile_begin(self, categories=CATEGORIES, max_launches=200000,
+                      by_kernel=False):
+        """Bracket launches of `categories` with HIP events (aggregated by
+        category, or by kernel when by_kernel)."""
         mask = 0
         for c in categories:
             mask |= 1 << CATEGORIES.index(c)
+        self._prof_by_kernel = by_kernel
+        if by_kernel:
+            mask |= 1 << 16
         _check("dl_ws_profile_begin",
                lib().dl_ws_profile_begin(self.h, mask, int(max_launches)))
 
@@ -239,8 +246,9 @@ class Workspace:
         fl = (C.c_double * n)()
         by = (C.c_double * n)()
         _check("dl_ws_profile_end", lib().dl_ws_profile_end(self.h, ms, cnt, fl, by))
+        names = KERNELS if getattr(self, "_prof_by_kernel", False) else CATEGORIES
         return {c: dict(ms=ms[i], launches=cnt[i], flops=fl[i], bytes=by[i])
-                for i, c in enumerate(CATEGORIES) if cnt[i]}
+                for i, c in enumerate(names) if cnt[i]}
 
     def get_block(self, which: int, kind: int, t: int = 0) -> torch.Tensor:
         m = self.model
