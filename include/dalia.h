@@ -105,10 +105,30 @@ void dl_model_destroy(dl_model* model);
 dl_status dl_model_dims(const dl_model* model, int64_t* n, int64_t* b,
                         int64_t* a, int64_t* N, int64_t* bp);
 
-/* Allocate the dense BTA workspace for Q_p and Q_c of `model` (flags: bit 0
- * = keep storage for selected inversion).  All device memory of the
- * evaluation path is allocated here. */
+/* Workspace flags. */
+enum {
+  DL_WS_SELINV = 1,   /* keep the storage of the selected inversion        */
+  DL_WS_KEEP_QP = 2,  /* store Q_p in full (inspection); by default Q_p is
+                         assembled just in time into a ring of blocks, as
+                         only its log-determinant is needed                */
+  DL_WS_GRAPH = 4     /* fobj_eval replays one captured HIP graph          */
+};
+
+/* Allocate the dense BTA workspace for Q_p and Q_c of `model`.  All device
+ * memory of the evaluation path is allocated here. */
 dl_status dl_ws_create(const dl_model* model, int32_t flags, dl_ws** out);
+
+/* A workspace of nmodels instances evaluated together: every launch of an
+ * evaluation serves the same step of all instances (and of both Q_p and
+ * Q_c).  The same model may be passed several times (e.g. the 2*dim+1
+ * points of a central-difference gradient, Eq. 10, the paper's first
+ * parallel layer); models may also differ in size.  Per-instance inputs and
+ * outputs are packed in instance order: theta of instance k at offset
+ * sum_{k'<k} dim_theta(k'), N-vectors at sum_{k'<k} N(k'), logdet/info of
+ * bta_factor at cnt*k (cnt = 2 for DL_BOTH, else 1). */
+dl_status dl_ws_create_batch(const dl_model* const* models, int32_t nmodels,
+                             int32_t flags, dl_ws** out);
+int32_t dl_ws_batch(const dl_ws* ws);
 void dl_ws_destroy(dl_ws* ws);
 /* Device bytes held by the workspace. */
 size_t dl_ws_bytes(const dl_ws* ws);
@@ -145,7 +165,10 @@ dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
 /* fobj_eval -- steps a1..a8: f_obj (Eq. 8) for ntheta hyperparameter vectors
  * (theta_dev: ntheta x dim_theta, row-major).  fobj_dev[k], parts_dev[k]
  * (may be NULL) and info_dev[2k..2k+1] (Q_p, Q_c pivots; may be NULL)
- * receive the results.  mu of the last theta stays in the workspace. */
+ * receive the results.  A batch workspace of B instances evaluates B thetas
+ * per pass (ntheta may be any count when all instances share one model;
+ * otherwise ntheta must equal B).  mu of the last pass stays in the
+ * workspace. */
 dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                     double* fobj_dev, dl_fobj_parts* parts_dev,
                     int64_t* info_dev, void* stream);

@@ -14,9 +14,12 @@ namespace dl {
 // Eq. 5; the joint precision has blocks (k, j) = sum_i (Lambda^-1)_{ik}
 // (Lambda^-1)_{ij} Q^i (Eq. 11).  Q^i = T^i (x) Q_s^i, Q_s = kappa^4 C +
 // 2 kappa^2 G + G C^-1 G, T the unit-variance AR1 precision.
-__global__ void k_theta_coeffs(ModelDev m, const double* __restrict__ theta,
-                               double* __restrict__ coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
+  if (threadIdx.x != 0) return;
+  const ThetaJob J = jobs[blockIdx.x];
+  const ModelDev& m = *J.m;
+  const double* __restrict__ theta = J.theta;
+  double* __restrict__ coef = J.coef;
   const int nv = m.nv;
   double kap[3], rho[3], tau[3], Li[3][3];
   double Mw[3][3][3];
@@ -118,9 +121,9 @@ __global__ void k_theta_coeffs(ModelDev m, const double* __restrict__ theta,
   coef[C_BAD] = bad ? 1.0 : 0.0;
 }
 
-hipError_t launch_theta_coeffs(const ModelDev& m, const double* theta,
-                               double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_theta_coeffs, dim3(1), dim3(64), 0, s, m, theta, coef);
+hipError_t launch_theta_coeffs(const ThetaJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_theta_coeffs, dim3(count), dim3(64), 0, s, jobs);
   return hipGetLastError();
 }
 
@@ -134,32 +137,38 @@ hipError_t launch_theta_coeffs(const ModelDev& m, const double* theta,
 // so the result does not depend on scheduling.  Padding columns c >= b
 // (up to the padded block size bp) carry a unit diagonal, which leaves the
 // log-determinant unchanged.
-__global__ __launch_bounds__(256) void k_assemble_cols(
-    ModelDev m, const double* __restrict__ coef, AssembleOut o) {
+__global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict__ jobs) {
   extern __shared__ double lds[];
+  const AsmJob J = jobs[blockIdx.z];
+  const ModelDev& m = *J.m;
+  const AssembleOut& o = J.o;
   const int c = blockIdx.x;
-  const int t = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tl = blockIdx.y;
   const int bp = m.bp, ap = m.ap, ns = m.ns, nv = m.nv;
+  if (c >= bp || tl >= J.nt) return;
+  const int t = J.t0 + tl;
+  const int tid = threadIdx.x;
   const int64_t ldbr = bp + ap;
   double* colD = lds;            // bp
   double* colB = lds + bp;       // bp
   double* colR = lds + 2 * bp;   // ap (<= 64)
   __shared__ double rhs_s;
   const bool hasB = t + 1 < m.nt;
-  const int64_t dofs = (int64_t)t * bp * bp + (int64_t)c * bp;
-  const int64_t bofs = (int64_t)t * bp * bp + (int64_t)c * bp;
-  const int64_t brofs = (int64_t)t * ldbr * bp + (int64_t)c * ldbr;
+  double* Dp = o.Dp ? o.Dp + tl * o.dp_stride + (int64_t)c * bp : nullptr;
+  double* Bp = o.Bp ? o.Bp + tl * o.bp_stride + (int64_t)c * bp : nullptr;
+  double* Dc = o.Dc ? o.Dc + tl * o.dc_stride + (int64_t)c * bp : nullptr;
+  double* BRc = o.BRc ? o.BRc + tl * o.brc_stride + (int64_t)c * ldbr : nullptr;
 
   if (c >= m.b) {
     for (int r = tid; r < bp; r += 256) {
       const double v = (r == c) ? 1.0 : 0.0;
-      if (o.Dp) { o.Dp[dofs + r] = v; o.Bp[bofs + r] = 0.0; }
-      if (o.Dc) o.Dc[dofs + r] = v;
+      if (Dp) Dp[r] = v;
+      if (Bp) Bp[r] = 0.0;
+      if (Dc) Dc[r] = v;
     }
-    if (o.Dc)
-      for (int r = tid; r < bp + ap; r += 256) o.BRc[brofs + r] = 0.0;
-    if (tid == 0) o.rhs[(int64_t)t * bp + c] = 0.0;
+    if (BRc)
+      for (int r = tid; r < bp + ap; r += 256) BRc[r] = 0.0;
+    if (Dc && tid == 0) o.rhs[(int64_t)t * bp + c] = 0.0;
     return;
   }
   const int j = c / ns;
@@ -174,24 +183,22 @@ __global__ __launch_bounds__(256) void k_assemble_cols(
     const int k = idx % nv;
     const int r = k * ns + m.sp_col[e];
     const double pc = m.sp_C[e], pg = m.sp_G[e], pg2 = m.sp_G2[e];
-    const double* cd = coef + C_D + ((tt * 3 + k) * 3 + j) * 3;
+    const double* cd = J.coef + C_D + ((tt * 3 + k) * 3 + j) * 3;
     colD[r] = cd[0] * pc + cd[1] * pg + cd[2] * pg2;
     if (hasB) {
-      const double* cb = coef + C_B + (k * 3 + j) * 3;
+      const double* cb = J.coef + C_B + (k * 3 + j) * 3;
       colB[r] = cb[0] * pc + cb[1] * pg + cb[2] * pg2;
     }
   }
   __syncthreads();
-  if (o.Dp) {
-    for (int r = tid; r < bp; r += 256) {
-      o.Dp[dofs + r] = (r >= c) ? colD[r] : 0.0;
-      o.Bp[bofs + r] = colB[r];
-    }
-  }
-  if (!o.Dc) return;
+  if (Dp)
+    for (int r = tid; r < bp; r += 256) Dp[r] = (r >= c) ? colD[r] : 0.0;
+  if (Bp)
+    for (int r = tid; r < bp; r += 256) Bp[r] = colB[r];
+  if (!Dc) return;
   __syncthreads();
   if (tid == 0) {
-    const double tau = coef[C_TAU + j];
+    const double tau = J.coef[C_TAU + j];
     const int64_t key = ((int64_t)j * m.nt + t) * ns + s;
     double racc = 0.0;
     const int nr = m.nr;
@@ -211,10 +218,10 @@ __global__ __launch_bounds__(256) void k_assemble_cols(
   }
   __syncthreads();
   for (int r = tid; r < bp; r += 256) {
-    o.Dc[dofs + r] = (r >= c) ? colD[r] : 0.0;
-    o.BRc[brofs + r] = colB[r];
+    Dc[r] = (r >= c) ? colD[r] : 0.0;
+    BRc[r] = colB[r];
   }
-  for (int r = tid; r < ap; r += 256) o.BRc[brofs + bp + r] = colR[r];
+  for (int r = tid; r < ap; r += 256) BRc[bp + r] = colR[r];
   if (tid == 0) o.rhs[(int64_t)t * bp + c] = rhs_s;
 }
 
@@ -223,10 +230,14 @@ __global__ __launch_bounds__(256) void k_assemble_cols(
 // per-response covariate blocks; workgroup 1 + e computes one covariate
 // Gram entry (response j, r >= r2) or one right-hand-side entry, summing
 // the response's rows with a fixed reduction tree.
-__global__ __launch_bounds__(256) void k_assemble_tip(
-    ModelDev m, const double* __restrict__ coef, AssembleOut o) {
+__global__ __launch_bounds__(256) void k_assemble_tip(const AsmJob* __restrict__ jobs) {
   __shared__ double sh[256];
+  const AsmJob J = jobs[blockIdx.y];
+  const ModelDev& m = *J.m;
+  const AssembleOut& o = J.o;
+  const double* __restrict__ coef = J.coef;
   const int tid = threadIdx.x;
+  if (m.ap == 0) return;
   const int nr = m.nr, nv = m.nv, ap = m.ap, a = m.a;
   const int ngram = nv * nr * nr;
   if (blockIdx.x == 0) {
@@ -245,6 +256,7 @@ __global__ __launch_bounds__(256) void k_assemble_tip(
   }
   if (!o.Pc) return;
   int e = blockIdx.x - 1;
+  if (e >= ngram + nv * nr) return;
   int j, r, r2;
   bool gram = e < ngram;
   if (gram) {
@@ -282,25 +294,31 @@ __global__ __launch_bounds__(256) void k_assemble_tip(
   }
 }
 
-hipError_t launch_assemble(const ModelDev& m, const double* coef,
-                           const AssembleOut& o, hipStream_t s) {
-  const size_t shmem = (size_t)(2 * m.bp + m.ap) * sizeof(double);
-  if (shmem > 65536) {
-    hipError_t a = hipFuncSetAttribute(
-        (const void*)k_assemble_cols,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (a != hipSuccess) return a;
-  }
-  hipLaunchKernelGGL(k_assemble_cols, dim3(m.bp, m.nt), dim3(256), shmem, s, m,
-                     coef, o);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (m.ap > 0) {
-    const int nblk = 1 + m.nv * m.nr * m.nr + m.nv * m.nr;
-    hipLaunchKernelGGL(k_assemble_tip, dim3(nblk), dim3(256), 0, s, m, coef, o);
-    e = hipGetLastError();
-  }
-  return e;
+hipError_t launch_assemble_cols(const AsmJob* jobs, int count, int max_bp,
+                                int max_nt, int max_shmem_doubles, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t shmem = (size_t)max_shmem_doubles * sizeof(double);
+  hipLaunchKernelGGL(k_assemble_cols, dim3(max_bp, max_nt, count), dim3(256),
+                     shmem, s, jobs);
+  return hipGetLastError();
+}
+
+// Allow the column kernel its dynamic LDS (2*bp + ap doubles) beyond the
+// default 64 KiB; called once per workspace, outside any graph capture.
+hipError_t prepare_assemble(int max_shmem_doubles) {
+  const size_t shmem = (size_t)max_shmem_doubles * sizeof(double);
+  if (shmem <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_assemble_cols,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+}
+
+// max_blocks = 1 + max over jobs of nv*nr*nr + nv*nr
+hipError_t launch_assemble_tips(const AsmJob* jobs, int count, int max_blocks,
+                                hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble_tip, dim3(max_blocks, count), dim3(256), 0, s,
+                     jobs);
+  return hipGetLastError();
 }
 
 // ---- a8: quadratic forms --------------------------------------------------------
@@ -324,12 +342,13 @@ __device__ __forceinline__ double blk_sum(double v, double* sh) {
   return r;
 }
 
-constexpr int QF_BLOCKS = 512;
-
-__global__ __launch_bounds__(256) void k_quad_prior(
-    ModelDev m, const double* __restrict__ coef, const double* __restrict__ mu,
-    double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_quad_prior(const QuadJob* __restrict__ jobs) {
   __shared__ double sh[256];
+  const QuadJob Q = jobs[blockIdx.y];
+  const ModelDev& m = *Q.m;
+  const double* __restrict__ coef = Q.coef;
+  const double* __restrict__ mu = Q.mu;
+  double* __restrict__ partial = Q.partial;
   const int64_t nrows = (int64_t)m.nt * m.b;
   const int ns = m.ns, nv = m.nv, bp = m.bp;
   double acc = 0.0;
@@ -364,10 +383,13 @@ __global__ __launch_bounds__(256) void k_quad_prior(
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_quad_obs(
-    ModelDev m, const double* __restrict__ coef, const double* __restrict__ mu,
-    double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_quad_obs(const QuadJob* __restrict__ jobs) {
   __shared__ double sh[256];
+  const QuadJob Q = jobs[blockIdx.y];
+  const ModelDev& m = *Q.m;
+  const double* __restrict__ coef = Q.coef;
+  const double* __restrict__ mu = Q.mu;
+  double* __restrict__ partial = Q.partial + QF_BLOCKS;
   const int ns = m.ns, nr = m.nr, bp = m.bp;
   double acc = 0.0;
   for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < m.m_total;
@@ -387,9 +409,11 @@ __global__ __launch_bounds__(256) void k_quad_obs(
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_quad_final(const double* partial,
-                                                    double* out2) {
+__global__ __launch_bounds__(256) void k_quad_final(const QuadJob* __restrict__ jobs) {
   __shared__ double sh[256];
+  const QuadJob Q = jobs[blockIdx.x];
+  const double* partial = Q.partial;
+  double* out2 = Q.out2;
   for (int w = 0; w < 2; ++w) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < QF_BLOCKS; i += 256) acc += partial[w * QF_BLOCKS + i];
@@ -398,16 +422,11 @@ __global__ __launch_bounds__(256) void k_quad_final(const double* partial,
   }
 }
 
-// out2[0] = mu^T Q_p mu, out2[1] = (y - A mu)^T D (y - A mu);
-// partial needs 2 * QF_BLOCKS doubles.
-hipError_t launch_quadforms(const ModelDev& m, const double* coef,
-                            const double* mu, double* partial, double* out2,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_quad_prior, dim3(QF_BLOCKS), dim3(256), 0, s, m, coef, mu,
-                     partial);
-  hipLaunchKernelGGL(k_quad_obs, dim3(QF_BLOCKS), dim3(256), 0, s, m, coef, mu,
-                     partial + QF_BLOCKS);
-  hipLaunchKernelGGL(k_quad_final, dim3(1), dim3(256), 0, s, partial, out2);
+hipError_t launch_quadforms(const QuadJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quad_prior, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_quad_obs, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_quad_final, dim3(count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 
@@ -415,12 +434,16 @@ hipError_t launch_quadforms(const ModelDev& m, const double* coef,
 // part and the (2 pi)^{-N/2} factors of Eq. 1 and Eq. 3 cancel:
 // f = log p(theta) + [sum_j m_j/2 log tau_j - m/2 log 2pi - 1/2 quad_obs]
 //     + 1/2 log|Q_p| - 1/2 mu^T Q_p mu - 1/2 log|Q_c|.
-__global__ void k_combine(const double* __restrict__ coef,
-                          const double* __restrict__ logdet2,
-                          const int64_t* __restrict__ info2,
-                          const double* __restrict__ quad2, double* f,
-                          dl_fobj_parts* parts, int64_t* info_out) {
+__global__ void k_combine(const CombineJob* __restrict__ jobs) {
   if (threadIdx.x != 0) return;
+  const CombineJob C = jobs[blockIdx.x];
+  const double* coef = C.coef;
+  const double* logdet2 = C.logdet2;
+  const int64_t* info2 = C.info2;
+  const double* quad2 = C.quad2;
+  double* f = C.f;
+  dl_fobj_parts* parts = C.parts;
+  int64_t* info_out = C.info_out;
   const double lp = coef[C_LOGPRIOR];
   const double llc = coef[C_LLCONST];
   double v = lp + llc - 0.5 * quad2[1] + 0.5 * logdet2[0] - 0.5 * quad2[0] -
@@ -445,13 +468,9 @@ __global__ void k_combine(const double* __restrict__ coef,
   }
 }
 
-hipError_t launch_combine(const ModelDev& m, const double* coef,
-                          const double* logdet2, const int64_t* info2,
-                          const double* quad2, double* f, dl_fobj_parts* parts,
-                          int64_t* info_out, hipStream_t s) {
-  (void)m;
-  hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, s, coef, logdet2, info2,
-                     quad2, f, parts, info_out);
+hipError_t launch_combine(const CombineJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3(count), dim3(64), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -71,29 +71,46 @@ struct DeviceTasks {
 };
 
 // ---- 64x64 diagonal-tile Cholesky ------------------------------------------
-// Factor the nb x nb (nb = 64) SPD tile at A (lda) in place: lower = L, upper
-// zeroed; write L^{-1} to Ginv (64 x 64, ld 64) when Ginv != nullptr;
-// logdiag[i] = log L_ii; on a non-positive pivot set *info = row0 + i + 1
-// (first failure only).  `ntiles` tiles are processed, tile k at
-// A + k*(tile_stride) etc.  The tile has only `valid` leading rows that are
-// real; the rest must be identity-padded by the caller.
+// Factor the 64 x 64 SPD tile at A (lda) in place.  mode 0: lower triangle
+// of A <- L (upper zeroed), Ginv (64 x 64, ld 64, may be null) <- L^{-1};
+// mode 1: lower triangle of A <- L^{-1} (the factor itself is not kept).
+// logdiag[i] = log L_ii; on a non-positive pivot *info = row0 + i + 1 (first
+// failure only).  A batch of tiles is one launch, one workgroup per tile.
 struct PotrfTileArgs {
   double* A;
   int64_t lda;
   double* Ginv;
   double* logdiag;
   int64_t* info;
-  int64_t row0;  // global row of the tile's first row (for info)
+  int64_t row0;
+  int32_t mode;
+  int32_t pad_;
 };
-hipError_t launch_potrf_tile(const PotrfTileArgs& a, hipStream_t s);
+hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
+                              hipStream_t s);
 
-hipError_t launch_copy_tile64(const double* src, int64_t lds, double* dst,
-                              int64_t ldd, int ntiles, int64_t src_tile_stride,
-                              int64_t dst_tile_stride, hipStream_t s);
+// ---- small batched element-wise jobs ------------------------------------------
+enum : int { MJ_FILL = 0, MJ_COPY = 1, MJ_ZERO_I64 = 2, MJ_DIAG = 3,
+             MJ_COPY2D = 4, MJ_ZERO_UPPER_TILES = 5 };
+struct MiscJob {
+  int32_t kind, rows, cols, pad_;
+  double* dst;
+  const double* src;
+  int64_t n, lds, ldd;
+  double v;
+};
+hipError_t launch_misc(const MiscJob* jobs_dev, int count, hipStream_t s);
 
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
-hipError_t launch_zero_upper_tiles(double* A, int64_t ld, int n, hipStream_t s);
-hipError_t launch_sum_log(const double* logdiag, int64_t n, double scale,
-                          double* out, double* partial, hipStream_t s);
+// out[0] = scale * sum(src[0..n)) with a fixed reduction order; partial
+// holds SUM_BLOCKS doubles per job.
+constexpr int SUM_BLOCKS = 128;
+struct SumJob {
+  const double* src;
+  int64_t n;
+  double scale;
+  double* dst;
+  double* partial;
+};
+hipError_t launch_sums(const SumJob* jobs_dev, int count, hipStream_t s);
 
 }  // namespace dl

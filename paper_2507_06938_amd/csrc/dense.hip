@@ -26,7 +26,8 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
 // instruction cache.
 constexpr int CW = 16;  // columns per wave
 
-__global__ __launch_bounds__(256) void k_potrf_tile(PotrfTileArgs a) {
+__global__ __launch_bounds__(256) void k_potrf_tile(const PotrfTileArgs* __restrict__ args) {
+  const PotrfTileArgs a = args[blockIdx.x];
   __shared__ double Lc[NB][SLD];   // Lc[k][i] = L(i, k)
   __shared__ double Gk[NB][SLD];   // Gk[k][c] = L^{-1}(k, c)
   __shared__ int sbad;
@@ -63,14 +64,16 @@ __global__ __launch_bounds__(256) void k_potrf_tile(PotrfTileArgs a) {
       }
     }
   }
+  if (a.mode == 0) {
 #pragma unroll
-  for (int q = 0; q < CW; ++q)
-    a.A[(int64_t)i + (int64_t)(CW * w + q) * a.lda] = r[q];
+    for (int q = 0; q < CW; ++q)
+      a.A[(int64_t)i + (int64_t)(CW * w + q) * a.lda] = r[q];
+  }
   if (w == 0 && a.logdiag) a.logdiag[i] = log(Lc[i][i]);
   if (threadIdx.x == 0 && sbad < NB && a.info)
     atomicCAS((unsigned long long*)a.info, 0ull,
               (unsigned long long)(a.row0 + sbad + 1));
-  if (!a.Ginv) return;
+  if (a.mode == 0 && !a.Ginv) return;
   const int c = i;
   double g[CW];
 #pragma unroll
@@ -97,69 +100,66 @@ __global__ __launch_bounds__(256) void k_potrf_tile(PotrfTileArgs a) {
     }
   }
   __syncthreads();
+  double* dst = a.mode == 0 ? a.Ginv : a.A;
+  const int64_t ldd = a.mode == 0 ? NB : a.lda;
   for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
     const int rr = idx & 63, cc = idx >> 6;
-    a.Ginv[rr + cc * NB] = (rr >= cc) ? Gk[rr][cc] : 0.0;
+    dst[rr + cc * ldd] = (rr >= cc) ? Gk[rr][cc] : 0.0;
   }
 }
 
-hipError_t launch_potrf_tile(const PotrfTileArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, a);
+hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
+                              hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_potrf_tile, dim3(count), dim3(256), 0, s, args);
   return hipGetLastError();
 }
 
-__global__ void k_copy_tile64(const double* __restrict__ src, int64_t lds,
-                              double* __restrict__ dst, int64_t ldd,
-                              int64_t sstride, int64_t dstride) {
-  const double* s = src + sstride * blockIdx.x;
-  double* d = dst + dstride * blockIdx.x;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx & 63, c = idx >> 6;
-    d[(int64_t)r + (int64_t)c * ldd] = s[(int64_t)r + (int64_t)c * lds];
-  }
-}
-
-hipError_t launch_copy_tile64(const double* src, int64_t lds, double* dst,
-                              int64_t ldd, int ntiles, int64_t sstride,
-                              int64_t dstride, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_tile64, dim3(ntiles), dim3(256), 0, s, src, lds,
-                     dst, ldd, sstride, dstride);
-  return hipGetLastError();
-}
-
-// Zero the tiles strictly above the diagonal tiles of an n x n (n % 64 == 0)
-// column-major matrix.
-__global__ void k_zero_upper_tiles(double* A, int64_t ld, int n) {
-  const int64_t total = (int64_t)n * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(i % n), c = (int)(i / n);
-    if ((r >> 6) < (c >> 6)) A[r + (int64_t)c * ld] = 0.0;
-  }
-}
-
-hipError_t launch_zero_upper_tiles(double* A, int64_t ld, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_upper_tiles, dim3(1024), dim3(256), 0, s, A, ld, n);
-  return hipGetLastError();
-}
-
-__global__ void k_fill(double* p, int64_t n, double v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Batched element-wise jobs: grid (blocks, jobs).
+__global__ __launch_bounds__(256) void k_misc(const MiscJob* __restrict__ jobs) {
+  const MiscJob J = jobs[blockIdx.y];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = v;
+  int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  switch (J.kind) {
+    case MJ_FILL:
+      for (int64_t i = i0; i < J.n; i += stride) J.dst[i] = J.v;
+      break;
+    case MJ_COPY:
+      for (int64_t i = i0; i < J.n; i += stride) J.dst[i] = J.src[i];
+      break;
+    case MJ_ZERO_I64:
+      for (int64_t i = i0; i < J.n; i += stride) ((int64_t*)J.dst)[i] = 0;
+      break;
+    case MJ_DIAG:
+      for (int64_t i = i0; i < J.n; i += stride) J.dst[i] = J.src[i * (J.lds + 1)];
+      break;
+    case MJ_COPY2D: {
+      const int64_t tot = (int64_t)J.rows * J.cols;
+      for (int64_t i = i0; i < tot; i += stride) {
+        const int64_t r = i % J.rows, c = i / J.rows;
+        J.dst[r + c * J.ldd] = J.src[r + c * J.lds];
+      }
+      break;
+    }
+    case MJ_ZERO_UPPER_TILES: {
+      const int64_t tot = (int64_t)J.rows * J.rows;
+      for (int64_t i = i0; i < tot; i += stride) {
+        const int64_t r = i % J.rows, c = i / J.rows;
+        if ((r >> 6) < (c >> 6)) J.dst[r + c * J.ldd] = 0.0;
+      }
+      break;
+    }
+  }
 }
 
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+hipError_t launch_misc(const MiscJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_misc, dim3(256, count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 
-// Deterministic sum: each block reduces a fixed contiguous range with a
-// fixed tree; block partials are then reduced by one block in index order.
+// Deterministic sums: block b of job j reduces a fixed contiguous range with
+// a fixed tree; the job's block partials are then reduced in index order.
 __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -173,38 +173,31 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_sum_partial(const double* x, int64_t n,
-                                                     int64_t per_block,
-                                                     double* partial) {
+__global__ __launch_bounds__(256) void k_sum_partial(const SumJob* __restrict__ jobs) {
   __shared__ double sh[256];
-  const int64_t b0 = (int64_t)blockIdx.x * per_block;
-  const int64_t b1 = min(n, b0 + per_block);
+  const SumJob J = jobs[blockIdx.y];
+  const int64_t per = (J.n + SUM_BLOCKS - 1) / SUM_BLOCKS;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = min(J.n, b0 + per);
   double acc = 0.0;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) acc += x[i];
-  const double s = block_sum_256(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) acc += J.src[i];
+  const double v = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) J.partial[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(256) void k_sum_final(const double* partial, int np,
-                                                   double scale, double* out) {
+__global__ __launch_bounds__(256) void k_sum_final(const SumJob* __restrict__ jobs) {
   __shared__ double sh[256];
+  const SumJob J = jobs[blockIdx.x];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) acc += partial[i];
-  const double s = block_sum_256(acc, sh);
-  if (threadIdx.x == 0) out[0] = scale * s;
+  for (int i = threadIdx.x; i < SUM_BLOCKS; i += 256) acc += J.partial[i];
+  const double v = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) J.dst[0] = J.scale * v;
 }
 
-// out[0] = scale * sum(x[0..n)); `partial` needs 256 doubles.
-hipError_t launch_sum_log(const double* x, int64_t n, double scale,
-                          double* out, double* partial, hipStream_t s) {
-  int64_t per = (n + 255) / 256;
-  if (per < 1024) per = 1024;
-  int nb = (int)((n + per - 1) / per);
-  if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(256), 0, s, x, n, per,
-                     partial);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, scale,
-                     out);
+hipError_t launch_sums(const SumJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_partial, dim3(SUM_BLOCKS, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_sum_final, dim3(count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,1202 @@
+// Batched evaluation engine: workspaces of one or more instances (an
+// instance = one hyperparameter vector on one model), the launch plans of
+// assembly, BTA factorisation, solve and selected inversion, and the C-ABI
+// entry points.
+//
+// Every operation is first written as a sequence of per-matrix steps (one
+// sequence per instance and matrix: Q_p and Q_c of every instance).  Steps
+// carry a key that orders them within their sequence; steps of different
+// sequences with the same key are independent and are merged into one
+// launch.  This runs Q_p and Q_c of an evaluation concurrently (the paper's
+// second layer of parallelism, here inside each launch) and the
+// 2*dim(theta)+1 evaluations of a finite-difference gradient concurrently
+// (its first layer), while each launch still walks the time steps in order.
+// All descriptors are built once at workspace creation; running a plan only
+// launches kernels.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "engine.hpp"
+#include "selinv.hpp"
+#include "solve.hpp"
+
+namespace dl {
+
+enum OpKind : int {
+  OP_GEMM, OP_POTRF, OP_MISC, OP_GEMV_N, OP_GEMV_T, OP_SUM, OP_FINISH,
+  OP_ASM_COLS, OP_ASM_TIPS, OP_THETA, OP_QUAD, OP_COMBINE, OP_NKIND
+};
+
+// One step of one sequence (before merging).
+struct Step {
+  uint64_t key = 0;
+  OpKind kind = OP_MISC;
+  int cat = DL_CAT_OTHER;
+  double flops = 0.0, bytes = 0.0;
+  std::vector<GemmTask> gemm;
+  PotrfTileArgs potrf{};
+  MiscJob misc{};
+  GemvN gn{};
+  GemvT gt{};
+  SumJob sum{};
+  FinishJob fin{};
+  AsmJob asmj{};
+  ThetaJob th{};
+  QuadJob quad{};
+  CombineJob comb{};
+  int gx = 0, gy = 0, gz = 0;  // grid bounds contributed by this step
+};
+
+// A merged launch.
+struct Launch {
+  OpKind kind;
+  int cat;
+  double flops, bytes;
+  int off, count;     // into the per-kind descriptor array
+  int gx, gy, gz;     // grid bounds (max over merged steps)
+};
+
+struct Plan {
+  std::vector<Launch> launches;
+};
+
+// Host-side descriptor arrays (uploaded once per workspace).
+struct Descs {
+  std::vector<GemmTask> gemm;
+  std::vector<PotrfTileArgs> potrf;
+  std::vector<MiscJob> misc;
+  std::vector<GemvN> gn;
+  std::vector<GemvT> gt;
+  std::vector<SumJob> sum;
+  std::vector<FinishJob> fin;
+  std::vector<AsmJob> asmj;
+  std::vector<ThetaJob> th;
+  std::vector<QuadJob> quad;
+  std::vector<CombineJob> comb;
+};
+
+struct DevDescs {
+  GemmTask* gemm = nullptr;
+  PotrfTileArgs* potrf = nullptr;
+  MiscJob* misc = nullptr;
+  GemvN* gn = nullptr;
+  GemvT* gt = nullptr;
+  SumJob* sum = nullptr;
+  FinishJob* fin = nullptr;
+  AsmJob* asmj = nullptr;
+  ThetaJob* th = nullptr;
+  QuadJob* quad = nullptr;
+  CombineJob* comb = nullptr;
+};
+
+// key = (((major * 16 + group) * 256 + j) * 4 + sub)
+static uint64_t K(uint64_t major, uint64_t group, uint64_t j = 0, uint64_t sub = 0) {
+  return ((major * 16 + group) * 256 + j) * 4 + sub;
+}
+
+// Merge sequences: steps with equal keys and kinds form one launch; keys are
+// visited in increasing order, so each sequence keeps its own order.
+static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D, Plan& P) {
+  std::map<std::pair<uint64_t, int>, std::vector<const Step*>> groups;
+  for (const auto& sq : seqs)
+    for (const Step& st : sq) groups[{st.key, (int)st.kind}].push_back(&st);
+  for (auto& kv : groups) {
+    const std::vector<const Step*>& g = kv.second;
+    Launch L{};
+    L.kind = (OpKind)kv.first.second;
+    L.cat = g.front()->cat;
+    L.flops = L.bytes = 0.0;
+    L.gx = L.gy = L.gz = 0;
+    for (const Step* st : g) {
+      L.flops += st->flops;
+      L.bytes += st->bytes;
+      L.gx = std::max(L.gx, st->gx);
+      L.gy = std::max(L.gy, st->gy);
+      L.gz = std::max(L.gz, st->gz);
+    }
+    switch (L.kind) {
+      case OP_GEMM: {
+        L.off = (int)D.gemm.size();
+        for (const Step* st : g) D.gemm.insert(D.gemm.end(), st->gemm.begin(), st->gemm.end());
+        L.count = (int)D.gemm.size() - L.off;
+        L.gx = finalize_tasks(D.gemm.data() + L.off, L.count);
+        if (L.gx == 0) continue;
+        break;
+      }
+#define PUSH(vec, fld)                                  \
+  L.off = (int)D.vec.size();                            \
+  for (const Step* st : g) D.vec.push_back(st->fld);    \
+  L.count = (int)D.vec.size() - L.off;                  \
+  break;
+      case OP_POTRF: PUSH(potrf, potrf)
+      case OP_MISC: PUSH(misc, misc)
+      case OP_GEMV_N: PUSH(gn, gn)
+      case OP_GEMV_T: PUSH(gt, gt)
+      case OP_SUM: PUSH(sum, sum)
+      case OP_FINISH: PUSH(fin, fin)
+      case OP_ASM_COLS: PUSH(asmj, asmj)
+      case OP_ASM_TIPS: PUSH(asmj, asmj)
+      case OP_THETA: PUSH(th, th)
+      case OP_QUAD: PUSH(quad, quad)
+      case OP_COMBINE: PUSH(comb, comb)
+#undef PUSH
+      default: continue;
+    }
+    P.launches.push_back(L);
+  }
+}
+
+static GemmTask mk(const double* A, int64_t lda, const double* B, int64_t ldb,
+                   double* C, int64_t ldc, int M, int N, int K_, int flags,
+                   double alpha, double beta) {
+  GemmTask t{};
+  t.A = A; t.B = B; t.C = C;
+  t.lda = lda; t.ldb = ldb; t.ldc = ldc;
+  t.M = M; t.N = N; t.K = K_; t.flags = flags;
+  t.alpha = alpha; t.beta = beta;
+  return t;
+}
+
+static Step gemm_step(uint64_t key, int cat, double flops, std::vector<GemmTask> ts) {
+  Step s;
+  s.key = key;
+  s.kind = OP_GEMM;
+  s.cat = cat;
+  s.flops = flops;
+  s.gemm = std::move(ts);
+  return s;
+}
+
+static Step misc_step(uint64_t key, int cat, int kind, double* dst,
+                      const double* src, int64_t n, double v = 0.0) {
+  Step s;
+  s.key = key;
+  s.kind = OP_MISC;
+  s.cat = cat;
+  s.misc.kind = kind;
+  s.misc.dst = dst;
+  s.misc.src = src;
+  s.misc.n = n;
+  s.misc.v = v;
+  return s;
+}
+
+// Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
+// panels of 64 columns.  Diagonal tiles are overwritten by their inverses
+// (they are used only through them); L(I, j) = A(I, j) G_jj^T; trailing
+// update A(I, J) -= L(I, j) L(J, j)^T.  `breal`: unpadded size (operation
+// count).  Keys (major, group 1, panel j, sub 0..2).
+static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
+                      int n, double* logdiag, int64_t* info, int64_t row0,
+                      int breal) {
+  const int nbk = n / 64;
+  for (int j = 0; j < nbk; ++j) {
+    const double w = (double)std::max(0, std::min(64, breal - j * 64));
+    const double below = (double)std::max(0, breal - (j + 1) * 64);
+    double* Ajj = A + (int64_t)j * 64 * (ld + 1);
+    Step s;
+    s.key = K(major, 1, j, 0);
+    s.kind = OP_POTRF;
+    s.cat = DL_CAT_POTRF_TILE;
+    s.flops = w * w * w / 3.0;
+    s.potrf.A = Ajj;
+    s.potrf.lda = ld;
+    s.potrf.Ginv = nullptr;
+    s.potrf.logdiag = logdiag + (int64_t)j * 64;
+    s.potrf.info = info;
+    s.potrf.row0 = row0 + (int64_t)j * 64;
+    s.potrf.mode = 1;
+    q.push_back(s);
+    if (j + 1 < nbk) {
+      const int rows = n - (j + 1) * 64;
+      double* panel = A + (int64_t)(j + 1) * 64 + (int64_t)j * 64 * ld;
+      q.push_back(gemm_step(K(major, 1, j, 1), DL_CAT_PANEL_TRSM, below * w * w,
+                            {mk(panel, ld, Ajj, ld, panel, ld, rows, 64, 64,
+                                F_TB | F_BETA0, 1.0, 0.0)}));
+      q.push_back(gemm_step(K(major, 1, j, 2), DL_CAT_PANEL_SYRK, below * below * w,
+                            {mk(panel, ld, panel, ld,
+                                A + (int64_t)(j + 1) * 64 * (ld + 1), ld, rows,
+                                rows, 64, F_TB | F_LOWER, -1.0, 1.0)}));
+    }
+  }
+}
+
+// In-place inverse of the lower-triangular factor whose diagonal tiles
+// already hold their inverses: recursive halving, G21 = -G22 (L21 G11), all
+// nodes of one depth merged, deepest first.  temp: n x (n/2 + 64) (ld n).
+// `breal`: unpadded size for the operation count (0: not counted).
+static void collect_nodes(int lo, int hi, int depth,
+                          std::vector<std::vector<int>>& lv) {
+  if (hi - lo <= 1) return;
+  const int mid = lo + (hi - lo) / 2;
+  if ((int)lv.size() <= depth) lv.resize(depth + 1);
+  lv[depth].push_back(lo);
+  lv[depth].push_back(hi);
+  collect_nodes(lo, mid, depth + 1, lv);
+  collect_nodes(mid, hi, depth + 1, lv);
+}
+
+static void seq_trtri(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
+                      int n, double* temp, int breal) {
+  const int nbk = n / 64;
+  auto ext = [&](int lo, int hi) {
+    return (double)std::max(0, std::min(hi * 64, breal) - lo * 64);
+  };
+  std::vector<std::vector<int>> lv;
+  collect_nodes(0, nbk, 0, lv);
+  const int D = (int)lv.size();
+  for (int d = D - 1; d >= 0; --d) {
+    std::vector<GemmTask> tT, tG;
+    double fT = 0.0, fG = 0.0;
+    for (size_t k = 0; k < lv[d].size(); k += 2) {
+      const int lo = lv[d][k], hi = lv[d][k + 1];
+      const int mid = lo + (hi - lo) / 2;
+      const int n1 = (mid - lo) * 64, n2 = (hi - mid) * 64;
+      double* L21 = A + (int64_t)mid * 64 + (int64_t)lo * 64 * ld;
+      double* G11 = A + (int64_t)lo * 64 * (ld + 1);
+      double* G22 = A + (int64_t)mid * 64 * (ld + 1);
+      double* T = temp + (int64_t)lo * 64;
+      tT.push_back(mk(L21, ld, G11, ld, T, n, n2, n1, n1, F_KLO_COL | F_BETA0, 1.0, 0.0));
+      tG.push_back(mk(G22, ld, T, n, L21, ld, n2, n1, n2, F_KHI_ROW | F_BETA0, -1.0, 0.0));
+      const double r1 = ext(lo, mid), r2 = ext(mid, hi);
+      fT += r2 * r1 * r1;
+      fG += r1 * r2 * r2;
+    }
+    const int lvl = 15 - d;  // deeper levels first
+    q.push_back(gemm_step(K(major, 2, lvl, 0), DL_CAT_TRTRI, fT, tT));
+    q.push_back(gemm_step(K(major, 2, lvl, 1), DL_CAT_TRTRI, fG, tG));
+  }
+}
+
+}  // namespace dl
+
+using namespace dl;
+
+// ---- workspace -----------------------------------------------------------------------
+
+struct Inst {
+  const dl_model* model = nullptr;
+  ModelDev m{};
+  int dim = 0;
+  // Q_p: full storage (keep_qp) or a ring of 2 diagonal and 3 sub-diagonal
+  // blocks assembled just in time (only log|Q_p| is needed)
+  double *Dp = nullptr, *Bp = nullptr, *Pp = nullptr;
+  bool qp_ring = true;
+  // Q_c: full storage, [B_t; R_t] in nt+1 slots of (bp+ap) x bp
+  double *Dc = nullptr, *BRc = nullptr, *Pc = nullptr, *GPc = nullptr;
+  int64_t ldbr = 0;
+  std::vector<int> slot_final;
+  double *theta = nullptr, *coef = nullptr, *logdiag[2] = {nullptr, nullptr};
+  double *logdet2 = nullptr, *quad2 = nullptr, *sumpart = nullptr, *qpart = nullptr;
+  int64_t* info2 = nullptr;
+  double *rhs = nullptr, *x = nullptr, *mu = nullptr, *u = nullptr, *gpart = nullptr;
+  double* ttemp[2] = {nullptr, nullptr};
+  double *f = nullptr, *parts = nullptr;
+  int64_t* info_out = nullptr;
+  // selected inversion
+  double *WV = nullptr, *Y = nullptr, *XC[2] = {nullptr, nullptr}, *selout = nullptr;
+  double* GPp = nullptr;
+};
+
+struct dl_ws {
+  std::vector<Inst> inst;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  int flags = 0;
+  bool sel = false, keep_qp = false;
+  int dim_total = 0;
+  double* theta_all = nullptr;   // packed theta of all instances
+  double* f_all = nullptr;       // [B]
+  double* parts_all = nullptr;   // [B x 8]
+  int64_t* info_all = nullptr;   // [B x 2]
+  Descs H;
+  DevDescs Dd;
+  Plan theta_p, asm_p[3], fac_p[3], solve_p, selinv_p, post_p, eval_p;
+  bool assembled[2] = {false, false}, factored[2] = {false, false};
+  bool solved = false;
+  int max_shmem = 0;
+  // graph of the whole evaluation plan
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = false;
+  // launch profiling (measurement only)
+  int prof_mask = 0, prof_by_kernel = 0, prof_used = 0;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_cat;
+  std::vector<double> prof_flops, prof_bytes;
+};
+
+static int prof_begin(dl_ws* W, int cat, int kind, hipStream_t s) {
+  if (!W->prof_mask || !((W->prof_mask >> cat) & 1)) return -1;
+  if (W->prof_used >= (int)W->prof_cat.size()) return -1;
+  const int k = W->prof_used++;
+  if (hipEventRecord(W->prof_ev[2 * k], s) != hipSuccess) return -1;
+  W->prof_cat[k] = W->prof_by_kernel ? kind : cat;
+  return k;
+}
+
+static void prof_end(dl_ws* W, int k, double flops, double bytes, hipStream_t s) {
+  if (k < 0) return;
+  (void)hipEventRecord(W->prof_ev[2 * k + 1], s);
+  W->prof_flops[k] = flops;
+  W->prof_bytes[k] = bytes;
+}
+
+static hipError_t run(dl_ws* W, const Plan& P, hipStream_t s) {
+  const DevDescs& d = W->Dd;
+  for (const Launch& L : P.launches) {
+    int kk = DL_KERNEL_OTHER;
+    if (L.kind == OP_GEMM) kk = DL_KERNEL_GEMM;
+    else if (L.kind == OP_POTRF) kk = DL_KERNEL_POTRF_TILE;
+    else if (L.kind == OP_GEMV_N || L.kind == OP_GEMV_T) kk = DL_KERNEL_GEMV;
+    else if (L.kind == OP_ASM_COLS) kk = DL_KERNEL_ASSEMBLE;
+    const int pk = prof_begin(W, L.cat, kk, s);
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+      case OP_GEMM: e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s); break;
+      case OP_POTRF: e = launch_potrf_tiles(d.potrf + L.off, L.count, s); break;
+      case OP_MISC: e = launch_misc(d.misc + L.off, L.count, s); break;
+      case OP_GEMV_N: e = launch_gemv_n(d.gn + L.off, L.count, L.gx, s); break;
+      case OP_GEMV_T: e = launch_gemv_t(d.gt + L.off, L.count, L.gx, s); break;
+      case OP_SUM: e = launch_sums(d.sum + L.off, L.count, s); break;
+      case OP_FINISH: e = launch_selinv_finish(d.fin + L.off, L.count, L.gx, s); break;
+      case OP_ASM_COLS:
+        e = launch_assemble_cols(d.asmj + L.off, L.count, L.gx, L.gy, W->max_shmem, s);
+        break;
+      case OP_ASM_TIPS: e = launch_assemble_tips(d.asmj + L.off, L.count, L.gx, s); break;
+      case OP_THETA: e = launch_theta_coeffs(d.th + L.off, L.count, s); break;
+      case OP_QUAD: e = launch_quadforms(d.quad + L.off, L.count, s); break;
+      case OP_COMBINE: e = launch_combine(d.comb + L.off, L.count, s); break;
+      default: break;
+    }
+    prof_end(W, pk, L.flops, L.bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---- plan construction -----------------------------------------------------------------
+
+static double asm_bytes(const ModelDev& m, bool p, bool c, int nsteps) {
+  const double b = m.b, a = m.a;
+  const double per = 2.0 * b * b;  // a diagonal and a sub-diagonal block
+  double by = 0.0;
+  if (p) by += per * nsteps;
+  if (c) by += per * nsteps + a * b * nsteps;
+  return 8.0 * by;
+}
+
+// theta -> coefficients, tips and fixed-effect right-hand side, and the dense
+// blocks of Q_c (and Q_p when it is stored in full).
+static void seq_assemble(dl_ws* W, Inst& I, bool p, bool c, std::vector<Step>& q) {
+  const ModelDev& m = I.m;
+  Step th;
+  th.key = K(0, 0, 0, 0);
+  th.kind = OP_THETA;
+  th.cat = DL_CAT_ASSEMBLE;
+  th.th.m = I.model->dev;
+  th.th.theta = I.theta;
+  th.th.coef = I.coef;
+  q.push_back(th);
+  Step tip;
+  tip.key = K(0, 1, 0, 0);
+  tip.kind = OP_ASM_TIPS;
+  tip.cat = DL_CAT_ASSEMBLE;
+  tip.asmj.m = I.model->dev;
+  tip.asmj.coef = I.coef;
+  tip.asmj.o.Pp = p ? I.Pp : nullptr;
+  tip.asmj.o.Pc = c ? I.Pc : nullptr;
+  tip.asmj.o.rhs = I.rhs;
+  tip.gx = 1 + m.nv * m.nr * m.nr + m.nv * m.nr;
+  q.push_back(tip);
+  const bool full_p = p && !I.qp_ring;
+  if (c || full_p) {
+    Step s;
+    s.key = K(0, 2, 0, 0);
+    s.kind = OP_ASM_COLS;
+    s.cat = DL_CAT_ASSEMBLE;
+    s.bytes = asm_bytes(m, full_p, c, m.nt);
+    AsmJob& J = s.asmj;
+    J.m = I.model->dev;
+    J.coef = I.coef;
+    J.t0 = 0;
+    J.nt = m.nt;
+    const int64_t bb = (int64_t)m.bp * m.bp;
+    if (full_p) {
+      J.o.Dp = I.Dp; J.o.dp_stride = bb;
+      J.o.Bp = I.Bp; J.o.bp_stride = bb;
+    }
+    if (c) {
+      J.o.Dc = I.Dc; J.o.dc_stride = bb;
+      J.o.BRc = I.BRc; J.o.brc_stride = I.ldbr * m.bp;
+    }
+    J.o.rhs = I.rhs;
+    s.gx = m.bp;
+    s.gy = m.nt;
+    q.push_back(s);
+  }
+}
+
+// BTA Cholesky of Q_p (w = 0) or Q_c (w = 1) of instance I.  Keys: major =
+// t + 1 (0 is the prologue), then 1 + nt_max for the tip.
+static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& q) {
+  const ModelDev& m = I.m;
+  const int bp = m.bp;
+  const int64_t bb = (int64_t)bp * bp;
+  const bool ring = (w == 0) && I.qp_ring;
+  const int64_t ldbr = (w == 0) ? bp : I.ldbr;
+  const int apr = (w == 0) ? 0 : m.ap;
+  double* P = (w == 0) ? I.Pp : I.Pc;
+  double* logdiag = I.logdiag[w];
+  int64_t* info = I.info2 + w;
+  q.push_back(misc_step(K(0, 0), DL_CAT_OTHER, MJ_ZERO_I64, (double*)info, nullptr, 1));
+  // storage maps
+  std::vector<int> slot(m.nt + 1);
+  for (int t = 0; t <= m.nt; ++t) slot[t] = t;
+  int spare = m.nt;
+  double* Dbase = (w == 0) ? I.Dp : I.Dc;
+  double* Bbase = (w == 0) ? I.Bp : I.BRc;
+  auto Dt = [&](int t) { return Dbase + (ring ? (int64_t)(t % 2) : (int64_t)t) * bb; };
+  auto BRs = [&](int sl) { return Bbase + (int64_t)sl * ldbr * bp; };
+  auto asm_qp = [&](int t, uint64_t key) {
+    Step s;
+    s.key = key;
+    s.kind = OP_ASM_COLS;
+    s.cat = DL_CAT_ASSEMBLE;
+    s.bytes = asm_bytes(m, true, false, 1);
+    s.asmj.m = I.model->dev;
+    s.asmj.coef = I.coef;
+    s.asmj.t0 = t;
+    s.asmj.nt = 1;
+    s.asmj.o.Dp = Dt(t);
+    s.asmj.o.Bp = BRs(t % 2);
+    s.asmj.o.rhs = I.rhs;
+    s.gx = bp;
+    s.gy = 1;
+    q.push_back(s);
+  };
+  if (ring) asm_qp(0, K(0, 3));
+  const bool count_inv = (w == 1) && W->sel;
+  for (int t = 0; t < m.nt; ++t) {
+    const uint64_t major = (uint64_t)t + 1;
+    const bool last = (t + 1 == m.nt);
+    if (ring && !last) asm_qp(t + 1, K(major, 0));
+    seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
+              (int64_t)t * m.b, m.b);
+    seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0);
+    const int rows_lo = last ? bp : 0;
+    const int M = (last ? 0 : bp) + apr;
+    if (M <= 0) continue;
+    int src = ring ? (t % 2) : slot[t];
+    int nw = ring ? 2 : spare;
+    const double b = m.b, ar = apr ? m.a : 0;
+    const double mreal = (last ? 0.0 : b) + ar;
+    // [B_t; R_t] <- [B_t; R_t] L_tt^{-T} = [B_t; R_t] G_t^T
+    q.push_back(gemm_step(K(major, 3), DL_CAT_TRSM, mreal * b * b,
+                          {mk(BRs(src) + rows_lo, ldbr, Dt(t), bp, BRs(nw) + rows_lo,
+                              ldbr, M, bp, bp, F_TB | F_KHI_COL | F_BETA0, 1.0, 0.0)}));
+    if (!ring) {
+      spare = slot[t];
+      slot[t] = nw;
+    }
+    double* BRt = BRs(nw);
+    std::vector<GemmTask> up;
+    if (!last) {
+      up.push_back(mk(BRt, ldbr, BRt, ldbr, Dt(t + 1), bp, bp, bp, bp,
+                      F_TB | F_LOWER, -1.0, 1.0));
+      if (apr)
+        up.push_back(mk(BRt + bp, ldbr, BRt, ldbr, BRs(slot[t + 1]) + bp, ldbr, apr,
+                        bp, bp, F_TB, -1.0, 1.0));
+    }
+    if (apr)
+      up.push_back(mk(BRt + bp, ldbr, BRt + bp, ldbr, P, m.ap, apr, apr, bp,
+                      F_TB | F_LOWER, -1.0, 1.0));
+    const double upd = (last ? 0.0 : b * b * b + 2.0 * ar * b * b) + ar * ar * b;
+    q.push_back(gemm_step(K(major, 4), DL_CAT_UPDATE, upd, up));
+  }
+  const uint64_t tail = (uint64_t)nt_max + 1;
+  if (m.ap > 0) {
+    Step s;
+    s.key = K(tail, 0);
+    s.kind = OP_POTRF;
+    s.cat = DL_CAT_POTRF_TILE;
+    s.flops = (double)m.a * m.a * m.a / 3.0;
+    s.potrf.A = P;
+    s.potrf.lda = m.ap;
+    s.potrf.Ginv = (w == 1) ? I.GPc : I.GPp;
+    s.potrf.logdiag = logdiag + (int64_t)m.nt * bp;
+    s.potrf.info = info;
+    s.potrf.row0 = (int64_t)m.nt * m.b;
+    s.potrf.mode = 0;
+    q.push_back(s);
+  }
+  Step sl;
+  sl.key = K(tail, 1);
+  sl.kind = OP_SUM;
+  sl.cat = DL_CAT_OTHER;
+  sl.sum.src = logdiag;
+  sl.sum.n = m.Np;
+  sl.sum.scale = 2.0;
+  sl.sum.dst = I.logdet2 + w;
+  sl.sum.partial = I.sumpart + w * SUM_BLOCKS;
+  q.push_back(sl);
+  if (w == 1) I.slot_final.assign(slot.begin(), slot.begin() + m.nt);
+}
+
+static Step gn_step(uint64_t key, GemvN g, double bytes) {
+  Step s;
+  s.key = key;
+  s.kind = OP_GEMV_N;
+  s.cat = DL_CAT_SOLVE;
+  s.gn = g;
+  s.bytes = bytes;
+  s.flops = bytes / 4.0;
+  s.gx = g.M;
+  return s;
+}
+
+static Step gt_step(uint64_t key, GemvT g, double bytes) {
+  Step s;
+  s.key = key;
+  s.kind = OP_GEMV_T;
+  s.cat = DL_CAT_SOLVE;
+  s.gt = g;
+  s.bytes = bytes;
+  s.flops = bytes / 4.0;
+  s.gx = g.N;
+  return s;
+}
+
+// Forward and backward block substitution with the factor of Q_c:
+// L z = x (z overwrites x), then L^T mu = z.
+static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
+  const ModelDev& m = I.m;
+  const int bp = m.bp, ap = m.ap;
+  const int64_t ldbr = I.ldbr;
+  const double b = m.b, a = m.a;
+  auto BRs = [&](int t) { return I.BRc + (int64_t)I.slot_final[t] * ldbr * bp; };
+  auto G = [&](int t) { return I.Dc + (int64_t)t * bp * bp; };
+  double* x = I.x;
+  double* xP = x + (int64_t)m.nt * bp;
+  double* mu = I.mu;
+  double* muP = mu + (int64_t)m.nt * bp;
+  double* part = I.gpart;
+  for (int t = 0; t < m.nt; ++t) {
+    double* xt = x + (int64_t)t * bp;
+    const uint64_t mj = (uint64_t)t + 1;
+    if (t > 0)
+      q.push_back(gn_step(K(mj, 0), {bp + ap, bp, BRs(t - 1), ldbr,
+                                     x + (int64_t)(t - 1) * bp, 0, -1.0, 1.0, bp, xt,
+                                     I.u, xP, xP, part},
+                          8.0 * (b + a) * b));
+    q.push_back(gn_step(K(mj, 1), {bp, bp, G(t), bp, t > 0 ? I.u : xt, 1, 1.0, 0.0,
+                                   -1, nullptr, xt, nullptr, nullptr, part},
+                        4.0 * b * b));
+  }
+  const uint64_t mid = (uint64_t)nt_max + 1;
+  if (ap > 0) {
+    q.push_back(gn_step(K(mid, 0), {ap, bp, BRs(m.nt - 1) + bp, ldbr,
+                                    x + (int64_t)(m.nt - 1) * bp, 0, -1.0, 1.0, -1,
+                                    xP, xP, nullptr, nullptr, part},
+                        8.0 * a * b));
+    q.push_back(gn_step(K(mid, 1), {ap, ap, I.GPc, ap, xP, 1, 1.0, 0.0, -1, nullptr,
+                                    xP, nullptr, nullptr, part},
+                        4.0 * a * a));
+    q.push_back(gt_step(K(mid, 2), {ap, ap, I.GPc, ap, xP, -1, nullptr, 1, 1.0, 0.0,
+                                    nullptr, muP},
+                        4.0 * a * a));
+  }
+  for (int t = m.nt - 1; t >= 0; --t) {
+    double* xt = x + (int64_t)t * bp;
+    const uint64_t mj = mid + 1 + (uint64_t)(m.nt - 1 - t);
+    if (t == m.nt - 1) {
+      if (ap > 0)
+        q.push_back(gt_step(K(mj, 0), {ap, bp, BRs(t) + bp, ldbr, muP, -1, nullptr, 0,
+                                       -1.0, 1.0, xt, I.u},
+                            8.0 * a * b));
+      else
+        q.push_back(misc_step(K(mj, 0), DL_CAT_SOLVE, MJ_COPY, I.u, xt, bp));
+    } else {
+      q.push_back(gt_step(K(mj, 0), {bp + ap, bp, BRs(t), ldbr,
+                                     mu + (int64_t)(t + 1) * bp, bp, muP, 0, -1.0, 1.0,
+                                     xt, I.u},
+                          8.0 * (b + a) * b));
+    }
+    q.push_back(gt_step(K(mj, 1), {bp, bp, G(t), bp, I.u, -1, nullptr, 1, 1.0, 0.0,
+                                   nullptr, mu + (int64_t)t * bp},
+                        4.0 * b * b));
+  }
+}
+
+// Takahashi selected inversion of Q_c, backward in time, from the factor's
+// off-diagonal blocks and the diagonal-block inverses G_t.
+static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
+  const ModelDev& m = I.m;
+  const int bp = m.bp, ap = m.ap;
+  const int64_t ld = I.ldbr;  // bp + ap
+  const double b = m.b, a = m.a;
+  auto BRs = [&](int t) { return I.BRc + (int64_t)I.slot_final[t] * ld * bp; };
+  auto G = [&](int t) { return I.Dc + (int64_t)t * bp * bp; };
+  for (int k = 0; k < 2; ++k)
+    q.push_back(misc_step(K(0, 0, 0, k), DL_CAT_SELINV, MJ_FILL, I.XC[k], nullptr,
+                          ld * ld, 0.0));
+  if (ap > 0) {
+    // X_P = G_P^T G_P into the corner of both ping-pong buffers
+    std::vector<GemmTask> xp;
+    for (int k = 0; k < 2; ++k)
+      xp.push_back(mk(I.GPc, ap, I.GPc, ap, I.XC[k] + bp + (int64_t)bp * ld, ld, ap,
+                      ap, ap, F_TA | F_BETA0, 1.0, 0.0));
+    q.push_back(gemm_step(K(0, 1), DL_CAT_SELINV, 2.0 * a * a * a, xp));
+    Step dg = misc_step(K(0, 2), DL_CAT_SELINV, MJ_DIAG,
+                        I.selout + (int64_t)m.nt * bp, I.XC[0] + bp + (int64_t)bp * ld,
+                        ap);
+    dg.misc.lds = ld;
+    q.push_back(dg);
+  }
+  int cur = 0;
+  for (int t = m.nt - 1; t >= 0; --t) {
+    const uint64_t mj = 1 + (uint64_t)(m.nt - 1 - t);
+    const int nxt = cur ^ 1;
+    const bool last = (t + 1 == m.nt);
+    if (last) {
+      q.push_back(misc_step(K(mj, 0), DL_CAT_SELINV, MJ_FILL, I.WV, nullptr, ld * bp));
+      if (ap > 0)
+        q.push_back(gemm_step(K(mj, 1), DL_CAT_SELINV, a * b * b,
+                              {mk(BRs(t) + bp, ld, G(t), bp, I.WV + bp, ld, ap, bp, bp,
+                                  F_KLO_COL | F_BETA0, 1.0, 0.0)}));
+    } else {
+      // [W_t; V_t] = [B_t; R_t]_factor G_t
+      q.push_back(gemm_step(K(mj, 1), DL_CAT_SELINV, (b + a) * b * b,
+                            {mk(BRs(t), ld, G(t), bp, I.WV, ld, bp + ap, bp, bp,
+                                F_KLO_COL | F_BETA0, 1.0, 0.0)}));
+    }
+    const double ba = b + a;
+    // [X_{t+1,t}; X_{P,t}] = -[[X_{t+1,t+1}, X_{t+1,P}]; [X_{P,t+1}, X_P]] WV
+    q.push_back(gemm_step(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
+                          {mk(I.XC[cur], ld, I.WV, ld, I.Y, ld, bp + ap, bp, bp + ap,
+                              F_BETA0, -1.0, 0.0)}));
+    // X_tt = G_t^T G_t - Y^T WV   (lower triangle)
+    q.push_back(gemm_step(K(mj, 3), DL_CAT_SELINV, b * b * b / 3.0,
+                          {mk(G(t), bp, G(t), bp, I.XC[nxt], ld, bp, bp, bp,
+                              F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0, 1.0, 0.0)}));
+    q.push_back(gemm_step(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
+                          {mk(I.Y, ld, I.WV, ld, I.XC[nxt], ld, bp, bp, bp + ap,
+                              F_TA | F_LOWER, -1.0, 1.0)}));
+    Step fin;
+    fin.key = K(mj, 5);
+    fin.kind = OP_FINISH;
+    fin.cat = DL_CAT_SELINV;
+    fin.fin.XC = I.XC[nxt];
+    fin.fin.ld = ld;
+    fin.fin.bp = bp;
+    fin.fin.ap = ap;
+    fin.fin.Y = I.Y;
+    fin.fin.out = I.selout + (int64_t)t * bp;
+    fin.gx = bp;
+    q.push_back(fin);
+    cur = nxt;
+  }
+}
+
+// mu^T Q_p mu, (y - A mu)^T D (y - A mu) and f_obj, per instance.
+static void seq_post(dl_ws* W, Inst& I, int k, std::vector<Step>& q) {
+  Step s;
+  s.key = K(0, 0);
+  s.kind = OP_QUAD;
+  s.cat = DL_CAT_OTHER;
+  s.quad.m = I.model->dev;
+  s.quad.coef = I.coef;
+  s.quad.mu = I.mu;
+  s.quad.partial = I.qpart;
+  s.quad.out2 = I.quad2;
+  q.push_back(s);
+  Step c;
+  c.key = K(0, 1);
+  c.kind = OP_COMBINE;
+  c.cat = DL_CAT_OTHER;
+  c.comb.coef = I.coef;
+  c.comb.logdet2 = I.logdet2;
+  c.comb.info2 = I.info2;
+  c.comb.quad2 = I.quad2;
+  c.comb.f = W->f_all + k;
+  c.comb.parts = (dl_fobj_parts*)(W->parts_all + 8 * (int64_t)k);
+  c.comb.info_out = W->info_all + 2 * (int64_t)k;
+  q.push_back(c);
+}
+
+static void append(Plan& dst, const Plan& src) {
+  dst.launches.insert(dst.launches.end(), src.launches.begin(), src.launches.end());
+}
+
+static dl_status build_plans(dl_ws* W) {
+  int nt_max = 0;
+  for (auto& I : W->inst) nt_max = std::max(nt_max, I.m.nt);
+  Descs& H = W->H;
+  // assembly: which = 0 (Q_p), 1 (Q_c), 2 (both)
+  for (int wh = 0; wh < 3; ++wh) {
+    std::vector<std::vector<Step>> seqs;
+    for (auto& I : W->inst) {
+      seqs.emplace_back();
+      seq_assemble(W, I, wh != 1, wh != 0, seqs.back());
+    }
+    merge(seqs, H, W->asm_p[wh]);
+  }
+  for (int wh = 0; wh < 3; ++wh) {
+    std::vector<std::vector<Step>> seqs;
+    for (auto& I : W->inst)
+      for (int w = 0; w < 2; ++w) {
+        if ((wh == 0 && w == 1) || (wh == 1 && w == 0)) continue;
+        seqs.emplace_back();
+        seq_factor(W, I, w, nt_max, seqs.back());
+      }
+    merge(seqs, H, W->fac_p[wh]);
+  }
+  {
+    std::vector<std::vector<Step>> seqs;
+    for (auto& I : W->inst) {
+      seqs.emplace_back();
+      seqs.back().push_back(misc_step(K(0, 0), DL_CAT_SOLVE, MJ_COPY, I.x, I.rhs, I.m.Np));
+      std::vector<Step> s2;
+      seq_solve(W, I, nt_max, s2);
+      for (auto& st : s2) st.key += K(1, 0);  // after the copy
+      seqs.back().insert(seqs.back().end(), s2.begin(), s2.end());
+    }
+    merge(seqs, H, W->solve_p);
+  }
+  {
+    std::vector<std::vector<Step>> seqs;
+    for (size_t k = 0; k < W->inst.size(); ++k) {
+      seqs.emplace_back();
+      seq_post(W, W->inst[k], (int)k, seqs.back());
+    }
+    merge(seqs, H, W->post_p);
+  }
+  if (W->sel) {
+    std::vector<std::vector<Step>> seqs;
+    for (auto& I : W->inst) {
+      seqs.emplace_back();
+      seq_selinv(W, I, nt_max, seqs.back());
+    }
+    merge(seqs, H, W->selinv_p);
+  }
+  W->eval_p.launches.clear();
+  append(W->eval_p, W->asm_p[2]);
+  append(W->eval_p, W->fac_p[2]);
+  append(W->eval_p, W->solve_p);
+  append(W->eval_p, W->post_p);
+  // upload descriptor arrays
+  dl_status st = DL_OK;
+  auto up = [&](auto& vec, auto*& dptr) {
+    using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+    if (st != DL_OK) return;
+    void* p = nullptr;
+    st = dev_alloc(W->allocs, sizeof(T) * (vec.size() + 1), &p, &W->bytes);
+    if (st != DL_OK) return;
+    if (!vec.empty() &&
+        hipMemcpy(p, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      st = DL_EHIP;
+    dptr = (T*)p;
+  };
+  up(H.gemm, W->Dd.gemm);
+  up(H.potrf, W->Dd.potrf);
+  up(H.misc, W->Dd.misc);
+  up(H.gn, W->Dd.gn);
+  up(H.gt, W->Dd.gt);
+  up(H.sum, W->Dd.sum);
+  up(H.fin, W->Dd.fin);
+  up(H.asmj, W->Dd.asmj);
+  up(H.th, W->Dd.th);
+  up(H.quad, W->Dd.quad);
+  up(H.comb, W->Dd.comb);
+  return st;
+}
+
+static void ws_free(dl_ws* W) {
+  if (!W) return;
+  for (hipEvent_t e : W->prof_ev) (void)hipEventDestroy(e);
+  if (W->graph_exec) (void)hipGraphExecDestroy(W->graph_exec);
+  if (W->graph) (void)hipGraphDestroy(W->graph);
+  if (W->cap_stream) (void)hipStreamDestroy(W->cap_stream);
+  free_all(W->allocs);
+  delete W;
+}
+
+extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
+                                        int32_t nmodels, int32_t flags,
+                                        dl_ws** out) {
+  if (!models || nmodels <= 0 || !out) return DL_EINVAL;
+  for (int k = 0; k < nmodels; ++k)
+    if (!models[k]) return DL_EINVAL;
+  dl_ws* W = new (std::nothrow) dl_ws();
+  if (!W) return DL_ENOMEM;
+  W->flags = flags;
+  W->sel = (flags & DL_WS_SELINV) != 0;
+  W->keep_qp = (flags & DL_WS_KEEP_QP) != 0;
+  W->use_graph = (flags & DL_WS_GRAPH) != 0;
+  W->inst.resize(nmodels);
+  dl_status st = DL_OK;
+  auto A = [&](size_t bytes, void** p) {
+    if (st == DL_OK) st = dev_alloc(W->allocs, bytes, p, &W->bytes);
+  };
+  int dim_total = 0;
+  for (int k = 0; k < nmodels; ++k) {
+    Inst& I = W->inst[k];
+    I.model = models[k];
+    I.m = models[k]->d;
+    I.dim = I.m.dim_theta;
+    dim_total += I.dim;
+    const ModelDev& m = I.m;
+    const int bp = m.bp, ap = m.ap;
+    const int64_t bb = (int64_t)bp * bp;
+    W->max_shmem = std::max(W->max_shmem, 2 * bp + ap);
+    I.qp_ring = !W->keep_qp;
+    I.ldbr = bp + ap;
+    if (I.qp_ring) {
+      A(sizeof(double) * 2 * bb, (void**)&I.Dp);
+      A(sizeof(double) * 3 * bb, (void**)&I.Bp);
+    } else {
+      A(sizeof(double) * m.nt * bb, (void**)&I.Dp);
+      A(sizeof(double) * (m.nt + 1) * bb, (void**)&I.Bp);
+    }
+    A(sizeof(double) * m.nt * bb, (void**)&I.Dc);
+    A(sizeof(double) * (m.nt + 1) * I.ldbr * bp, (void**)&I.BRc);
+    const size_t tip = sizeof(double) * (ap > 0 ? ap * ap : 1);
+    A(tip, (void**)&I.Pp);
+    A(tip, (void**)&I.Pc);
+    A(tip, (void**)&I.GPc);
+    A(tip, (void**)&I.GPp);
+    for (int w = 0; w < 2; ++w) {
+      A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttemp[w]);
+      A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
+    }
+    A(sizeof(double) * (I.dim + 1), (void**)&I.theta);
+    A(sizeof(double) * C_SIZE, (void**)&I.coef);
+    A(sizeof(double) * 2, (void**)&I.logdet2);
+    A(sizeof(int64_t) * 2, (void**)&I.info2);
+    A(sizeof(double) * 2, (void**)&I.quad2);
+    A(sizeof(double) * 2 * SUM_BLOCKS, (void**)&I.sumpart);
+    A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.qpart);
+    A(sizeof(double) * m.Np, (void**)&I.rhs);
+    A(sizeof(double) * m.Np, (void**)&I.x);
+    A(sizeof(double) * m.Np, (void**)&I.mu);
+    A(sizeof(double) * I.ldbr, (void**)&I.u);
+    A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
+    if (W->sel) {
+      A(sizeof(double) * I.ldbr * bp, (void**)&I.WV);
+      A(sizeof(double) * I.ldbr * bp, (void**)&I.Y);
+      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[0]);
+      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[1]);
+      A(sizeof(double) * m.Np, (void**)&I.selout);
+    }
+  }
+  W->dim_total = dim_total;
+  A(sizeof(double) * (dim_total + 1), (void**)&W->theta_all);
+  A(sizeof(double) * nmodels, (void**)&W->f_all);
+  A(sizeof(double) * 8 * nmodels, (void**)&W->parts_all);
+  A(sizeof(int64_t) * 2 * nmodels, (void**)&W->info_all);
+  if (st != DL_OK) {
+    ws_free(W);
+    return st;
+  }
+  // instance theta buffers are views of the packed array
+  {
+    int off = 0;
+    for (auto& I : W->inst) {
+      I.theta = W->theta_all + off;
+      off += I.dim;
+    }
+  }
+  if (W->max_shmem * 8 > 160 * 1024 ||
+      prepare_assemble(W->max_shmem) != hipSuccess) {
+    ws_free(W);
+    return DL_EINVAL;
+  }
+  if ((st = build_plans(W)) != DL_OK) {
+    ws_free(W);
+    return st;
+  }
+  *out = W;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_create(const dl_model* model, int32_t flags,
+                                  dl_ws** out) {
+  const dl_model* ms[1] = {model};
+  return dl_ws_create_batch(ms, 1, flags, out);
+}
+
+extern "C" void dl_ws_destroy(dl_ws* W) { ws_free(W); }
+extern "C" size_t dl_ws_bytes(const dl_ws* W) { return W ? W->bytes : 0; }
+extern "C" int32_t dl_ws_batch(const dl_ws* W) { return W ? (int32_t)W->inst.size() : 0; }
+
+// ---- entry points --------------------------------------------------------------------------
+
+static dl_status copy_theta_in(dl_ws* W, const double* theta_dev, int n_inst,
+                               hipStream_t s) {
+  int dims = 0;
+  for (int k = 0; k < n_inst; ++k) dims += W->inst[k].dim;
+  DL_HIP_CHECK(hipMemcpyAsync(W->theta_all, theta_dev, sizeof(double) * dims,
+                              hipMemcpyDeviceToDevice, s));
+  return DL_OK;
+}
+
+extern "C" dl_status bta_assemble(dl_ws* W, const double* theta_dev,
+                                  dl_which which, void* stream) {
+  if (!W || !theta_dev || which < DL_QP || which > DL_BOTH) return DL_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  dl_status st = copy_theta_in(W, theta_dev, (int)W->inst.size(), s);
+  if (st != DL_OK) return st;
+  DL_HIP_CHECK(run(W, W->asm_p[which], s));
+  if (which != DL_QC) { W->assembled[0] = true; W->factored[0] = false; }
+  if (which != DL_QP) { W->assembled[1] = true; W->factored[1] = false; }
+  W->solved = false;
+  return DL_OK;
+}
+
+extern "C" dl_status bta_factor(dl_ws* W, dl_which which, double* logdet_dev,
+                                int64_t* info_dev, void* stream) {
+  if (!W || which < DL_QP || which > DL_BOTH) return DL_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int w0 = which == DL_QC ? 1 : 0;
+  const int w1 = which == DL_QP ? 0 : 1;
+  for (int w = w0; w <= w1; ++w)
+    if (!W->assembled[w]) return DL_ESTATE;
+  DL_HIP_CHECK(run(W, W->fac_p[which], s));
+  for (int w = w0; w <= w1; ++w) {
+    W->assembled[w] = false;
+    W->factored[w] = true;
+  }
+  const int cnt = w1 - w0 + 1;
+  for (size_t k = 0; k < W->inst.size(); ++k) {
+    Inst& I = W->inst[k];
+    if (logdet_dev)
+      DL_HIP_CHECK(hipMemcpyAsync(logdet_dev + cnt * k, I.logdet2 + w0,
+                                  cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (info_dev)
+      DL_HIP_CHECK(hipMemcpyAsync(info_dev + cnt * k, I.info2 + w0,
+                                  cnt * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status bta_solve(dl_ws* W, double* rhs_inout_dev, void* stream) {
+  if (!W) return DL_EINVAL;
+  if (!W->factored[1]) return DL_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  if (rhs_inout_dev) {
+    // the plan copies rhs -> x first, so stage the caller's vectors in rhs
+    int64_t off = 0;
+    for (auto& I : W->inst) {
+      DL_HIP_CHECK(launch_unpack(I.m, rhs_inout_dev + off, I.rhs, s));
+      off += I.m.N;
+    }
+  }
+  DL_HIP_CHECK(run(W, W->solve_p, s));
+  if (rhs_inout_dev) {
+    int64_t off = 0;
+    for (auto& I : W->inst) {
+      DL_HIP_CHECK(launch_pack(I.m, I.mu, rhs_inout_dev + off, s));
+      off += I.m.N;
+    }
+  }
+  W->solved = true;
+  return DL_OK;
+}
+
+extern "C" dl_status bta_selinv(dl_ws* W, double* diag_out_dev, void* stream) {
+  if (!W || !diag_out_dev) return DL_EINVAL;
+  if (!W->sel || !W->factored[1]) return DL_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  DL_HIP_CHECK(run(W, W->selinv_p, s));
+  int64_t off = 0;
+  for (auto& I : W->inst) {
+    DL_HIP_CHECK(launch_pack(I.m, I.selout, diag_out_dev + off, s));
+    off += I.m.N;
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_mean(dl_ws* W, double* out_dev, void* stream) {
+  if (!W || !out_dev) return DL_EINVAL;
+  if (!W->solved) return DL_ESTATE;
+  int64_t off = 0;
+  for (auto& I : W->inst) {
+    DL_HIP_CHECK(launch_pack(I.m, I.mu, out_dev + off, (hipStream_t)stream));
+    off += I.m.N;
+  }
+  return DL_OK;
+}
+
+static dl_status run_eval(dl_ws* W, hipStream_t s) {
+  if (!W->use_graph) {
+    DL_HIP_CHECK(run(W, W->eval_p, s));
+    return DL_OK;
+  }
+  if (!W->graph_exec) {
+    // capture the whole evaluation on a private stream once; the captured
+    // launches read theta from and write results to the workspace buffers
+    if (!W->cap_stream)
+      DL_HIP_CHECK(hipStreamCreateWithFlags(&W->cap_stream, hipStreamNonBlocking));
+    DL_HIP_CHECK(hipStreamBeginCapture(W->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = run(W, W->eval_p, W->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(W->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return DL_EHIP;
+    }
+    W->graph = g;
+    DL_HIP_CHECK(hipGraphInstantiate(&W->graph_exec, g, nullptr, nullptr, 0));
+  }
+  DL_HIP_CHECK(hipGraphLaunch(W->graph_exec, s));
+  return DL_OK;
+}
+
+extern "C" dl_status fobj_eval(dl_ws* W, const double* theta_dev, int32_t ntheta,
+                               double* fobj_dev, dl_fobj_parts* parts_dev,
+                               int64_t* info_dev, void* stream) {
+  if (!W || !theta_dev || ntheta < 0 || (!fobj_dev && !parts_dev)) return DL_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)W->inst.size();
+  // instances of different models take exactly one theta each
+  bool uniform = true;
+  for (auto& I : W->inst)
+    if (I.model != W->inst[0].model) uniform = false;
+  if (!uniform && ntheta != B) return DL_EINVAL;
+  const int dim = W->inst[0].dim;
+  for (int k0 = 0; k0 < ntheta; k0 += B) {
+    const int nk = std::min(B, ntheta - k0);
+    dl_status st = copy_theta_in(W, theta_dev + (int64_t)k0 * dim, nk, s);
+    if (st != DL_OK) return st;
+    if ((st = run_eval(W, s)) != DL_OK) return st;
+    if (fobj_dev)
+      DL_HIP_CHECK(hipMemcpyAsync(fobj_dev + k0, W->f_all, sizeof(double) * nk,
+                                  hipMemcpyDeviceToDevice, s));
+    if (parts_dev)
+      DL_HIP_CHECK(hipMemcpyAsync(parts_dev + k0, W->parts_all,
+                                  sizeof(dl_fobj_parts) * nk,
+                                  hipMemcpyDeviceToDevice, s));
+    if (info_dev)
+      DL_HIP_CHECK(hipMemcpyAsync(info_dev + 2 * (int64_t)k0, W->info_all,
+                                  sizeof(int64_t) * 2 * nk, hipMemcpyDeviceToDevice, s));
+  }
+  W->assembled[0] = W->assembled[1] = false;
+  W->factored[0] = W->factored[1] = true;
+  W->solved = true;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_get_block(dl_ws* W, dl_which which, int32_t kind,
+                                     int32_t t, double* out_dev, void* stream) {
+  if (!W || !out_dev || (which != DL_QP && which != DL_QC)) return DL_EINVAL;
+  if (W->inst.size() != 1) return DL_EINVAL;
+  Inst& I = W->inst[0];
+  const ModelDev& m = I.m;
+  hipStream_t s = (hipStream_t)stream;
+  const int bp = m.bp;
+  const bool p = which == DL_QP;
+  if (p && I.qp_ring && kind != 3 && kind != 4) return DL_ESTATE;
+  std::vector<MiscJob> jobs(1);
+  MiscJob& J = jobs[0];
+  J.kind = MJ_COPY2D;
+  J.dst = out_dev;
+  if (kind == 4) {
+    DL_HIP_CHECK(launch_pack(m, I.rhs, out_dev, s));
+    return DL_OK;
+  }
+  if (kind == 3) {
+    if (m.a == 0) return DL_EINVAL;
+    J.src = p ? I.Pp : I.Pc; J.lds = m.ap; J.ldd = m.a; J.rows = m.a; J.cols = m.a;
+  } else {
+    if (t < 0 || t >= m.nt) return DL_EINVAL;
+    const bool fact = W->factored[p ? 0 : 1];
+    const int sl = (!p && fact) ? I.slot_final[t] : t;
+    const int64_t ldbr = p ? bp : I.ldbr;
+    const double* BRt = (p ? I.Bp : I.BRc) + (int64_t)sl * ldbr * bp;
+    if (kind == 0) {
+      J.src = (p ? I.Dp : I.Dc) + (int64_t)t * bp * bp; J.lds = bp;
+      J.ldd = m.b; J.rows = m.b; J.cols = m.b;
+    } else if (kind == 1) {
+      if (t + 1 >= m.nt) return DL_EINVAL;
+      J.src = BRt; J.lds = ldbr; J.ldd = m.b; J.rows = m.b; J.cols = m.b;
+    } else if (kind == 2) {
+      if (p || m.a == 0) return DL_EINVAL;
+      J.src = BRt + bp; J.lds = ldbr; J.ldd = m.a; J.rows = m.a; J.cols = m.b;
+    } else {
+      return DL_EINVAL;
+    }
+  }
+  // one-off descriptor copy (inspection path, synchronous)
+  void* d = nullptr;
+  DL_HIP_CHECK(hipMalloc(&d, sizeof(MiscJob)));
+  hipError_t e = hipMemcpyAsync(d, jobs.data(), sizeof(MiscJob), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_misc((const MiscJob*)d, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  return e == hipSuccess ? DL_OK : DL_EHIP;
+}
+
+// ---- profiling ----------------------------------------------------------------------------
+
+static void prof_free(dl_ws* W) {
+  for (hipEvent_t e : W->prof_ev) (void)hipEventDestroy(e);
+  W->prof_ev.clear();
+  W->prof_cat.clear();
+  W->prof_flops.clear();
+  W->prof_bytes.clear();
+  W->prof_used = 0;
+  W->prof_mask = 0;
+}
+
+extern "C" dl_status dl_ws_profile_begin(dl_ws* W, int32_t mask, int32_t max_launches) {
+  if (!W || max_launches <= 0 || (mask & 0xffff) == 0) return DL_EINVAL;
+  if (W->use_graph) return DL_ESTATE;
+  prof_free(W);
+  W->prof_by_kernel = (mask & DL_PROFILE_BY_KERNEL) ? 1 : 0;
+  W->prof_ev.resize(2 * (size_t)max_launches, nullptr);
+  for (auto& e : W->prof_ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      prof_free(W);
+      return DL_EHIP;
+    }
+  W->prof_cat.assign(max_launches, 0);
+  W->prof_flops.assign(max_launches, 0.0);
+  W->prof_bytes.assign(max_launches, 0.0);
+  W->prof_mask = mask & 0xffff;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_profile_end(dl_ws* W, double* ms, int64_t* launches,
+                                       double* flops, double* bytes) {
+  if (!W) return DL_EINVAL;
+  for (int c = 0; c < DL_NCAT; ++c) {
+    if (ms) ms[c] = 0.0;
+    if (launches) launches[c] = 0;
+    if (flops) flops[c] = 0.0;
+    if (bytes) bytes[c] = 0.0;
+  }
+  dl_status st = DL_OK;
+  for (int k = 0; k < W->prof_used; ++k) {
+    if (hipEventSynchronize(W->prof_ev[2 * k + 1]) != hipSuccess) { st = DL_EHIP; break; }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, W->prof_ev[2 * k], W->prof_ev[2 * k + 1]) != hipSuccess) {
+      st = DL_EHIP;
+      break;
+    }
+    const int c = W->prof_cat[k];
+    if (ms) ms[c] += t;
+    if (launches) launches[c] += 1;
+    if (flops) flops[c] += W->prof_flops[k];
+    if (bytes) bytes[c] += W->prof_bytes[k];
+  }
+  prof_free(W);
+  return st;
+}

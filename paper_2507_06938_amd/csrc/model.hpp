@@ -50,27 +50,68 @@ struct ModelDev {
   double prior_fixed;
 };
 
+// Dense targets of one assembly job.  Time step t0 + k of the job writes
+// Dp + k*dp_stride (Q_p diagonal block, ld bp), Bp + k*bp_stride (Q_p
+// sub-diagonal block, ld bp), Dc + k*dc_stride, BRc + k*brc_stride
+// ([B_t; R_t] of Q_c, ld bp+ap) and the right-hand side rhs[t*bp + c]
+// (with Q_c).  A null pointer skips that matrix.
 struct AssembleOut {
-  double* Dp;   // nt x (bp x bp), ld bp       (nullptr: skip Q_p)
-  double* Bp;   // slots of bp x bp, ld bp     (slot t for time t)
-  double* Dc;   // nt x (bp x bp)              (nullptr: skip Q_c)
-  double* BRc;  // slots of (bp+ap) x bp, ld bp+ap
+  double* Dp;
+  int64_t dp_stride;
+  double* Bp;
+  int64_t bp_stride;
+  double* Dc;
+  int64_t dc_stride;
+  double* BRc;
+  int64_t brc_stride;
   double* Pp;   // ap x ap (tip of Q_p), ld ap
   double* Pc;   // ap x ap (tip of Q_c)
   double* rhs;  // Np
 };
 
-hipError_t launch_theta_coeffs(const ModelDev& m, const double* theta,
-                               double* coef, hipStream_t s);
-hipError_t launch_assemble(const ModelDev& m, const double* coef,
-                           const AssembleOut& o, hipStream_t s);
-hipError_t launch_quadforms(const ModelDev& m, const double* coef,
-                            const double* mu, double* partial, double* out2,
-                            hipStream_t s);
-hipError_t launch_combine(const ModelDev& m, const double* coef,
-                          const double* logdet2, const int64_t* info2,
-                          const double* quad2, double* f, dl_fobj_parts* parts,
-                          int64_t* info_out, hipStream_t s);
+struct ThetaJob {
+  const ModelDev* m;
+  const double* theta;
+  double* coef;
+};
+
+struct AsmJob {
+  const ModelDev* m;
+  const double* coef;
+  AssembleOut o;
+  int t0, nt;
+};
+
+struct QuadJob {
+  const ModelDev* m;
+  const double* coef;
+  const double* mu;
+  double* partial;  // 2 * QF_BLOCKS
+  double* out2;     // [mu^T Q_p mu, (y - A mu)^T D (y - A mu)]
+};
+
+struct CombineJob {
+  const double* coef;
+  const double* logdet2;
+  const int64_t* info2;
+  const double* quad2;
+  double* f;
+  dl_fobj_parts* parts;
+  int64_t* info_out;
+};
+
+constexpr int QF_BLOCKS = 256;
+
+hipError_t launch_theta_coeffs(const ThetaJob* jobs, int count, hipStream_t s);
+// max_bp / max_nt bound the grid over the jobs; max_shmem_doubles = max over
+// the jobs' models of 2*bp + ap.
+hipError_t launch_assemble_cols(const AsmJob* jobs, int count, int max_bp,
+                                int max_nt, int max_shmem_doubles, hipStream_t s);
+hipError_t prepare_assemble(int max_shmem_doubles);
+hipError_t launch_assemble_tips(const AsmJob* jobs, int count, int max_blocks,
+                                hipStream_t s);
+hipError_t launch_quadforms(const QuadJob* jobs, int count, hipStream_t s);
+hipError_t launch_combine(const CombineJob* jobs, int count, hipStream_t s);
 hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
                        hipStream_t s);
 hipError_t launch_unpack(const ModelDev& m, const double* in, double* padded,

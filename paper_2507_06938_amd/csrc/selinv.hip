@@ -4,22 +4,18 @@
 
 namespace dl {
 
-// After X_tt (lower triangle) is formed in XC (ld = bp+ap):
-//   * mirror its lower triangle to the upper one (X_tt is symmetric and the
-//     next step multiplies with the full block);
-//   * place X_{P,t} (rows bp.. of Y) into XC's arrow rows and, transposed,
-//     its arrow columns;
-//   * write diag(X_tt) to out.
-// Workgroups 0..ntri-1 mirror one lower 64x64 tile pair each through LDS;
-// the next ceil(bp/64) workgroups copy the arrow rows/columns and the
+// Workgroups 0..ntri-1 of job blockIdx.y mirror one lower 64x64 tile each
+// through LDS; the next bp/64 workgroups copy the arrow rows/columns and the
 // diagonal of one 64-column strip.
-__global__ __launch_bounds__(256) void k_selinv_finish(double* XC, int64_t ld,
-                                                       int bp, int ap,
-                                                       const double* Y,
-                                                       double* out, int ntri) {
+__global__ __launch_bounds__(256) void k_selinv_finish(const FinishJob* __restrict__ jobs) {
   __shared__ double tile[64][65];
+  const FinishJob F = jobs[blockIdx.y];
+  const int T = F.bp / 64;
+  const int ntri = T * (T + 1) / 2;
   const int tid = threadIdx.x;
   int blk = blockIdx.x;
+  double* XC = F.XC;
+  const int64_t ld = F.ld;
   if (blk < ntri) {
     int I = (int)((sqrt(8.0 * (double)blk + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= blk) ++I;
@@ -40,67 +36,24 @@ __global__ __launch_bounds__(256) void k_selinv_finish(double* XC, int64_t ld,
     return;
   }
   blk -= ntri;
+  if (blk >= T) return;
   const int c0 = blk * 64;
+  const int ap = F.ap, bp = F.bp;
   for (int idx = tid; idx < 64 * ap; idx += 256) {
     const int i = idx % ap, c = c0 + idx / ap;
-    if (c >= bp) continue;
-    const double v = Y[(int64_t)(bp + i) + (int64_t)c * ld];
+    const double v = F.Y[(int64_t)(bp + i) + (int64_t)c * ld];
     XC[(int64_t)(bp + i) + (int64_t)c * ld] = v;
     XC[(int64_t)c + (int64_t)(bp + i) * ld] = v;
   }
-  if (tid < 64 && c0 + tid < bp)
-    out[c0 + tid] = XC[(int64_t)(c0 + tid) * (ld + 1)];
+  if (tid < 64) F.out[c0 + tid] = XC[(int64_t)(c0 + tid) * (ld + 1)];
 }
 
-hipError_t launch_selinv_finish(double* XC, int64_t ld, int bp, int ap,
-                                const double* Y, double* out, hipStream_t s) {
-  const int T = bp / 64;
-  const int ntri = T * (T + 1) / 2;
-  hipLaunchKernelGGL(k_selinv_finish, dim3(ntri + T), dim3(256), 0, s, XC, ld,
-                     bp, ap, Y, out, ntri);
-  return hipGetLastError();
-}
-
-__global__ void k_diag_copy(const double* A, int64_t ld, int n, double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = A[(int64_t)i * (ld + 1)];
-}
-
-hipError_t launch_diag_copy(const double* A, int64_t ld, int n, double* out,
-                            hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag_copy, dim3((n + 255) / 256), dim3(256), 0, s, A, ld,
-                     n, out);
-  return hipGetLastError();
-}
-
-__global__ void k_zero_i64(int64_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
-hipError_t launch_zero_i64(int64_t* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_i64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
-// Copy the leading rows x cols of a column-major matrix.
-__global__ void k_copy2d(const double* src, int64_t lds, double* dst,
-                         int64_t ldd, int rows, int cols) {
-  const int64_t n = (int64_t)rows * cols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(i % rows), c = (int)(i / rows);
-    dst[r + (int64_t)c * ldd] = src[r + (int64_t)c * lds];
-  }
-}
-
-hipError_t launch_copy2d(const double* src, int64_t lds, double* dst,
-                         int64_t ldd, int rows, int cols, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy2d, dim3(1024), dim3(256), 0, s, src, lds, dst, ldd,
-                     rows, cols);
+hipError_t launch_selinv_finish(const FinishJob* jobs, int count, int max_bp,
+                                hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int T = max_bp / 64;
+  hipLaunchKernelGGL(k_selinv_finish, dim3(T * (T + 1) / 2 + T, count), dim3(256),
+                     0, s, jobs);
   return hipGetLastError();
 }
 

@@ -2,11 +2,17 @@
 #include "common.hpp"
 
 namespace dl {
-hipError_t launch_selinv_finish(double* XC, int64_t ld, int bp, int ap,
-                                const double* Y, double* out, hipStream_t s);
-hipError_t launch_diag_copy(const double* A, int64_t ld, int n, double* out,
-                            hipStream_t s);
-hipError_t launch_zero_i64(int64_t* p, int n, hipStream_t s);
-hipError_t launch_copy2d(const double* src, int64_t lds, double* dst,
-                         int64_t ldd, int rows, int cols, hipStream_t s);
+// One step of the selected-inversion sweep is finished per job: mirror the
+// lower triangle of X_tt (bp x bp at XC, ld) to its upper triangle, copy
+// X_{P,t} (rows bp.. of Y) into the arrow rows and columns of XC, and write
+// diag(X_tt) to out.
+struct FinishJob {
+  double* XC;
+  int64_t ld;
+  int bp, ap;
+  const double* Y;
+  double* out;
+};
+hipError_t launch_selinv_finish(const FinishJob* jobs_dev, int count,
+                                int max_bp, hipStream_t s);
 }  // namespace dl

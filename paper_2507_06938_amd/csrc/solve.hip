@@ -1,112 +1,84 @@
-// Memory-bound matrix-vector products for the block forward/backward solves
-// (HBM-bound: each launch streams one dense block once, coalesced).
-#include "common.hpp"
+// Memory-bound matrix-vector products of the block forward/backward solves
+// (HBM-bound: each job streams one dense block once, coalesced).  One launch
+// serves a batch of independent jobs (one per matrix of a batch).
 #include "solve.hpp"
 
 namespace dl {
 
-// y = beta*base + alpha*A*x, A column-major M x K.  Grid (ceil(M/64), KS):
-// workgroup (i, s) sums columns of its k-split into partial[s*M + row];
-// lane = row, the 4 waves interleave columns and are combined in a fixed
-// order.  `tri`: A is lower triangular, columns k > row are skipped.
+// Workgroup (i, s, j): rows 64i..64i+63 of job j, k-split s; lane = row, the
+// 4 waves interleave columns and are combined in a fixed order.  `tri`: A is
+// lower triangular, columns k > row are skipped.
 __global__ __launch_bounds__(256) void k_gemv_n_partial(
-    int M, int K, const double* __restrict__ A, int64_t lda,
-    const double* __restrict__ x, int tri, int ks_len,
-    double* __restrict__ partial) {
+    const GemvN* __restrict__ jobs) {
   __shared__ double sh[4][64];
+  const GemvN g = jobs[blockIdx.z];
+  if ((int)blockIdx.x * 64 >= g.M) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = blockIdx.x * 64 + lane;
-  int k0 = blockIdx.y * ks_len;
-  int k1 = min(K, k0 + ks_len);
-  if (tri) k1 = min(k1, blockIdx.x * 64 + 64);
+  const int ks_len = (g.K + GEMV_KS - 1) / GEMV_KS;
+  const int k0 = blockIdx.y * ks_len;
+  int k1 = min(g.K, k0 + ks_len);
+  if (g.tri) k1 = min(k1, (int)blockIdx.x * 64 + 64);
   double acc = 0.0;
-  if (row < M) {
+  if (row < g.M) {
     for (int k = k0 + wave; k < k1; k += 4)
-      acc += A[(int64_t)row + (int64_t)k * lda] * x[k];
+      acc += g.A[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
   }
   sh[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && row < M)
-    partial[(int64_t)blockIdx.y * M + row] =
+  if (wave == 0 && row < g.M)
+    g.partial[(int64_t)blockIdx.y * g.M + row] =
         (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
-__global__ void k_gemv_n_finish(int M, int KS, const double* __restrict__ partial,
-                                double alpha, double beta, int split,
-                                const double* base1, double* out1,
-                                const double* base2, double* out2) {
+__global__ void k_gemv_n_finish(const GemvN* __restrict__ jobs) {
+  const GemvN g = jobs[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
+  if (i >= g.M) return;
   double s = 0.0;
-  for (int k = 0; k < KS; ++k) s += partial[(int64_t)k * M + i];
+  for (int k = 0; k < GEMV_KS; ++k) s += g.partial[(int64_t)k * g.M + i];
+  const int split = g.split < 0 ? g.M : g.split;
   if (i < split) {
-    const double b = base1 ? beta * base1[i] : 0.0;
-    out1[i] = b + alpha * s;
+    const double b = g.base1 ? g.beta * g.base1[i] : 0.0;
+    g.out1[i] = b + g.alpha * s;
   } else {
-    const double b = base2 ? beta * base2[i - split] : 0.0;
-    out2[i - split] = b + alpha * s;
+    const double b = g.base2 ? g.beta * g.base2[i - split] : 0.0;
+    g.out2[i - split] = b + g.alpha * s;
   }
 }
 
-hipError_t launch_gemv_n(const GemvN& g, double* partial, hipStream_t s) {
-  if (g.M <= 0) return hipSuccess;
-  int KS = (g.K + 255) / 256;
-  if (KS < 1) KS = 1;
-  if (KS > GEMV_MAX_KS) KS = GEMV_MAX_KS;
-  const int ks_len = (g.K + KS - 1) / KS;
-  dim3 grid((g.M + 63) / 64, KS);
-  hipLaunchKernelGGL(k_gemv_n_partial, grid, dim3(256), 0, s, g.M, g.K, g.A,
-                     g.lda, g.x, g.tri, ks_len, partial);
-  hipLaunchKernelGGL(k_gemv_n_finish, dim3((g.M + 255) / 256), dim3(256), 0, s,
-                     g.M, KS, partial, g.alpha, g.beta,
-                     g.split < 0 ? g.M : g.split, g.base1, g.out1, g.base2,
-                     g.out2);
+hipError_t launch_gemv_n(const GemvN* jobs, int count, int max_M, hipStream_t s) {
+  if (count <= 0 || max_M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemv_n_partial, dim3((max_M + 63) / 64, GEMV_KS, count),
+                     dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_gemv_n_finish, dim3((max_M + 255) / 256, count), dim3(256),
+                     0, s, jobs);
   return hipGetLastError();
 }
 
-// y[j] = beta*base[j] + alpha * sum_i A[i, j] x[i]; x[i] = x1[i] for
-// i < split, x2[i - split] otherwise.  One wave per column, lanes stride the
-// rows, then a fixed butterfly.  `tri`: A lower triangular (rows i < j
-// skipped).  y must not alias x.
-__global__ __launch_bounds__(256) void k_gemv_t(
-    int M, int N, const double* __restrict__ A, int64_t lda,
-    const double* __restrict__ x1, int split, const double* __restrict__ x2,
-    int tri, double alpha, double beta, const double* base,
-    double* __restrict__ y) {
+// One wave per column j of job blockIdx.y, lanes stride the rows, then a
+// fixed butterfly.  `tri`: A lower triangular (rows i < j skipped).  y must
+// not alias x.
+__global__ __launch_bounds__(256) void k_gemv_t(const GemvT* __restrict__ jobs) {
+  const GemvT g = jobs[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = blockIdx.x * 4 + wave;
-  if (j >= N) return;
-  const double* col = A + (int64_t)j * lda;
-  const int i0 = tri ? (j & ~63) : 0;
+  if (j >= g.N) return;
+  const double* col = g.A + (int64_t)j * g.lda;
+  const int split = g.split < 0 ? g.M : g.split;
+  const int i0 = g.tri ? (j & ~63) : 0;
   double acc = 0.0;
-  for (int i = i0 + lane; i < M; i += 64) {
-    const double xv = (i < split) ? x1[i] : x2[i - split];
+  for (int i = i0 + lane; i < g.M; i += 64) {
+    const double xv = (i < split) ? g.x1[i] : g.x2[i - split];
     acc += col[i] * xv;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[j] = (base ? beta * base[j] : 0.0) + alpha * acc;
+  if (lane == 0) g.y[j] = (g.base ? g.beta * g.base[j] : 0.0) + g.alpha * acc;
 }
 
-hipError_t launch_gemv_t(const GemvT& g, hipStream_t s) {
-  if (g.N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemv_t, dim3((g.N + 3) / 4), dim3(256), 0, s, g.M, g.N,
-                     g.A, g.lda, g.x1, g.split < 0 ? g.M : g.split, g.x2, g.tri,
-                     g.alpha, g.beta, g.base, g.y);
-  return hipGetLastError();
-}
-
-__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
-                       int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
-hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+hipError_t launch_gemv_t(const GemvT* jobs, int count, int max_N, hipStream_t s) {
+  if (count <= 0 || max_N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemv_t, dim3((max_N + 3) / 4, count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

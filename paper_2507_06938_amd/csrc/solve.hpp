@@ -3,10 +3,11 @@
 
 namespace dl {
 
-constexpr int GEMV_MAX_KS = 16;
+constexpr int GEMV_KS = 8;  // k-splits of a column-major matrix-vector product
 
-// out = beta*base + alpha*A*x split into rows [0, split) -> out1/base1 and
-// rows [split, M) -> out2/base2 (split < 0: all rows to out1).
+// out = beta*base + alpha*A*x, rows [0, split) -> out1/base1 and rows
+// [split, M) -> out2/base2 (split < 0: all rows to out1).  `partial` holds
+// GEMV_KS * M doubles private to this job.
 struct GemvN {
   int M, K;
   const double* A;
@@ -19,8 +20,10 @@ struct GemvN {
   double* out1;
   const double* base2;
   double* out2;
+  double* partial;
 };
 
+// y = beta*base + alpha*A^T*x with x = [x1 (rows < split); x2].
 struct GemvT {
   int M, N;
   const double* A;
@@ -34,9 +37,11 @@ struct GemvT {
   double* y;
 };
 
-// partial needs GEMV_MAX_KS * M doubles.
-hipError_t launch_gemv_n(const GemvN& g, double* partial, hipStream_t s);
-hipError_t launch_gemv_t(const GemvT& g, hipStream_t s);
-hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+// Batched launches over job arrays in device memory; max_M / max_N bound the
+// grid over all jobs.
+hipError_t launch_gemv_n(const GemvN* jobs_dev, int count, int max_M,
+                         hipStream_t s);
+hipError_t launch_gemv_t(const GemvT* jobs_dev, int count, int max_N,
+                         hipStream_t s);
 
 }  // namespace dl

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
 
 DL_QP, DL_QC, DL_BOTH = 0, 1, 2
+DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH = 1, 2, 4
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other")
@@ -63,6 +64,8 @@ def lib():
             "dl_model_destroy": (None, [vp]),
             "dl_model_dims": (i32, [vp] + [C.POINTER(i64)] * 5),
             "dl_ws_create": (i32, [vp, i32, C.POINTER(vp)]),
+            "dl_ws_create_batch": (i32, [C.POINTER(vp), i32, i32, C.POINTER(vp)]),
+            "dl_ws_batch": (i32, [vp]),
             "dl_ws_destroy": (None, [vp]),
             "dl_ws_bytes": (C.c_size_t, [vp]),
             "bta_assemble": (i32, [vp, vp, i32, vp]),
@@ -158,14 +161,25 @@ class Model:
 
 
 class Workspace:
-    """Dense BTA workspace of Q_p and Q_c for one model."""
+    """Dense BTA workspace of Q_p and Q_c for one model, or for a batch of
+    instances (a list of models, repeated entries allowed) evaluated
+    together.  Per-instance vectors are packed in instance order."""
 
-    def __init__(self, model: Model, selinv: bool = False):
-        self.model = model
+    def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
+                 graph: bool = False):
+        if isinstance(models, Model):
+            models = [models]
+        self.models = list(models)
+        self.model = self.models[0]
+        flags = ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
+                 | (DL_WS_GRAPH if graph else 0))
         h = C.c_void_p()
-        _check("dl_ws_create",
-               lib().dl_ws_create(model.h, 1 if selinv else 0, C.byref(h)))
+        arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
+        _check("dl_ws_create_batch",
+               lib().dl_ws_create_batch(arr, len(self.models), flags, C.byref(h)))
         self.h = h
+        self.B = len(self.models)
+        self.N_total = sum(m.N for m in self.models)
         self.dev = torch.device("cuda")
 
     @property
@@ -182,7 +196,7 @@ class Workspace:
         self._keep = th
 
     def factor(self, which=DL_BOTH):
-        k = 2 if which == DL_BOTH else 1
+        k = (2 if which == DL_BOTH else 1) * self.B
         ld = torch.empty(k, dtype=torch.float64, device=self.dev)
         info = torch.empty(k, dtype=torch.int64, device=self.dev)
         _check("bta_factor", lib().bta_factor(self.h, which, _ptr(ld), _ptr(info),
@@ -197,13 +211,13 @@ class Workspace:
         return rhs
 
     def mean(self) -> torch.Tensor:
-        out = torch.empty(self.model.N, dtype=torch.float64, device=self.dev)
+        out = torch.empty(self.N_total, dtype=torch.float64, device=self.dev)
         _check("dl_ws_mean", lib().dl_ws_mean(self.h, _ptr(out), _stream()))
         return out
 
     def selinv(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
-            out = torch.empty(self.model.N, dtype=torch.float64, device=self.dev)
+            out = torch.empty(self.N_total, dtype=torch.float64, device=self.dev)
         _check("bta_selinv", lib().bta_selinv(self.h, _ptr(out), _stream()))
         return out
 

@@ -63,7 +63,7 @@ def case(request, D):
     theta = wl.theta + 0.05 * np.sin(np.arange(wl.dim_theta) + 1.0)
     ref = oracle_case(wl, theta)
     model = D.Model.from_workload(wl)
-    ws = D.Workspace(model, selinv=True)
+    ws = D.Workspace(model, selinv=True, keep_qp=True)
     return request.param, wl, theta, ref, model, ws
 
 

@@ -1,0 +1,157 @@
+"""Pins of the oracle's optimiser pieces (Eq. 9, 10) and of its FP64
+surrogate network, against closed forms, textbook special cases and an
+analytic gradient of the Gaussian marginal likelihood."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import bfgs as OB
+from oracle import fobj as OF
+from oracle import mlp as OL
+from oracle import model as OM
+
+
+def test_central_difference_closed_form():
+    """For f = sum x^3 the central difference is 3x^2 + h^2 exactly."""
+    x = np.array([0.3, -1.2, 2.0])
+    h = 1e-2
+    g = OB.central_gradient(lambda v: float(np.sum(v ** 3)), x, h)
+    np.testing.assert_allclose(g, 3 * x ** 2 + h ** 2, rtol=1e-12)
+    pts = OB.fd_stencil(x, h)
+    assert pts.shape == (2 * 3 + 1, 3)   # 2*dim + 1 evaluations
+
+
+def test_bfgs_quadratic_reaches_solution():
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((6, 6))
+    A = B @ B.T + 6 * np.eye(6)
+    b = rng.standard_normal(6)
+    fg = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)
+    x, f, hist = OB.bfgs_minimize(fg, np.zeros(6), max_iter=200, ftol=0, gtol=1e-10)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-7, atol=1e-9)
+
+
+def test_bfgs_rosenbrock_with_fd_gradient():
+    f = lambda v: (1 - v[0]) ** 2 + 100 * (v[1] - v[0] ** 2) ** 2
+    fg = lambda v: (f(v), OB.central_gradient(f, v, 1e-6))
+    x, fx, _ = OB.bfgs_minimize(fg, np.array([-1.2, 1.0]), max_iter=500, ftol=0,
+                                gtol=1e-6)
+    np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-4)
+
+
+def _analytic_grad_univariate(wl, theta):
+    """d f_obj / d theta from f_obj = log p(theta) + log N(y; 0, S),
+    S = A Q_p^-1 A^T + D^-1, written from dS/dtheta_k (dense, tiny)."""
+    lk, phi, ltu, lty = theta
+    kap, rho, tau_u, tau_y = math.exp(lk), math.tanh(phi / 2), math.exp(ltu), math.exp(lty)
+    nx, nt, a = wl.nx, wl.nt, wl.a
+    C = np.eye(nx * nx)
+    G = OM.stiffness_G(nx).toarray()
+    Qs = kap ** 4 * C + 2 * kap ** 2 * G + G @ G
+    dQs = 4 * kap ** 4 * C + 4 * kap ** 2 * G          # d/d log kappa
+    Mr = np.diag(np.r_[1.0, np.full(nt - 2, 1 + rho ** 2), 1.0]) \
+        - rho * (np.eye(nt, k=1) + np.eye(nt, k=-1))
+    dMr = np.diag(np.r_[0.0, np.full(nt - 2, 2 * rho), 0.0]) \
+        - (np.eye(nt, k=1) + np.eye(nt, k=-1))
+    T = Mr / (1 - rho ** 2)
+    dT = 2 * rho / (1 - rho ** 2) ** 2 * Mr + dMr / (1 - rho ** 2)
+    drho = 0.5 * (1 - rho ** 2)
+    nst = nx * nx * nt
+    def border(Z):
+        out = np.zeros((nst + a, nst + a))
+        out[:nst, :nst] = Z
+        return out
+    Qp = border(tau_u * np.kron(T, Qs))
+    Qp[nst:, nst:] = wl.prior_fixed * np.eye(a)
+    dQ = [border(tau_u * np.kron(T, dQs)), border(tau_u * drho * np.kron(dT, Qs)),
+          border(tau_u * np.kron(T, Qs))]
+    A = OM.design_matrix(wl).toarray()
+    y = OM.observations(wl)
+    m = y.shape[0]
+    Qi = np.linalg.inv(Qp)
+    S = A @ Qi @ A.T + np.eye(m) / tau_y
+    Si = np.linalg.inv(S)
+    alpha = Si @ y
+    g = np.zeros(4)
+    for k, dq in enumerate(dQ):
+        dS = -A @ Qi @ dq @ Qi @ A.T
+        g[k] = -0.5 * np.trace(Si @ dS) + 0.5 * alpha @ dS @ alpha
+    dS = -np.eye(m) / tau_y
+    g[3] = -0.5 * np.trace(Si @ dS) + 0.5 * alpha @ dS @ alpha
+    g -= (theta - wl.theta_prior_mean) / wl.theta_prior_sd ** 2
+    return g
+
+
+def test_fd_gradient_of_fobj_matches_analytic():
+    wl = W.scaled("grad", 4, 3, 1, 2, 30, seed=3)
+    theta = wl.theta + np.array([0.1, -0.2, 0.15, -0.05])
+    g_fd = OB.central_gradient(lambda t: OF.fobj(wl, t), theta, 1e-3)
+    g_an = _analytic_grad_univariate(wl, theta)
+    np.testing.assert_allclose(g_fd, g_an, rtol=1e-4, atol=1e-4)
+
+
+# ---- surrogate network -----------------------------------------------------------
+
+def _net(seed=0, sizes=(4, 8, 8, 1)):
+    rng = np.random.default_rng(seed)
+    return [(rng.standard_normal((o, i)) / math.sqrt(i), 0.1 * rng.standard_normal(o))
+            for i, o in zip(sizes[:-1], sizes[1:])]
+
+
+def test_silu_gradient():
+    z = np.linspace(-4, 4, 17)
+    h = 1e-6
+    fd = (OL.silu(z + h) - OL.silu(z - h)) / (2 * h)
+    np.testing.assert_allclose(OL.silu_grad(z), fd, rtol=1e-8, atol=1e-10)
+
+
+def test_backward_matches_finite_differences():
+    params = _net()
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((5, 4))
+    y = rng.standard_normal(5)
+    loss, grads = OL.mse_loss(params, X, y)
+    h = 1e-6
+    for k in range(len(params)):
+        W, b = params[k]
+        for (i, j) in [(0, 0), (W.shape[0] - 1, W.shape[1] - 1), (1 % W.shape[0], 2 % W.shape[1])]:
+            Wp, Wm = W.copy(), W.copy()
+            Wp[i, j] += h
+            Wm[i, j] -= h
+            pp = list(params); pp[k] = (Wp, b)
+            pm = list(params); pm[k] = (Wm, b)
+            fd = (OL.mse_loss(pp, X, y)[0] - OL.mse_loss(pm, X, y)[0]) / (2 * h)
+            assert abs(grads[k][0][i, j] - fd) <= 1e-6 * max(1.0, abs(fd))
+    # input gradient
+    yhat, dX = OL.input_gradient(params, X)
+    for j in range(4):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[:, j] += h
+        Xm[:, j] -= h
+        fd = (OL.forward(params, Xp)[0] - OL.forward(params, Xm)[0]) / (2 * h)
+        np.testing.assert_allclose(dX[:, j], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_bf16_rounding_against_torch():
+    torch = pytest.importorskip("torch")
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.75e-3, 3.1415926, 65504.0,
+                     1e-30, -7.77e20], dtype=np.float32)
+    want = torch.tensor(vals).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(OL.bf16_round(vals), want)
+    assert OL.bf16_round(np.float32(1 + 2 ** -8)) == 1.0        # tie to even
+    assert OL.bf16_round(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments, the bias-corrected first step is -lr g/(|g| + eps)."""
+    params = [(np.array([[1.0, -2.0]]), np.array([0.5]))]
+    grads = [(np.array([[0.3, -4.0]]), np.array([1e-3]))]
+    state = {}
+    OL.adam(params, grads, state, lr=0.01, eps=1e-8)
+    W, b = params[0]
+    np.testing.assert_allclose(W, [[1.0 - 0.01 * 0.3 / (0.3 + 1e-8),
+                                    -2.0 + 0.01 * 4.0 / (4.0 + 1e-8)]], rtol=1e-14)
+    np.testing.assert_allclose(b, [0.5 - 0.01 * 1e-3 / (1e-3 + 1e-8)], rtol=1e-14)
