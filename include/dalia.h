@@ -199,6 +199,46 @@ dl_status dl_dgemm(int32_t transa, int32_t transb, int32_t lower, int64_t M,
 dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
                     double* logdet_dev, int64_t* info_dev, void* stream);
 
+/* Pick the FP64 GEMM tile (64x64 or 128x128 outputs per workgroup) of every
+ * matrix-product launch of the workspace by timing both on the device,
+ * once per distinct launch shape; choices are appended to / read from the
+ * text file cache_path (may be NULL).  Synchronises the stream; the
+ * workspace's matrices must be re-assembled afterwards (fobj_eval always
+ * does).  Call before the first evaluation of a DL_WS_GRAPH workspace. */
+dl_status dl_autotune(dl_ws* ws, const char* cache_path, void* stream);
+dl_status dl_ws_tile_counts(const dl_ws* ws, int64_t* n64, int64_t* n128);
+
+/* ---- surrogate network (learned model of f_obj over theta) ----------------
+ * Multi-layer perceptron sizes[0] -> ... -> sizes[n-1] = 1, SiLU between
+ * layers, linear output.  Parameters live in one FP32 device vector (layer
+ * k: W_k row-major sizes[k+1] x sizes[k], then b_k), with FP32 Adam moments;
+ * every matrix product rounds both operands to bfloat16 and accumulates in
+ * FP32 on the matrix cores.  Batches of up to max_batch rows; inputs are
+ * row-major FP32.  Not thread-safe per network. */
+typedef struct dl_mlp dl_mlp;
+dl_status dl_mlp_create(const int32_t* sizes, int32_t nsizes, int32_t max_batch,
+                        dl_mlp** out);
+void dl_mlp_destroy(dl_mlp* net);
+/* Device pointers of the parameter and gradient vectors (owned by the
+ * network) and their length. */
+dl_status dl_mlp_params(dl_mlp* net, float** params_dev, float** grads_dev,
+                        int64_t* count);
+/* yhat_dev[i] = net(X_dev row i); keeps the activations for mlp_bwd. */
+dl_status mlp_fwd(dl_mlp* net, const float* X_dev, int32_t n, float* yhat_dev,
+                  void* stream);
+/* Back-propagate dy_dev (n, d loss / d yhat) through the last forward:
+ * parameter gradients are overwritten; dX_dev (n x sizes[0], may be NULL)
+ * receives d loss / d X (with dy = 1: the network's input gradient). */
+dl_status mlp_bwd(dl_mlp* net, const float* dy_dev, int32_t n, float* dX_dev,
+                  void* stream);
+/* dy = 2 (yhat - y) / n for the mean squared error of the last forward;
+ * loss_dev[0] = the loss (may be NULL). */
+dl_status mlp_mse_grad(dl_mlp* net, const float* y_dev, int32_t n, float* dy_dev,
+                       float* loss_dev, void* stream);
+/* One Adam step (Kingma & Ba) of all parameters with the current gradients. */
+dl_status mlp_adam(dl_mlp* net, float lr, float beta1, float beta2, float eps,
+                   void* stream);
+
 /* ---- launch profiling ------------------------------------------------------
  * Launch categories of the evaluation path.  With profiling enabled for a
  * category mask, every launch of those categories is bracketed by HIP events

@@ -8,8 +8,9 @@ Multi-layer perceptron  x -> SiLU(W1 x + b1) -> ... -> W_L h + b_L  (linear
 output), SiLU(z) = z sigma(z).  Forward, backward (weight gradients and the
 input gradient d yhat / d x) and the Adam update (Kingma & Ba 2015) written
 out plainly.  With ``bf16=True`` the weights and the layer inputs are
-rounded to bfloat16 (round to nearest even) before each product, as the GPU
-kernels feed the matrix cores, while sums stay in the working precision.
+rounded to bfloat16 (round to nearest even) before each product, and so
+are the back-propagated gradients entering a product, as the GPU kernels
+feed the matrix cores; sums stay in the working precision.
 """
 from __future__ import annotations
 
@@ -64,9 +65,10 @@ def backward(params, cache, dy, bf16: bool = False):
         hin, z = cache[k]
         if k + 1 < L:
             g = g * silu_grad(z)
-        grads[k] = (g.T @ hin, g.sum(axis=0))
+        gb = bf16_round(g) if bf16 else g
+        grads[k] = (gb.T @ hin, g.sum(axis=0))
         Wk = bf16_round(W) if bf16 else W
-        g = g @ Wk
+        g = gb @ Wk
     return grads, g
 
 

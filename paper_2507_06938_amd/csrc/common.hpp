@@ -53,13 +53,15 @@ struct GemmTask {
 constexpr int GEMM_BM = 64;
 constexpr int GEMM_BN = 64;
 
-// Fill tiles_m/n, ntiles, tile_begin; return total tiles.
-int finalize_tasks(GemmTask* t, int n);
+// Fill tiles_m/n, ntiles, tile_begin for square tiles of `tile` (64 or 128)
+// rows; return total tiles.
+int finalize_tasks(GemmTask* t, int n, int tile = 64);
 
 // Launch a batch of tasks already resident in device memory (tasks_dev) with
-// `total_tiles` workgroups.
+// `total_tiles` workgroups of tile x tile outputs (tile 64 or 128, the value
+// the tasks were finalised with).
 hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
-                             int total_tiles, hipStream_t s);
+                             int total_tiles, hipStream_t s, int tile = 64);
 
 // Convenience: copy host tasks to a device buffer, then launch.  Used by
 // the dense ABI entry points and by plan building (never inside timed

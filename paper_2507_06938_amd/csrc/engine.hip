@@ -59,10 +59,25 @@ struct Launch {
   double flops, bytes;
   int off, count;     // into the per-kind descriptor array
   int gx, gy, gz;     // grid bounds (max over merged steps)
+  int tile;           // GEMM output tile (64 or 128)
 };
 
+// Default GEMM tile for a launch (before any measured choice): 128x128 when
+// every task is large and the launch still has >= 200 such tiles to spread
+// over the 256 compute units, else 64x64.
+static int default_tile(std::vector<GemmTask>& t, int off, int count) {
+  bool big = true;
+  for (int i = 0; i < count; ++i) {
+    const GemmTask& g = t[off + i];
+    if (g.M < 512 || g.N < 512 || g.K < 256) big = false;
+  }
+  if (!big) return 64;
+  const int n128 = finalize_tasks(t.data() + off, count, 128);
+  return n128 >= 200 ? 128 : 64;
+}
+
 struct Plan {
-  std::vector<Launch> launches;
+  std::vector<int> idx;  // indices into the workspace's launch table
 };
 
 // Host-side descriptor arrays (uploaded once per workspace).
@@ -101,13 +116,15 @@ static uint64_t K(uint64_t major, uint64_t group, uint64_t j = 0, uint64_t sub =
 
 // Merge sequences: steps with equal keys and kinds form one launch; keys are
 // visited in increasing order, so each sequence keeps its own order.
-static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D, Plan& P) {
+static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
+                  std::vector<Launch>& table, Plan& P) {
   std::map<std::pair<uint64_t, int>, std::vector<const Step*>> groups;
   for (const auto& sq : seqs)
     for (const Step& st : sq) groups[{st.key, (int)st.kind}].push_back(&st);
   for (auto& kv : groups) {
     const std::vector<const Step*>& g = kv.second;
     Launch L{};
+    L.tile = 64;
     L.kind = (OpKind)kv.first.second;
     L.cat = g.front()->cat;
     L.flops = L.bytes = 0.0;
@@ -124,7 +141,8 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D, Plan& P)
         L.off = (int)D.gemm.size();
         for (const Step* st : g) D.gemm.insert(D.gemm.end(), st->gemm.begin(), st->gemm.end());
         L.count = (int)D.gemm.size() - L.off;
-        L.gx = finalize_tasks(D.gemm.data() + L.off, L.count);
+        L.tile = default_tile(D.gemm, L.off, L.count);
+        L.gx = finalize_tasks(D.gemm.data() + L.off, L.count, L.tile);
         if (L.gx == 0) continue;
         break;
       }
@@ -147,7 +165,8 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D, Plan& P)
 #undef PUSH
       default: continue;
     }
-    P.launches.push_back(L);
+    P.idx.push_back((int)table.size());
+    table.push_back(L);
   }
 }
 
@@ -316,6 +335,7 @@ struct dl_ws {
   int64_t* info_all = nullptr;   // [B x 2]
   Descs H;
   DevDescs Dd;
+  std::vector<Launch> table;
   Plan theta_p, asm_p[3], fac_p[3], solve_p, selinv_p, post_p, eval_p;
   bool assembled[2] = {false, false}, factored[2] = {false, false};
   bool solved = false;
@@ -348,9 +368,19 @@ static void prof_end(dl_ws* W, int k, double flops, double bytes, hipStream_t s)
   W->prof_bytes[k] = bytes;
 }
 
+static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s);
+
 static hipError_t run(dl_ws* W, const Plan& P, hipStream_t s) {
+  for (int i : P.idx) {
+    hipError_t e = run_launch(W, W->table[i], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
   const DevDescs& d = W->Dd;
-  for (const Launch& L : P.launches) {
+  {
     int kk = DL_KERNEL_OTHER;
     if (L.kind == OP_GEMM) kk = DL_KERNEL_GEMM;
     else if (L.kind == OP_POTRF) kk = DL_KERNEL_POTRF_TILE;
@@ -359,7 +389,7 @@ static hipError_t run(dl_ws* W, const Plan& P, hipStream_t s) {
     const int pk = prof_begin(W, L.cat, kk, s);
     hipError_t e = hipSuccess;
     switch (L.kind) {
-      case OP_GEMM: e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s); break;
+      case OP_GEMM: e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile); break;
       case OP_POTRF: e = launch_potrf_tiles(d.potrf + L.off, L.count, s); break;
       case OP_MISC: e = launch_misc(d.misc + L.off, L.count, s); break;
       case OP_GEMV_N: e = launch_gemv_n(d.gn + L.off, L.count, L.gx, s); break;
@@ -376,9 +406,8 @@ static hipError_t run(dl_ws* W, const Plan& P, hipStream_t s) {
       default: break;
     }
     prof_end(W, pk, L.flops, L.bytes, s);
-    if (e != hipSuccess) return e;
+    return e;
   }
-  return hipSuccess;
 }
 
 // ---- plan construction -----------------------------------------------------------------
@@ -731,7 +760,7 @@ static void seq_post(dl_ws* W, Inst& I, int k, std::vector<Step>& q) {
 }
 
 static void append(Plan& dst, const Plan& src) {
-  dst.launches.insert(dst.launches.end(), src.launches.begin(), src.launches.end());
+  dst.idx.insert(dst.idx.end(), src.idx.begin(), src.idx.end());
 }
 
 static dl_status build_plans(dl_ws* W) {
@@ -745,7 +774,7 @@ static dl_status build_plans(dl_ws* W) {
       seqs.emplace_back();
       seq_assemble(W, I, wh != 1, wh != 0, seqs.back());
     }
-    merge(seqs, H, W->asm_p[wh]);
+    merge(seqs, H, W->table, W->asm_p[wh]);
   }
   for (int wh = 0; wh < 3; ++wh) {
     std::vector<std::vector<Step>> seqs;
@@ -755,7 +784,7 @@ static dl_status build_plans(dl_ws* W) {
         seqs.emplace_back();
         seq_factor(W, I, w, nt_max, seqs.back());
       }
-    merge(seqs, H, W->fac_p[wh]);
+    merge(seqs, H, W->table, W->fac_p[wh]);
   }
   {
     std::vector<std::vector<Step>> seqs;
@@ -767,7 +796,7 @@ static dl_status build_plans(dl_ws* W) {
       for (auto& st : s2) st.key += K(1, 0);  // after the copy
       seqs.back().insert(seqs.back().end(), s2.begin(), s2.end());
     }
-    merge(seqs, H, W->solve_p);
+    merge(seqs, H, W->table, W->solve_p);
   }
   {
     std::vector<std::vector<Step>> seqs;
@@ -775,7 +804,7 @@ static dl_status build_plans(dl_ws* W) {
       seqs.emplace_back();
       seq_post(W, W->inst[k], (int)k, seqs.back());
     }
-    merge(seqs, H, W->post_p);
+    merge(seqs, H, W->table, W->post_p);
   }
   if (W->sel) {
     std::vector<std::vector<Step>> seqs;
@@ -783,9 +812,9 @@ static dl_status build_plans(dl_ws* W) {
       seqs.emplace_back();
       seq_selinv(W, I, nt_max, seqs.back());
     }
-    merge(seqs, H, W->selinv_p);
+    merge(seqs, H, W->table, W->selinv_p);
   }
-  W->eval_p.launches.clear();
+  W->eval_p.idx.clear();
   append(W->eval_p, W->asm_p[2]);
   append(W->eval_p, W->fac_p[2]);
   append(W->eval_p, W->solve_p);
@@ -1199,4 +1228,101 @@ extern "C" dl_status dl_ws_profile_end(dl_ws* W, double* ms, int64_t* launches,
   }
   prof_free(W);
   return st;
+}
+
+// ---- tile autotuner --------------------------------------------------------------------
+//
+// Every GEMM launch of the workspace's plans has a signature (category,
+// number of tasks, shape and flags of its tasks).  For each signature both
+// tile variants (64x64, 128x128) are timed in isolation with HIP events (the
+// launch reads and writes the workspace's own buffers; their contents are
+// rebuilt by the next assembly) and the faster one is kept for every launch
+// of that signature.  Choices are cached in a text file, one line per
+// signature, so later workspaces of the same shapes skip the measurement.
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+
+static std::string gemm_signature(const dl_ws* W, const Launch& L) {
+  std::ostringstream o;
+  o << "gfx950 gemm cat" << L.cat << " n" << L.count;
+  for (int i = 0; i < L.count && i < 8; ++i) {
+    const GemmTask& t = W->H.gemm[L.off + i];
+    o << " " << t.M << "x" << t.N << "x" << t.K << "f" << (t.flags & ~F_BETA0);
+  }
+  return o.str();
+}
+
+static dl_status retile(dl_ws* W, Launch& L, int tile) {
+  L.tile = tile;
+  L.gx = finalize_tasks(W->H.gemm.data() + L.off, L.count, tile);
+  DL_HIP_CHECK(hipMemcpy(W->Dd.gemm + L.off, W->H.gemm.data() + L.off,
+                         sizeof(GemmTask) * L.count, hipMemcpyHostToDevice));
+  return DL_OK;
+}
+
+extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream) {
+  if (!W) return DL_EINVAL;
+  if (W->graph_exec) return DL_ESTATE;  // tune before the first graph capture
+  hipStream_t s = (hipStream_t)stream;
+  std::unordered_map<std::string, int> best;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t sp = line.rfind(' ');
+      if (sp == std::string::npos) continue;
+      best[line.substr(0, sp)] = atoi(line.c_str() + sp + 1);
+    }
+  }
+  std::vector<std::string> fresh;
+  hipEvent_t e0, e1;
+  DL_HIP_CHECK(hipEventCreate(&e0));
+  DL_HIP_CHECK(hipEventCreate(&e1));
+  dl_status st = DL_OK;
+  for (Launch& L : W->table) {
+    if (L.kind != OP_GEMM || st != DL_OK) continue;
+    const std::string sig = gemm_signature(W, L);
+    auto it = best.find(sig);
+    if (it == best.end()) {
+      float tbest = 1e30f;
+      int choice = 64;
+      for (int tile : {64, 128}) {
+        if ((st = retile(W, L, tile)) != DL_OK) break;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          (void)hipEventRecord(e0, s);
+          (void)run_launch(W, L, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          tmin = std::min(tmin, ms);
+        }
+        if (tmin < tbest) { tbest = tmin; choice = tile; }
+      }
+      it = best.emplace(sig, choice).first;
+      fresh.push_back(sig);
+    }
+    if (st == DL_OK && L.tile != it->second) st = retile(W, L, it->second);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == DL_OK && cache_path && !fresh.empty()) {
+    std::ofstream out(cache_path, std::ios::app);
+    for (const auto& sig : fresh) out << sig << " " << best[sig] << "\n";
+  }
+  return st;
+}
+
+// Number of GEMM launches of the workspace using each tile size.
+extern "C" dl_status dl_ws_tile_counts(const dl_ws* W, int64_t* n64, int64_t* n128) {
+  if (!W) return DL_EINVAL;
+  int64_t a = 0, b = 0;
+  for (const Launch& L : W->table)
+    if (L.kind == OP_GEMM) (L.tile == 128 ? b : a)++;
+  if (n64) *n64 = a;
+  if (n128) *n128 = b;
+  return DL_OK;
 }

@@ -80,6 +80,15 @@ def lib():
             "dl_dpotrf": (i32, [i64, vp, i64, i32, vp, vp, vp]),
             "dl_status_string": (C.c_char_p, [i32]),
             "dl_ws_profile_begin": (i32, [vp, i32, i32]),
+            "dl_autotune": (i32, [vp, C.c_char_p, vp]),
+            "dl_ws_tile_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+            "dl_mlp_create": (i32, [vp, i32, i32, C.POINTER(vp)]),
+            "dl_mlp_destroy": (None, [vp]),
+            "dl_mlp_params": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)]),
+            "mlp_fwd": (i32, [vp, vp, i32, vp, vp]),
+            "mlp_bwd": (i32, [vp, vp, i32, vp, vp]),
+            "mlp_mse_grad": (i32, [vp, vp, i32, vp, vp, vp]),
+            "mlp_adam": (i32, [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
             "dl_ws_profile_end": (i32, [vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -240,6 +249,14 @@ class Workspace:
                                             _ptr(parts), _ptr(info), _stream()))
         return f, parts, info
 
+    def autotune(self, cache_path: Optional[str] = None):
+        """Measure and fix the GEMM tile of every launch (see dl_autotune)."""
+        p = cache_path.encode() if cache_path else None
+        _check("dl_autotune", lib().dl_autotune(self.h, p, _stream()))
+        a, b = C.c_int64(), C.c_int64()
+        _check("dl_ws_tile_counts", lib().dl_ws_tile_counts(self.h, C.byref(a), C.byref(b)))
+        return {"tile64": a.value, "tile128": b.value}
+
     def profile_begin(self, categories=CATEGORIES, max_launches=200000,
                       by_kernel=False):
         """Bracket launches of `categories` with HIP events (aggregated by
@@ -317,3 +334,79 @@ def dpotrf(A: torch.Tensor, inverse: bool = False):
 def fortran(x: torch.Tensor) -> torch.Tensor:
     """Column-major copy of a 2-D tensor (same logical values)."""
     return x.T.contiguous().T
+
+
+class MLP:
+    """Surrogate network on the device (FP32 master weights, BF16 matrix
+    products).  Parameters are exposed as a flat torch view."""
+
+    def __init__(self, sizes=(15, 256, 256, 256, 1), max_batch=4096):
+        L = lib()
+        arr = (C.c_int32 * len(sizes))(*sizes)
+        h = C.c_void_p()
+        _check("dl_mlp_create", L.dl_mlp_create(arr, len(sizes), int(max_batch),
+                                                C.byref(h)))
+        self.h = h
+        self.sizes = tuple(sizes)
+        self.max_batch = max_batch
+        pw, pg, cnt = C.c_void_p(), C.c_void_p(), C.c_int64()
+        _check("dl_mlp_params", L.dl_mlp_params(h, C.byref(pw), C.byref(pg), C.byref(cnt)))
+        self.nparam = cnt.value
+        self._pw, self._pg = pw.value, pg.value
+        # torch views over the library-owned buffers (no copy)
+        self.params = _device_view(self._pw, self.nparam, torch.float32)
+        self.grads = _device_view(self._pg, self.nparam, torch.float32)
+
+    def layers(self):
+        """[(W, b)] views into the parameter vector."""
+        out, off = [], 0
+        for i, o in zip(self.sizes[:-1], self.sizes[1:]):
+            W = self.params[off:off + i * o].view(o, i)
+            off += i * o
+            b = self.params[off:off + o]
+            off += o
+            out.append((W, b))
+        return out
+
+    def forward(self, X: torch.Tensor, out: Optional[torch.Tensor] = None):
+        n = X.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check("mlp_fwd", lib().mlp_fwd(self.h, _ptr(X), n, _ptr(out), _stream()))
+        return out
+
+    def backward(self, dy: torch.Tensor, want_dx: bool = False):
+        n = dy.shape[0]
+        dX = torch.empty((n, self.sizes[0]), dtype=torch.float32,
+                         device=dy.device) if want_dx else None
+        _check("mlp_bwd", lib().mlp_bwd(self.h, _ptr(dy), n, _ptr(dX), _stream()))
+        return dX
+
+    def mse_grad(self, y: torch.Tensor):
+        n = y.shape[0]
+        dy = torch.empty(n, dtype=torch.float32, device=y.device)
+        loss = torch.empty(1, dtype=torch.float32, device=y.device)
+        _check("mlp_mse_grad", lib().mlp_mse_grad(self.h, _ptr(y), n, _ptr(dy),
+                                                  _ptr(loss), _stream()))
+        return dy, loss
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        _check("mlp_adam", lib().mlp_adam(self.h, lr, b1, b2, eps, _stream()))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            torch.cuda.synchronize()
+            _lib.dl_mlp_destroy(self.h)
+            self.h = None
+
+
+def _device_view(ptr: int, n: int, dtype) -> torch.Tensor:
+    """A torch tensor over library-owned device memory (no ownership)."""
+    class _Holder:
+        pass
+    h = _Holder()
+    itemsize = torch.tensor([], dtype=dtype).element_size()
+    h.__cuda_array_interface__ = {
+        "shape": (n,), "typestr": "<f4" if dtype == torch.float32 else "<f8",
+        "data": (ptr, False), "version": 3, "strides": None}
+    return torch.as_tensor(h, device="cuda")

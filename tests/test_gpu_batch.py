@@ -121,3 +121,26 @@ def test_graph_replays_match_eager(D):
         assert np.array_equal(fg.cpu().numpy(), fe.cpu().numpy()), rep
         assert np.array_equal(pg.cpu().numpy(), pe.cpu().numpy()), rep
         del x
+
+
+def test_autotuned_tiles_give_identical_results(D, tmp_path):
+    """Both GEMM tile sizes sum each output over the same k sequence (extra
+    terms are exact zeros), so a tuned workspace reproduces the default one
+    bit for bit; the cache file is written and reused."""
+    wl = W.scaled("tune", 12, 4, 1, 2, 200, seed=9)
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True)
+    f0, p0, _ = ws.fobj(wl.theta)
+    v0 = ws.selinv().cpu().numpy()
+    cache = str(tmp_path / "tiles.txt")
+    counts = ws.autotune(cache)
+    assert counts["tile64"] + counts["tile128"] > 0
+    f1, p1, _ = ws.fobj(wl.theta)
+    v1 = ws.selinv().cpu().numpy()
+    torch.cuda.synchronize()
+    assert f0.item() == f1.item()
+    assert np.array_equal(v0, v1)
+    lines = open(cache).read().splitlines()
+    assert lines and all(l.rsplit(" ", 1)[1] in ("64", "128") for l in lines)
+    ws2 = D.Workspace(model, selinv=True)
+    assert ws2.autotune(cache) == counts   # read back from the cache
