@@ -84,7 +84,7 @@ typedef struct dl_fobj_parts {
   double quad_obs;   /* (y - A mu)^T D (y - A mu)                      */
   double log_prior;  /* log p(theta)                                   */
   double log_lik_const; /* sum_j m_j/2 log tau_j - m/2 log(2 pi)      */
-  double reserved;
+  double rel_residual;  /* |A^T D y - Q_c mu| / |A^T D y| of the final mu */
 } dl_fobj_parts;
 
 /* Number of hyperparameters: 4 for nv = 1, 4*nv + nv(nv-1)/2 otherwise.
@@ -111,8 +111,17 @@ enum {
   DL_WS_KEEP_QP = 2,  /* store Q_p in full (inspection); by default Q_p is
                          assembled just in time into a ring of blocks, as
                          only its log-determinant is needed                */
-  DL_WS_GRAPH = 4     /* fobj_eval replays one captured HIP graph          */
+  DL_WS_GRAPH = 4,    /* fobj_eval replays one captured HIP graph          */
+  DL_WS_MIXED = 8     /* mixed precision: the off-diagonal blocks [B_t; R_t]
+                         of Q_c (and Q_p) are stored in FP32 and their
+                         TRSM / SYRK / GEMM products run on FP32 matrix
+                         cores (FP32 accumulation, subtracted into FP64
+                         diagonal blocks and tips); diagonal-block Cholesky,
+                         inverses and log-determinants stay FP64; the mean
+                         is refined in FP64 against the sparse Q_c
+                         (DL_REFINE_STEPS steps)                           */
 };
+#define DL_REFINE_STEPS 3
 
 /* Allocate the dense BTA workspace for Q_p and Q_c of `model`.  All device
  * memory of the evaluation path is allocated here. */

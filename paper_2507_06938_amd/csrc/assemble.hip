@@ -159,15 +159,20 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
   double* Dc = o.Dc ? o.Dc + tl * o.dc_stride + (int64_t)c * bp : nullptr;
   double* BRc = o.BRc ? o.BRc + tl * o.brc_stride + (int64_t)c * ldbr : nullptr;
 
+  const bool b32 = o.b32 != 0;
+  float* Bp32 = o.Bp ? (float*)o.Bp + tl * o.bp_stride + (int64_t)c * bp : nullptr;
+  float* BRc32 = o.BRc ? (float*)o.BRc + tl * o.brc_stride + (int64_t)c * ldbr : nullptr;
   if (c >= m.b) {
     for (int r = tid; r < bp; r += 256) {
       const double v = (r == c) ? 1.0 : 0.0;
       if (Dp) Dp[r] = v;
-      if (Bp) Bp[r] = 0.0;
+      if (Bp) { if (b32) Bp32[r] = 0.f; else Bp[r] = 0.0; }
       if (Dc) Dc[r] = v;
     }
     if (BRc)
-      for (int r = tid; r < bp + ap; r += 256) BRc[r] = 0.0;
+      for (int r = tid; r < bp + ap; r += 256) {
+        if (b32) BRc32[r] = 0.f; else BRc[r] = 0.0;
+      }
     if (Dc && tid == 0) o.rhs[(int64_t)t * bp + c] = 0.0;
     return;
   }
@@ -194,7 +199,9 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
   if (Dp)
     for (int r = tid; r < bp; r += 256) Dp[r] = (r >= c) ? colD[r] : 0.0;
   if (Bp)
-    for (int r = tid; r < bp; r += 256) Bp[r] = colB[r];
+    for (int r = tid; r < bp; r += 256) {
+      if (b32) Bp32[r] = (float)colB[r]; else Bp[r] = colB[r];
+    }
   if (!Dc) return;
   __syncthreads();
   if (tid == 0) {
@@ -219,9 +226,11 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
   __syncthreads();
   for (int r = tid; r < bp; r += 256) {
     Dc[r] = (r >= c) ? colD[r] : 0.0;
-    BRc[r] = colB[r];
+    if (b32) BRc32[r] = (float)colB[r]; else BRc[r] = colB[r];
   }
-  for (int r = tid; r < ap; r += 256) BRc[bp + r] = colR[r];
+  for (int r = tid; r < ap; r += 256) {
+    if (b32) BRc32[bp + r] = (float)colR[r]; else BRc[bp + r] = colR[r];
+  }
   if (tid == 0) o.rhs[(int64_t)t * bp + c] = rhs_s;
 }
 
@@ -460,7 +469,7 @@ __global__ void k_combine(const CombineJob* __restrict__ jobs) {
     parts->quad_obs = quad2[1];
     parts->log_prior = lp;
     parts->log_lik_const = llc;
-    parts->reserved = 0.0;
+    parts->rel_residual = C.rnorm ? sqrt(C.rnorm[0] / (C.rnorm[1] > 0.0 ? C.rnorm[1] : 1.0)) : 0.0;
   }
   if (info_out) {
     info_out[0] = info2[0];
@@ -512,6 +521,136 @@ hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
 hipError_t launch_unpack(const ModelDev& m, const double* in, double* padded,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_unpack, dim3(1024), dim3(256), 0, s, m, in, padded);
+  return hipGetLastError();
+}
+
+// ---- FP64 residual of the conditional system (iterative refinement) ------------
+//
+// out = rhs - Q_c v with Q_c = Q_p + A^T D A, Q_p applied from its stencil as
+// in the quadratic form above and A^T D A as (A v) per observation row
+// followed by a gather over the rows touching each node (no atomics).
+__global__ __launch_bounds__(256) void k_res_av(const ResJob* __restrict__ jobs) {
+  const ResJob R = jobs[blockIdx.y];
+  const ModelDev& m = *R.m;
+  const int ns = m.ns, nr = m.nr, bp = m.bp;
+  for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < m.m_total;
+       row += (int64_t)gridDim.x * 256) {
+    int j = 0;
+    while (j + 1 < m.nv && row >= m.m_off[j + 1]) ++j;
+    const int t = m.obs_t[row];
+    const double* x = R.v + (int64_t)t * bp + j * ns;
+    double a = 0.0;
+    for (int q = 0; q < 3; ++q) a += m.obs_w[row * 3 + q] * x[m.obs_nodes[row * 3 + q]];
+    const double* xf = R.v + (int64_t)m.nt * bp + j * nr;
+    for (int r = 0; r < nr; ++r) a += m.obs_x[row * nr + r] * xf[r];
+    R.av[row] = R.coef[C_TAU + j] * a;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_res_rows(const ResJob* __restrict__ jobs) {
+  __shared__ double sh[256];
+  const ResJob R = jobs[blockIdx.y];
+  const ModelDev& m = *R.m;
+  const double* __restrict__ coef = R.coef;
+  const int ns = m.ns, nv = m.nv, bp = m.bp;
+  const int64_t nrows = (int64_t)m.nt * m.b;
+  double acc_r = 0.0, acc_b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nrows;
+       i += (int64_t)gridDim.x * 256) {
+    const int t = (int)(i / m.b);
+    const int rl = (int)(i - (int64_t)t * m.b);
+    const int k = rl / ns, sp = rl - k * ns;
+    const int tt = (m.nt == 1) ? 2 : ((t == 0 || t == m.nt - 1) ? 0 : 1);
+    double q = 0.0;
+    for (int dt = -1; dt <= 1; ++dt) {
+      const int t2 = t + dt;
+      if (t2 < 0 || t2 >= m.nt) continue;
+      for (int j = 0; j < nv; ++j) {
+        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * 3
+                                     : coef + C_B + (k * 3 + j) * 3;
+        const double* x = R.v + (int64_t)t2 * bp + j * ns;
+        for (int e = m.sp_ptr[sp]; e < m.sp_ptr[sp + 1]; ++e) {
+          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e];
+          q += qv * x[m.sp_col[e]];
+        }
+      }
+    }
+    const int64_t key = ((int64_t)k * m.nt + t) * ns + sp;
+    for (int64_t p = m.no_ptr[key]; p < m.no_ptr[key + 1]; ++p)
+      q += m.obs_w[(int64_t)m.no_row[p] * 3 + m.no_q[p]] * R.av[m.no_row[p]];
+    const int64_t o = (int64_t)t * bp + rl;
+    const double res = R.rhs[o] - q;
+    R.out[o] = res;
+    acc_r += res * res;
+    acc_b += R.rhs[o] * R.rhs[o];
+  }
+  const double s1 = blk_sum(acc_r, sh);
+  const double s2 = blk_sum(acc_b, sh);
+  if (threadIdx.x == 0) {
+    R.partial[blockIdx.x] = s1;
+    R.partial[QF_BLOCKS + blockIdx.x] = s2;
+  }
+}
+
+// fixed-effect rows (one workgroup per (response, effect)) and the final
+// norms; padded entries of out are zero
+__global__ __launch_bounds__(256) void k_res_tip(const ResJob* __restrict__ jobs) {
+  __shared__ double sh[256];
+  const ResJob R = jobs[blockIdx.y];
+  const ModelDev& m = *R.m;
+  const int nr = m.nr, nv = m.nv;
+  const int e = blockIdx.x;
+  const int64_t base = (int64_t)m.nt * m.bp;
+  if (e < nv * nr) {
+    const int j = e / nr, r = e % nr;
+    double acc = 0.0;
+    for (int64_t row = m.m_off[j] + threadIdx.x; row < m.m_off[j + 1]; row += 256)
+      acc += m.obs_x[row * nr + r] * R.av[row];
+    const double s = blk_sum(acc, sh);
+    if (threadIdx.x == 0) {
+      const int64_t o = base + e;
+      const double q = s + m.prior_fixed * R.v[o];
+      R.out[o] = R.rhs[o] - q;
+    }
+    return;
+  }
+  if (e == nv * nr) {
+    // padding rows and columns of the blocks carry zeros
+    for (int t = 0; t < m.nt; ++t)
+      for (int i = m.b + threadIdx.x; i < m.bp; i += 256) R.out[(int64_t)t * m.bp + i] = 0.0;
+    for (int i = m.a + threadIdx.x; i < m.ap; i += 256) R.out[base + i] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_res_final(const ResJob* __restrict__ jobs) {
+  __shared__ double sh[256];
+  const ResJob R = jobs[blockIdx.x];
+  const ModelDev& m = *R.m;
+  double a1 = 0.0, a2 = 0.0;
+  for (int i = threadIdx.x; i < QF_BLOCKS; i += 256) {
+    a1 += R.partial[i];
+    a2 += R.partial[QF_BLOCKS + i];
+  }
+  const int64_t base = (int64_t)m.nt * m.bp;
+  if (threadIdx.x == 0)
+    for (int f = 0; f < m.a; ++f) {
+      a1 += R.out[base + f] * R.out[base + f];
+      a2 += R.rhs[base + f] * R.rhs[base + f];
+    }
+  const double s1 = blk_sum(a1, sh);
+  const double s2 = blk_sum(a2, sh);
+  if (threadIdx.x == 0) {
+    R.norms[0] = s1;
+    R.norms[1] = s2;
+  }
+}
+
+hipError_t launch_residual(const ResJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_res_av, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_res_rows, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_res_tip, dim3(3 * 64 + 1, count), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(k_res_final, dim3(count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -36,6 +36,10 @@ enum : int {
   F_KLO_ROW = 32,
   F_KHI_ROW = 64,
   F_BETA0 = 128,   // ignore beta and the previous C (C may hold NaN)
+  // FP32 kernel only: operand stored in FP64 / output accumulated in FP64
+  F_A64 = 256,
+  F_B64 = 512,
+  F_C64 = 1024,
 };
 
 struct GemmTask {
@@ -62,6 +66,9 @@ int finalize_tasks(GemmTask* t, int n, int tile = 64);
 // the tasks were finalised with).
 hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
                              int total_tiles, hipStream_t s, int tile = 64);
+// FP32 MFMA variant; A/B/C pointers are float* unless F_A64/F_B64/F_C64.
+hipError_t launch_gemm32_tasks(const GemmTask* tasks_dev, int ntask,
+                               int total_tiles, hipStream_t s, int tile = 64);
 
 // Convenience: copy host tasks to a device buffer, then launch.  Used by
 // the dense ABI entry points and by plan building (never inside timed
@@ -93,7 +100,8 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
 
 // ---- small batched element-wise jobs ------------------------------------------
 enum : int { MJ_FILL = 0, MJ_COPY = 1, MJ_ZERO_I64 = 2, MJ_DIAG = 3,
-             MJ_COPY2D = 4, MJ_ZERO_UPPER_TILES = 5 };
+             MJ_COPY2D = 4, MJ_ZERO_UPPER_TILES = 5, MJ_COPY2D_F32 = 6,
+             MJ_AXPY = 7 };
 struct MiscJob {
   int32_t kind, rows, cols, pad_;
   double* dst;

@@ -141,6 +141,18 @@ __global__ __launch_bounds__(256) void k_misc(const MiscJob* __restrict__ jobs) 
       }
       break;
     }
+    case MJ_COPY2D_F32: {
+      const float* src32 = (const float*)J.src;
+      const int64_t tot = (int64_t)J.rows * J.cols;
+      for (int64_t i = i0; i < tot; i += stride) {
+        const int64_t r = i % J.rows, c = i / J.rows;
+        J.dst[r + c * J.ldd] = (double)src32[r + c * J.lds];
+      }
+      break;
+    }
+    case MJ_AXPY:
+      for (int64_t i = i0; i < J.n; i += stride) J.dst[i] += J.src[i];
+      break;
     case MJ_ZERO_UPPER_TILES: {
       const int64_t tot = (int64_t)J.rows * J.rows;
       for (int64_t i = i0; i < tot; i += stride) {

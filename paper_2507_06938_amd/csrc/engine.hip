@@ -29,7 +29,8 @@ namespace dl {
 
 enum OpKind : int {
   OP_GEMM, OP_POTRF, OP_MISC, OP_GEMV_N, OP_GEMV_T, OP_SUM, OP_FINISH,
-  OP_ASM_COLS, OP_ASM_TIPS, OP_THETA, OP_QUAD, OP_COMBINE, OP_NKIND
+  OP_ASM_COLS, OP_ASM_TIPS, OP_THETA, OP_QUAD, OP_COMBINE, OP_GEMM32, OP_RES,
+  OP_NKIND
 };
 
 // One step of one sequence (before merging).
@@ -49,6 +50,7 @@ struct Step {
   ThetaJob th{};
   QuadJob quad{};
   CombineJob comb{};
+  ResJob res{};
   int gx = 0, gy = 0, gz = 0;  // grid bounds contributed by this step
 };
 
@@ -93,6 +95,7 @@ struct Descs {
   std::vector<ThetaJob> th;
   std::vector<QuadJob> quad;
   std::vector<CombineJob> comb;
+  std::vector<ResJob> res;
 };
 
 struct DevDescs {
@@ -107,6 +110,7 @@ struct DevDescs {
   ThetaJob* th = nullptr;
   QuadJob* quad = nullptr;
   CombineJob* comb = nullptr;
+  ResJob* res = nullptr;
 };
 
 // key = (((major * 16 + group) * 256 + j) * 4 + sub)
@@ -137,7 +141,8 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
       L.gz = std::max(L.gz, st->gz);
     }
     switch (L.kind) {
-      case OP_GEMM: {
+      case OP_GEMM:
+      case OP_GEMM32: {
         L.off = (int)D.gemm.size();
         for (const Step* st : g) D.gemm.insert(D.gemm.end(), st->gemm.begin(), st->gemm.end());
         L.count = (int)D.gemm.size() - L.off;
@@ -162,6 +167,7 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
       case OP_THETA: PUSH(th, th)
       case OP_QUAD: PUSH(quad, quad)
       case OP_COMBINE: PUSH(comb, comb)
+      case OP_RES: PUSH(res, res)
 #undef PUSH
       default: continue;
     }
@@ -179,6 +185,22 @@ static GemmTask mk(const double* A, int64_t lda, const double* B, int64_t ldb,
   t.M = M; t.N = N; t.K = K_; t.flags = flags;
   t.alpha = alpha; t.beta = beta;
   return t;
+}
+
+// Pointer `elems` elements past `base` for storage of elem_bytes per element
+// (FP32 blocks of mixed-precision workspaces travel in double* fields).
+static double* eoff(void* base, int64_t elems, int elem_bytes) {
+  return (double*)((char*)base + elems * elem_bytes);
+}
+
+static Step gemm32_step(uint64_t key, int cat, double flops, std::vector<GemmTask> ts) {
+  Step s;
+  s.key = key;
+  s.kind = OP_GEMM32;
+  s.cat = cat;
+  s.flops = flops;
+  s.gemm = std::move(ts);
+  return s;
 }
 
 static Step gemm_step(uint64_t key, int cat, double flops, std::vector<GemmTask> ts) {
@@ -320,6 +342,9 @@ struct Inst {
   // selected inversion
   double *WV = nullptr, *Y = nullptr, *XC[2] = {nullptr, nullptr}, *selout = nullptr;
   double* GPp = nullptr;
+  bool mixed = false;       // [B_t; R_t] in FP32, their products on FP32 MFMA
+  int eb = 8;               // bytes per element of the [B_t; R_t] storage
+  double *mu_acc = nullptr, *av = nullptr, *rpart = nullptr, *rnorm = nullptr;
 };
 
 struct dl_ws {
@@ -327,7 +352,7 @@ struct dl_ws {
   std::vector<void*> allocs;
   size_t bytes = 0;
   int flags = 0;
-  bool sel = false, keep_qp = false;
+  bool sel = false, keep_qp = false, mixed = false;
   int dim_total = 0;
   double* theta_all = nullptr;   // packed theta of all instances
   double* f_all = nullptr;       // [B]
@@ -336,7 +361,7 @@ struct dl_ws {
   Descs H;
   DevDescs Dd;
   std::vector<Launch> table;
-  Plan theta_p, asm_p[3], fac_p[3], solve_p, selinv_p, post_p, eval_p;
+  Plan theta_p, asm_p[3], fac_p[3], solve_p, refine_p, selinv_p, post_p, eval_p;
   bool assembled[2] = {false, false}, factored[2] = {false, false};
   bool solved = false;
   int max_shmem = 0;
@@ -382,7 +407,7 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
   const DevDescs& d = W->Dd;
   {
     int kk = DL_KERNEL_OTHER;
-    if (L.kind == OP_GEMM) kk = DL_KERNEL_GEMM;
+    if (L.kind == OP_GEMM || L.kind == OP_GEMM32) kk = DL_KERNEL_GEMM;
     else if (L.kind == OP_POTRF) kk = DL_KERNEL_POTRF_TILE;
     else if (L.kind == OP_GEMV_N || L.kind == OP_GEMV_T) kk = DL_KERNEL_GEMV;
     else if (L.kind == OP_ASM_COLS) kk = DL_KERNEL_ASSEMBLE;
@@ -390,6 +415,10 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
     hipError_t e = hipSuccess;
     switch (L.kind) {
       case OP_GEMM: e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile); break;
+      case OP_GEMM32:
+        e = launch_gemm32_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile);
+        break;
+      case OP_RES: e = launch_residual(d.res + L.off, L.count, s); break;
       case OP_POTRF: e = launch_potrf_tiles(d.potrf + L.off, L.count, s); break;
       case OP_MISC: e = launch_misc(d.misc + L.off, L.count, s); break;
       case OP_GEMV_N: e = launch_gemv_n(d.gn + L.off, L.count, L.gx, s); break;
@@ -466,6 +495,7 @@ static void seq_assemble(dl_ws* W, Inst& I, bool p, bool c, std::vector<Step>& q
       J.o.BRc = I.BRc; J.o.brc_stride = I.ldbr * m.bp;
     }
     J.o.rhs = I.rhs;
+    J.o.b32 = I.mixed ? 1 : 0;
     s.gx = m.bp;
     s.gy = m.nt;
     q.push_back(s);
@@ -492,7 +522,9 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
   double* Dbase = (w == 0) ? I.Dp : I.Dc;
   double* Bbase = (w == 0) ? I.Bp : I.BRc;
   auto Dt = [&](int t) { return Dbase + (ring ? (int64_t)(t % 2) : (int64_t)t) * bb; };
-  auto BRs = [&](int sl) { return Bbase + (int64_t)sl * ldbr * bp; };
+  const int eb = I.eb;
+  auto BRs = [&](int sl) { return eoff(Bbase, (int64_t)sl * ldbr * bp, eb); };
+  auto BRo = [&](int sl, int rows) { return eoff(Bbase, (int64_t)sl * ldbr * bp + rows, eb); };
   auto asm_qp = [&](int t, uint64_t key) {
     Step s;
     s.key = key;
@@ -506,6 +538,7 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     s.asmj.o.Dp = Dt(t);
     s.asmj.o.Bp = BRs(t % 2);
     s.asmj.o.rhs = I.rhs;
+    s.asmj.o.b32 = I.mixed ? 1 : 0;
     s.gx = bp;
     s.gy = 1;
     q.push_back(s);
@@ -527,27 +560,34 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     const double b = m.b, ar = apr ? m.a : 0;
     const double mreal = (last ? 0.0 : b) + ar;
     // [B_t; R_t] <- [B_t; R_t] L_tt^{-T} = [B_t; R_t] G_t^T
-    q.push_back(gemm_step(K(major, 3), DL_CAT_TRSM, mreal * b * b,
-                          {mk(BRs(src) + rows_lo, ldbr, Dt(t), bp, BRs(nw) + rows_lo,
-                              ldbr, M, bp, bp, F_TB | F_KHI_COL | F_BETA0, 1.0, 0.0)}));
+    const int x64 = I.mixed ? F_B64 : 0;
+    auto gs = [&](uint64_t key, int cat, double fl, std::vector<GemmTask> ts) {
+      return I.mixed ? gemm32_step(key, cat, fl, std::move(ts))
+                     : gemm_step(key, cat, fl, std::move(ts));
+    };
+    q.push_back(gs(K(major, 3), DL_CAT_TRSM, mreal * b * b,
+                   {mk(BRo(src, rows_lo), ldbr, Dt(t), bp, BRo(nw, rows_lo), ldbr, M, bp,
+                       bp, F_TB | F_KHI_COL | F_BETA0 | x64, 1.0, 0.0)}));
     if (!ring) {
       spare = slot[t];
       slot[t] = nw;
     }
     double* BRt = BRs(nw);
+    double* RRt = BRo(nw, bp);
+    const int c64 = I.mixed ? F_C64 : 0;
     std::vector<GemmTask> up;
     if (!last) {
       up.push_back(mk(BRt, ldbr, BRt, ldbr, Dt(t + 1), bp, bp, bp, bp,
-                      F_TB | F_LOWER, -1.0, 1.0));
+                      F_TB | F_LOWER | c64, -1.0, 1.0));
       if (apr)
-        up.push_back(mk(BRt + bp, ldbr, BRt, ldbr, BRs(slot[t + 1]) + bp, ldbr, apr,
-                        bp, bp, F_TB, -1.0, 1.0));
+        up.push_back(mk(RRt, ldbr, BRt, ldbr, BRo(slot[t + 1], bp), ldbr, apr, bp, bp,
+                        F_TB, -1.0, 1.0));
     }
     if (apr)
-      up.push_back(mk(BRt + bp, ldbr, BRt + bp, ldbr, P, m.ap, apr, apr, bp,
-                      F_TB | F_LOWER, -1.0, 1.0));
+      up.push_back(mk(RRt, ldbr, RRt, ldbr, P, m.ap, apr, apr, bp,
+                      F_TB | F_LOWER | c64, -1.0, 1.0));
     const double upd = (last ? 0.0 : b * b * b + 2.0 * ar * b * b) + ar * ar * b;
-    q.push_back(gemm_step(K(major, 4), DL_CAT_UPDATE, upd, up));
+    q.push_back(gs(K(major, 4), DL_CAT_UPDATE, upd, up));
   }
   const uint64_t tail = (uint64_t)nt_max + 1;
   if (m.ap > 0) {
@@ -609,8 +649,13 @@ static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   const int bp = m.bp, ap = m.ap;
   const int64_t ldbr = I.ldbr;
   const double b = m.b, a = m.a;
-  auto BRs = [&](int t) { return I.BRc + (int64_t)I.slot_final[t] * ldbr * bp; };
+  const int eb = I.eb;
+  auto BRs = [&](int t) { return eoff(I.BRc, (int64_t)I.slot_final[t] * ldbr * bp, eb); };
+  auto BRo = [&](int t, int rows) {
+    return eoff(I.BRc, (int64_t)I.slot_final[t] * ldbr * bp + rows, eb);
+  };
   auto G = [&](int t) { return I.Dc + (int64_t)t * bp * bp; };
+  const int a32 = I.mixed ? 1 : 0;
   double* x = I.x;
   double* xP = x + (int64_t)m.nt * bp;
   double* mu = I.mu;
@@ -622,7 +667,7 @@ static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     if (t > 0)
       q.push_back(gn_step(K(mj, 0), {bp + ap, bp, BRs(t - 1), ldbr,
                                      x + (int64_t)(t - 1) * bp, 0, -1.0, 1.0, bp, xt,
-                                     I.u, xP, xP, part},
+                                     I.u, xP, xP, part, a32},
                           8.0 * (b + a) * b));
     q.push_back(gn_step(K(mj, 1), {bp, bp, G(t), bp, t > 0 ? I.u : xt, 1, 1.0, 0.0,
                                    -1, nullptr, xt, nullptr, nullptr, part},
@@ -630,9 +675,9 @@ static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   }
   const uint64_t mid = (uint64_t)nt_max + 1;
   if (ap > 0) {
-    q.push_back(gn_step(K(mid, 0), {ap, bp, BRs(m.nt - 1) + bp, ldbr,
+    q.push_back(gn_step(K(mid, 0), {ap, bp, BRo(m.nt - 1, bp), ldbr,
                                     x + (int64_t)(m.nt - 1) * bp, 0, -1.0, 1.0, -1,
-                                    xP, xP, nullptr, nullptr, part},
+                                    xP, xP, nullptr, nullptr, part, a32},
                         8.0 * a * b));
     q.push_back(gn_step(K(mid, 1), {ap, ap, I.GPc, ap, xP, 1, 1.0, 0.0, -1, nullptr,
                                     xP, nullptr, nullptr, part},
@@ -646,15 +691,15 @@ static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     const uint64_t mj = mid + 1 + (uint64_t)(m.nt - 1 - t);
     if (t == m.nt - 1) {
       if (ap > 0)
-        q.push_back(gt_step(K(mj, 0), {ap, bp, BRs(t) + bp, ldbr, muP, -1, nullptr, 0,
-                                       -1.0, 1.0, xt, I.u},
+        q.push_back(gt_step(K(mj, 0), {ap, bp, BRo(t, bp), ldbr, muP, -1, nullptr, 0,
+                                       -1.0, 1.0, xt, I.u, a32},
                             8.0 * a * b));
       else
         q.push_back(misc_step(K(mj, 0), DL_CAT_SOLVE, MJ_COPY, I.u, xt, bp));
     } else {
       q.push_back(gt_step(K(mj, 0), {bp + ap, bp, BRs(t), ldbr,
                                      mu + (int64_t)(t + 1) * bp, bp, muP, 0, -1.0, 1.0,
-                                     xt, I.u},
+                                     xt, I.u, a32},
                           8.0 * (b + a) * b));
     }
     q.push_back(gt_step(K(mj, 1), {bp, bp, G(t), bp, I.u, -1, nullptr, 1, 1.0, 0.0,
@@ -670,8 +715,19 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   const int bp = m.bp, ap = m.ap;
   const int64_t ld = I.ldbr;  // bp + ap
   const double b = m.b, a = m.a;
-  auto BRs = [&](int t) { return I.BRc + (int64_t)I.slot_final[t] * ld * bp; };
+  const int eb = I.eb;
+  auto BRs = [&](int t) { return eoff(I.BRc, (int64_t)I.slot_final[t] * ld * bp, eb); };
+  auto BRo = [&](int t, int rows) {
+    return eoff(I.BRc, (int64_t)I.slot_final[t] * ld * bp + rows, eb);
+  };
   auto G = [&](int t) { return I.Dc + (int64_t)t * bp * bp; };
+  // mixed precision: W = [B;R]G and the products with it run on FP32 MFMA
+  const bool mx = I.mixed;
+  auto gs = [&](uint64_t key, int cat, double fl, std::vector<GemmTask> ts) {
+    return mx ? gemm32_step(key, cat, fl, std::move(ts)) : gemm_step(key, cat, fl, std::move(ts));
+  };
+  const int fB64 = mx ? F_B64 : 0, fA64 = mx ? F_A64 : 0, fC64 = mx ? F_C64 : 0;
+  double* WVr = eoff(I.WV, bp, eb);  // arrow rows of WV
   for (int k = 0; k < 2; ++k)
     q.push_back(misc_step(K(0, 0, 0, k), DL_CAT_SELINV, MJ_FILL, I.XC[k], nullptr,
                           ld * ld, 0.0));
@@ -694,29 +750,30 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     const int nxt = cur ^ 1;
     const bool last = (t + 1 == m.nt);
     if (last) {
-      q.push_back(misc_step(K(mj, 0), DL_CAT_SELINV, MJ_FILL, I.WV, nullptr, ld * bp));
+      q.push_back(misc_step(K(mj, 0), DL_CAT_SELINV, MJ_FILL, I.WV, nullptr,
+                            ld * bp * eb / 8));
       if (ap > 0)
-        q.push_back(gemm_step(K(mj, 1), DL_CAT_SELINV, a * b * b,
-                              {mk(BRs(t) + bp, ld, G(t), bp, I.WV + bp, ld, ap, bp, bp,
-                                  F_KLO_COL | F_BETA0, 1.0, 0.0)}));
+        q.push_back(gs(K(mj, 1), DL_CAT_SELINV, a * b * b,
+                       {mk(BRo(t, bp), ld, G(t), bp, WVr, ld, ap, bp, bp,
+                           F_KLO_COL | F_BETA0 | fB64, 1.0, 0.0)}));
     } else {
       // [W_t; V_t] = [B_t; R_t]_factor G_t
-      q.push_back(gemm_step(K(mj, 1), DL_CAT_SELINV, (b + a) * b * b,
-                            {mk(BRs(t), ld, G(t), bp, I.WV, ld, bp + ap, bp, bp,
-                                F_KLO_COL | F_BETA0, 1.0, 0.0)}));
+      q.push_back(gs(K(mj, 1), DL_CAT_SELINV, (b + a) * b * b,
+                     {mk(BRs(t), ld, G(t), bp, I.WV, ld, bp + ap, bp, bp,
+                         F_KLO_COL | F_BETA0 | fB64, 1.0, 0.0)}));
     }
     const double ba = b + a;
     // [X_{t+1,t}; X_{P,t}] = -[[X_{t+1,t+1}, X_{t+1,P}]; [X_{P,t+1}, X_P]] WV
-    q.push_back(gemm_step(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
-                          {mk(I.XC[cur], ld, I.WV, ld, I.Y, ld, bp + ap, bp, bp + ap,
-                              F_BETA0, -1.0, 0.0)}));
+    q.push_back(gs(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
+                   {mk(I.XC[cur], ld, I.WV, ld, I.Y, ld, bp + ap, bp, bp + ap,
+                       F_BETA0 | fA64 | fC64, -1.0, 0.0)}));
     // X_tt = G_t^T G_t - Y^T WV   (lower triangle)
     q.push_back(gemm_step(K(mj, 3), DL_CAT_SELINV, b * b * b / 3.0,
                           {mk(G(t), bp, G(t), bp, I.XC[nxt], ld, bp, bp, bp,
                               F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0, 1.0, 0.0)}));
-    q.push_back(gemm_step(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
-                          {mk(I.Y, ld, I.WV, ld, I.XC[nxt], ld, bp, bp, bp + ap,
-                              F_TA | F_LOWER, -1.0, 1.0)}));
+    q.push_back(gs(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
+                   {mk(I.Y, ld, I.WV, ld, I.XC[nxt], ld, bp, bp, bp + ap,
+                       F_TA | F_LOWER | fA64 | fC64, -1.0, 1.0)}));
     Step fin;
     fin.key = K(mj, 5);
     fin.kind = OP_FINISH;
@@ -731,6 +788,46 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     q.push_back(fin);
     cur = nxt;
   }
+}
+
+// FP64 iterative refinement of the mean (mixed precision) and the final
+// residual |rhs - Q_c mu| / |rhs| of every workspace.  Each refinement step:
+// x = rhs - Q_c mu_acc (FP64, sparse), solve with the factor (x -> mu),
+// mu_acc += mu.
+static Step res_step(uint64_t key, Inst& I, const double* v, double* out) {
+  Step s;
+  s.key = key;
+  s.kind = OP_RES;
+  s.cat = DL_CAT_SOLVE;
+  s.res.m = I.model->dev;
+  s.res.coef = I.coef;
+  s.res.v = v;
+  s.res.rhs = I.rhs;
+  s.res.out = out;
+  s.res.av = I.av;
+  s.res.partial = I.rpart;
+  s.res.norms = I.rnorm;
+  return s;
+}
+
+static void seq_refine(dl_ws* W, Inst& I, int nt_max, int steps, std::vector<Step>& q) {
+  const uint64_t span = 2 * (uint64_t)nt_max + 8;
+  if (steps > 0)
+    q.push_back(misc_step(K(0, 0), DL_CAT_SOLVE, MJ_COPY, I.mu_acc, I.mu, I.m.Np));
+  for (int r = 0; r < steps; ++r) {
+    const uint64_t base = 1 + (uint64_t)r * span;
+    q.push_back(res_step(K(base, 0), I, I.mu_acc, I.x));
+    std::vector<Step> core;
+    seq_solve(W, I, nt_max, core);
+    for (auto& st : core) st.key += K(base + 1, 0);
+    q.insert(q.end(), core.begin(), core.end());
+    q.push_back(misc_step(K(base + span - 1, 0), DL_CAT_SOLVE, MJ_AXPY, I.mu_acc, I.mu,
+                          I.m.Np));
+  }
+  const uint64_t tail = 1 + (uint64_t)steps * span;
+  if (steps > 0)
+    q.push_back(misc_step(K(tail, 0), DL_CAT_SOLVE, MJ_COPY, I.mu, I.mu_acc, I.m.Np));
+  q.push_back(res_step(K(tail, 1), I, I.mu, I.x));
 }
 
 // mu^T Q_p mu, (y - A mu)^T D (y - A mu) and f_obj, per instance.
@@ -756,6 +853,7 @@ static void seq_post(dl_ws* W, Inst& I, int k, std::vector<Step>& q) {
   c.comb.f = W->f_all + k;
   c.comb.parts = (dl_fobj_parts*)(W->parts_all + 8 * (int64_t)k);
   c.comb.info_out = W->info_all + 2 * (int64_t)k;
+  c.comb.rnorm = I.rnorm;
   q.push_back(c);
 }
 
@@ -800,6 +898,14 @@ static dl_status build_plans(dl_ws* W) {
   }
   {
     std::vector<std::vector<Step>> seqs;
+    for (auto& I : W->inst) {
+      seqs.emplace_back();
+      seq_refine(W, I, nt_max, I.mixed ? DL_REFINE_STEPS : 0, seqs.back());
+    }
+    merge(seqs, H, W->table, W->refine_p);
+  }
+  {
+    std::vector<std::vector<Step>> seqs;
     for (size_t k = 0; k < W->inst.size(); ++k) {
       seqs.emplace_back();
       seq_post(W, W->inst[k], (int)k, seqs.back());
@@ -818,6 +924,7 @@ static dl_status build_plans(dl_ws* W) {
   append(W->eval_p, W->asm_p[2]);
   append(W->eval_p, W->fac_p[2]);
   append(W->eval_p, W->solve_p);
+  append(W->eval_p, W->refine_p);
   append(W->eval_p, W->post_p);
   // upload descriptor arrays
   dl_status st = DL_OK;
@@ -844,6 +951,7 @@ static dl_status build_plans(dl_ws* W) {
   up(H.th, W->Dd.th);
   up(H.quad, W->Dd.quad);
   up(H.comb, W->Dd.comb);
+  up(H.res, W->Dd.res);
   return st;
 }
 
@@ -868,6 +976,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->flags = flags;
   W->sel = (flags & DL_WS_SELINV) != 0;
   W->keep_qp = (flags & DL_WS_KEEP_QP) != 0;
+  W->mixed = (flags & DL_WS_MIXED) != 0;
   W->use_graph = (flags & DL_WS_GRAPH) != 0;
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
@@ -887,15 +996,22 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     W->max_shmem = std::max(W->max_shmem, 2 * bp + ap);
     I.qp_ring = !W->keep_qp;
     I.ldbr = bp + ap;
+    I.mixed = W->mixed;
+    I.eb = I.mixed ? 4 : 8;
+    const size_t eb = I.eb;
     if (I.qp_ring) {
       A(sizeof(double) * 2 * bb, (void**)&I.Dp);
-      A(sizeof(double) * 3 * bb, (void**)&I.Bp);
+      A(eb * 3 * bb, (void**)&I.Bp);
     } else {
       A(sizeof(double) * m.nt * bb, (void**)&I.Dp);
-      A(sizeof(double) * (m.nt + 1) * bb, (void**)&I.Bp);
+      A(eb * (m.nt + 1) * bb, (void**)&I.Bp);
     }
     A(sizeof(double) * m.nt * bb, (void**)&I.Dc);
-    A(sizeof(double) * (m.nt + 1) * I.ldbr * bp, (void**)&I.BRc);
+    A(eb * (m.nt + 1) * I.ldbr * bp, (void**)&I.BRc);
+    A(sizeof(double) * m.Np, (void**)&I.mu_acc);
+    A(sizeof(double) * (m.m_total + 1), (void**)&I.av);
+    A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.rpart);
+    A(sizeof(double) * 2, (void**)&I.rnorm);
     const size_t tip = sizeof(double) * (ap > 0 ? ap * ap : 1);
     A(tip, (void**)&I.Pp);
     A(tip, (void**)&I.Pc);
@@ -1028,6 +1144,7 @@ extern "C" dl_status bta_solve(dl_ws* W, double* rhs_inout_dev, void* stream) {
     }
   }
   DL_HIP_CHECK(run(W, W->solve_p, s));
+  if (!rhs_inout_dev) DL_HIP_CHECK(run(W, W->refine_p, s));
   if (rhs_inout_dev) {
     int64_t off = 0;
     for (auto& I : W->inst) {
@@ -1148,16 +1265,18 @@ extern "C" dl_status dl_ws_get_block(dl_ws* W, dl_which which, int32_t kind,
     const bool fact = W->factored[p ? 0 : 1];
     const int sl = (!p && fact) ? I.slot_final[t] : t;
     const int64_t ldbr = p ? bp : I.ldbr;
-    const double* BRt = (p ? I.Bp : I.BRc) + (int64_t)sl * ldbr * bp;
+    const double* BRt = eoff(p ? I.Bp : I.BRc, (int64_t)sl * ldbr * bp, I.eb);
     if (kind == 0) {
       J.src = (p ? I.Dp : I.Dc) + (int64_t)t * bp * bp; J.lds = bp;
       J.ldd = m.b; J.rows = m.b; J.cols = m.b;
     } else if (kind == 1) {
       if (t + 1 >= m.nt) return DL_EINVAL;
       J.src = BRt; J.lds = ldbr; J.ldd = m.b; J.rows = m.b; J.cols = m.b;
+      if (I.mixed) J.kind = MJ_COPY2D_F32;
     } else if (kind == 2) {
       if (p || m.a == 0) return DL_EINVAL;
-      J.src = BRt + bp; J.lds = ldbr; J.ldd = m.a; J.rows = m.a; J.cols = m.b;
+      J.src = eoff((void*)BRt, bp, I.eb); J.lds = ldbr; J.ldd = m.a; J.rows = m.a; J.cols = m.b;
+      if (I.mixed) J.kind = MJ_COPY2D_F32;
     } else {
       return DL_EINVAL;
     }
@@ -1246,7 +1365,8 @@ extern "C" dl_status dl_ws_profile_end(dl_ws* W, double* ms, int64_t* launches,
 
 static std::string gemm_signature(const dl_ws* W, const Launch& L) {
   std::ostringstream o;
-  o << "gfx950 gemm cat" << L.cat << " n" << L.count;
+  o << "gfx950 " << (L.kind == OP_GEMM32 ? "gemm32" : "gemm") << " cat" << L.cat
+    << " n" << L.count;
   for (int i = 0; i < L.count && i < 8; ++i) {
     const GemmTask& t = W->H.gemm[L.off + i];
     o << " " << t.M << "x" << t.N << "x" << t.K << "f" << (t.flags & ~F_BETA0);
@@ -1282,7 +1402,7 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
   DL_HIP_CHECK(hipEventCreate(&e1));
   dl_status st = DL_OK;
   for (Launch& L : W->table) {
-    if (L.kind != OP_GEMM || st != DL_OK) continue;
+    if ((L.kind != OP_GEMM && L.kind != OP_GEMM32) || st != DL_OK) continue;
     const std::string sig = gemm_signature(W, L);
     auto it = best.find(sig);
     if (it == best.end()) {
@@ -1321,7 +1441,7 @@ extern "C" dl_status dl_ws_tile_counts(const dl_ws* W, int64_t* n64, int64_t* n1
   if (!W) return DL_EINVAL;
   int64_t a = 0, b = 0;
   for (const Launch& L : W->table)
-    if (L.kind == OP_GEMM) (L.tile == 128 ? b : a)++;
+    if (L.kind == OP_GEMM || L.kind == OP_GEMM32) (L.tile == 128 ? b : a)++;
   if (n64) *n64 = a;
   if (n128) *n128 = b;
   return DL_OK;

@@ -228,4 +228,185 @@ hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
   return hipGetLastError();
 }
 
+
+// ---- FP32 MFMA variant (mixed precision) --------------------------------------
+//
+// Same task model and tiling as above with v_mfma_f32_16x16x4_f32 and FP32
+// accumulation.  Operands are FP32 unless the task's F_A64 / F_B64 flag says
+// the operand is stored in FP64 (it is then rounded to FP32 when staged);
+// C is FP32 unless F_C64, in which case alpha*acc + beta*C is formed in FP64
+// and stored in FP64 (Schur updates into FP64 diagonal blocks and tips).
+// Lane layout of the FP32 accumulator: register r of lane l holds
+// D[4(l/16) + r][l%16] (checked against host GEMMs by the GPU tests).
+typedef float v4f_ __attribute__((ext_vector_type(4)));
+
+namespace {
+template <int BR>
+__device__ __forceinline__ void load_chunk32(const void* __restrict__ Xv, bool x64,
+                                             int64_t ldx, bool trans, int r0, int R,
+                                             int k0, int kend, int tid,
+                                             float (&v)[BR * BK / 256]) {
+  constexpr int PER = BR * BK / 256;
+  const double* X64 = (const double*)Xv;
+  const float* X32 = (const float*)Xv;
+  if (!trans) {
+    const int r = r0 + (tid % BR);
+    const int kb = k0 + (tid / BR) * PER;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = kb + i;
+      const int64_t o = (int64_t)r + (int64_t)k * ldx;
+      v[i] = (r < R && k < kend) ? (x64 ? (float)X64[o] : X32[o]) : 0.f;
+    }
+  } else {
+    const int k = k0 + (tid % BK);
+    const int rb = r0 + (tid / BK) * PER;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int r = rb + i;
+      const int64_t o = (int64_t)k + (int64_t)r * ldx;
+      v[i] = (r < R && k < kend) ? (x64 ? (float)X64[o] : X32[o]) : 0.f;
+    }
+  }
+}
+
+template <int BR>
+__device__ __forceinline__ void store_chunk32(float* __restrict__ S, bool trans, int tid,
+                                              const float (&v)[BR * BK / 256]) {
+  constexpr int PER = BR * BK / 256;
+  constexpr int LD = BR + 4;
+  if (!trans) {
+    const int r = tid % BR;
+    const int kb = (tid / BR) * PER;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) S[(kb + i) * LD + r] = v[i];
+  } else {
+    const int k = tid % BK;
+    const int rb = (tid / BK) * PER;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) S[k * LD + rb + i] = v[i];
+  }
+}
+}  // namespace
+
+template <int BT>
+__global__ __launch_bounds__(256) void k_gemm32_tasks(
+    const GemmTask* __restrict__ tasks, int ntask) {
+  constexpr int LD = BT + 4;
+  constexpr int F = BT / 32;
+  constexpr int PER = BT * BK / 256;
+  __shared__ float As[2][BK * LD];
+  __shared__ float Bs[2][BK * LD];
+
+  const int tid = threadIdx.x;
+  const int ti = find_task(tasks, ntask, blockIdx.x);
+  const GemmTask T = tasks[ti];
+  int tm, tn;
+  tile_coords(T, blockIdx.x - T.tile_begin, tm, tn);
+  const int m0 = tm * BT;
+  const int n0 = tn * BT;
+  const bool ta = T.flags & F_TA;
+  const bool tb = T.flags & F_TB;
+  const bool a64 = T.flags & F_A64;
+  const bool b64 = T.flags & F_B64;
+
+  int kb = 0, ke = T.K;
+  if (T.flags & F_KLO_COL) kb = max(kb, n0);
+  if (T.flags & F_KHI_COL) ke = min(ke, n0 + BT);
+  if (T.flags & F_KLO_ROW) kb = max(kb, m0);
+  if (T.flags & F_KHI_ROW) ke = min(ke, m0 + BT);
+  kb = (kb / BK) * BK;
+  const int nchunks = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lrow = lane & 15, lk = lane >> 4;
+
+  v4f_ acc[F][F];
+#pragma unroll
+  for (int i = 0; i < F; ++i)
+#pragma unroll
+    for (int j = 0; j < F; ++j) acc[i][j] = (v4f_){0.f, 0.f, 0.f, 0.f};
+
+  float va[PER], vb[PER];
+  if (nchunks > 0) {
+    load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, kb, ke, tid, va);
+    load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
+    store_chunk32<BT>(As[0], ta, tid, va);
+    store_chunk32<BT>(Bs[0], !tb, tid, vb);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const bool more = (c + 1) < nchunks;
+    if (more) {
+      const int k1 = kb + (c + 1) * BK;
+      load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, k1, ke, tid, va);
+      load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
+    }
+    const float* __restrict__ as = As[buf];
+    const float* __restrict__ bs = Bs[buf];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      float fa[F], fb[F];
+#pragma unroll
+      for (int i = 0; i < F; ++i) fa[i] = as[kk * LD + wm * (BT / 2) + i * 16 + lrow];
+#pragma unroll
+      for (int j = 0; j < F; ++j) fb[j] = bs[kk * LD + wn * (BT / 2) + j * 16 + lrow];
+#pragma unroll
+      for (int i = 0; i < F; ++i)
+#pragma unroll
+        for (int j = 0; j < F; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[j], fa[i], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      store_chunk32<BT>(As[buf ^ 1], ta, tid, va);
+      store_chunk32<BT>(Bs[buf ^ 1], !tb, tid, vb);
+    }
+    __syncthreads();
+  }
+  const bool lower = T.flags & F_LOWER;
+  const bool beta0 = T.flags & F_BETA0;
+  const bool c64 = T.flags & F_C64;
+#pragma unroll
+  for (int i = 0; i < F; ++i) {
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // accumulator element (row 4*lk + r of the 16x16 block of C^T)
+        const int m = m0 + wm * (BT / 2) + i * 16 + lrow;
+        const int n = n0 + wn * (BT / 2) + j * 16 + 4 * lk + r;
+        if (m >= T.M || n >= T.N || (lower && n > m)) continue;
+        const int64_t o = (int64_t)m + (int64_t)n * T.ldc;
+        if (c64) {
+          double* p = (double*)T.C + o;
+          double v = T.alpha * (double)acc[i][j][r];
+          if (!beta0) v += T.beta * (*p);
+          *p = v;
+        } else {
+          float* p = (float*)T.C + o;
+          float v = (float)T.alpha * acc[i][j][r];
+          if (!beta0) v += (float)T.beta * (*p);
+          *p = v;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_gemm32_tasks(const GemmTask* tasks_dev, int ntask,
+                               int total_tiles, hipStream_t s, int tile) {
+  if (total_tiles <= 0) return hipSuccess;
+  if (tile == 128)
+    hipLaunchKernelGGL(k_gemm32_tasks<128>, dim3(total_tiles), dim3(256), 0, s,
+                       tasks_dev, ntask);
+  else
+    hipLaunchKernelGGL(k_gemm32_tasks<64>, dim3(total_tiles), dim3(256), 0, s,
+                       tasks_dev, ntask);
+  return hipGetLastError();
+}
+
 }  // namespace dl

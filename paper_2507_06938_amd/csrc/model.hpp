@@ -67,6 +67,7 @@ struct AssembleOut {
   double* Pp;   // ap x ap (tip of Q_p), ld ap
   double* Pc;   // ap x ap (tip of Q_c)
   double* rhs;  // Np
+  int b32;      // Bp and BRc are stored in FP32 (mixed precision)
 };
 
 struct ThetaJob {
@@ -98,6 +99,7 @@ struct CombineJob {
   double* f;
   dl_fobj_parts* parts;
   int64_t* info_out;
+  const double* rnorm;  // [|rhs - Q_c mu|^2, |rhs|^2] (may be null)
 };
 
 constexpr int QF_BLOCKS = 256;
@@ -111,6 +113,21 @@ hipError_t prepare_assemble(int max_shmem_doubles);
 hipError_t launch_assemble_tips(const AsmJob* jobs, int count, int max_blocks,
                                 hipStream_t s);
 hipError_t launch_quadforms(const QuadJob* jobs, int count, hipStream_t s);
+
+// out = rhs - Q_c v (FP64, from the stencil of Q_p and the observation rows;
+// used by the iterative refinement of the mixed-precision solve), and
+// norms[0] = |out|_2^2, norms[1] = |rhs|_2^2 (fixed reduction order).
+struct ResJob {
+  const ModelDev* m;
+  const double* coef;
+  const double* v;    // Np (padded BTA order)
+  const double* rhs;  // Np
+  double* out;        // Np
+  double* av;         // m_total scratch: (A v)_row
+  double* partial;    // 2 * QF_BLOCKS
+  double* norms;      // 2
+};
+hipError_t launch_residual(const ResJob* jobs, int count, hipStream_t s);
 hipError_t launch_combine(const CombineJob* jobs, int count, hipStream_t s);
 hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
                        hipStream_t s);

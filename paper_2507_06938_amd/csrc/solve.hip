@@ -21,8 +21,14 @@ __global__ __launch_bounds__(256) void k_gemv_n_partial(
   if (g.tri) k1 = min(k1, (int)blockIdx.x * 64 + 64);
   double acc = 0.0;
   if (row < g.M) {
-    for (int k = k0 + wave; k < k1; k += 4)
-      acc += g.A[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
+    if (g.a32) {
+      const float* A32 = (const float*)g.A;
+      for (int k = k0 + wave; k < k1; k += 4)
+        acc += (double)A32[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
+    } else {
+      for (int k = k0 + wave; k < k1; k += 4)
+        acc += g.A[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
+    }
   }
   sh[wave][lane] = acc;
   __syncthreads();
@@ -65,12 +71,13 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvT* __restrict__ jobs) 
   const int j = blockIdx.x * 4 + wave;
   if (j >= g.N) return;
   const double* col = g.A + (int64_t)j * g.lda;
+  const float* col32 = (const float*)g.A + (int64_t)j * g.lda;
   const int split = g.split < 0 ? g.M : g.split;
   const int i0 = g.tri ? (j & ~63) : 0;
   double acc = 0.0;
   for (int i = i0 + lane; i < g.M; i += 64) {
     const double xv = (i < split) ? g.x1[i] : g.x2[i - split];
-    acc += col[i] * xv;
+    acc += (g.a32 ? (double)col32[i] : col[i]) * xv;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) g.y[j] = (g.base ? g.beta * g.base[j] : 0.0) + g.alpha * acc;

@@ -21,6 +21,7 @@ struct GemvN {
   const double* base2;
   double* out2;
   double* partial;
+  int a32;  // A stored in FP32
 };
 
 // y = beta*base + alpha*A^T*x with x = [x1 (rows < split); x2].
@@ -35,6 +36,7 @@ struct GemvT {
   double alpha, beta;
   const double* base;
   double* y;
+  int a32;  // A stored in FP32
 };
 
 // Batched launches over job arrays in device memory; max_M / max_N bound the

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
 
 DL_QP, DL_QC, DL_BOTH = 0, 1, 2
-DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH = 1, 2, 4
+DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH, DL_WS_MIXED = 1, 2, 4, 8
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other")
@@ -27,7 +27,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
           5: "call order violated", 6: "refinement did not converge"}
 
 PARTS_FIELDS = ("f", "logdet_p", "logdet_c", "quad_p", "quad_obs",
-                "log_prior", "log_lik_const", "reserved")
+                "log_prior", "log_lik_const", "rel_residual")
 
 
 class DaliaError(RuntimeError):
@@ -175,13 +175,13 @@ class Workspace:
     together.  Per-instance vectors are packed in instance order."""
 
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
-                 graph: bool = False):
+                 graph: bool = False, mixed: bool = False):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
         self.model = self.models[0]
         flags = ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
-                 | (DL_WS_GRAPH if graph else 0))
+                 | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0))
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
         _check("dl_ws_create_batch",
@@ -235,10 +235,16 @@ class Workspace:
         tensors to write into (no allocation on the call)."""
         th = thetas if isinstance(thetas, torch.Tensor) and thetas.is_cuda \
             else torch.as_tensor(thetas, dtype=torch.float64)
-        if th.dim() == 1:
-            th = th[None]
-        th = th.to(self.dev).contiguous()
-        n = th.shape[0]
+        uniform = all(m is self.models[0] for m in self.models)
+        if not uniform:
+            # one packed theta per instance (dims may differ)
+            th = th.reshape(-1).to(self.dev).contiguous()
+            n = self.B
+        else:
+            if th.dim() == 1:
+                th = th[None]
+            th = th.to(self.dev).contiguous()
+            n = th.shape[0]
         if out is None:
             f = torch.empty(n, dtype=torch.float64, device=self.dev)
             parts = torch.empty((n, 8), dtype=torch.float64, device=self.dev)
