@@ -14,7 +14,12 @@ Prints one JSON line.  Besides the metric it reports the BTA Cholesky
 TFLOP/s of Q_c alone, the log-determinant error against the FP64 CPU oracle
 (stored values written by tests/golden/make_golden.py), the live roofline of
 the dominant kernel (HIP events around its launches during the timed steps)
-and the CPU oracle timed on a bounded sample of the same workload.
+and the CPU oracle timed on a bounded sample of the same workload.  GEMM
+tiles are the measured choices of the library's autotuner (cache file
+paper_2507_06938_amd/tiles_gfx950.txt; missing shapes are timed and added).
+Two further measurements of the same workload are extra fields of the
+line: the 9-point central-difference gradient as one batched,
+graph-replayed evaluation, and f_obj in mixed precision with its errors.
 """
 from __future__ import annotations
 
@@ -77,6 +82,66 @@ def cpu_baseline(nt_sample: int = 20, var_samples: int = 8):
     }
 
 
+def _events_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def fd_batch(D, W, wl, model, single_ms, tiles):
+    """The 2 dim(theta) + 1 = 9 central-difference points of one gradient
+    (Eq. 10, h = 1e-3) as one batched, graph-replayed evaluation."""
+    import numpy as np
+    import torch
+    h = 1e-3
+    d = wl.dim_theta
+    pts = np.repeat(wl.theta[None], 2 * d + 1, axis=0)
+    for i in range(d):
+        pts[1 + 2 * i, i] += h
+        pts[2 + 2 * i, i] -= h
+    th = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    ws = D.Workspace([model] * (2 * d + 1), graph=True)
+    if tiles:
+        ws.autotune(tiles)
+    ms = _events_ms(torch, lambda: ws.fobj(th), 3)
+    f, _, info = ws.fobj(th)
+    torch.cuda.synchronize()
+    grad = ((f[1::2] - f[2::2]) / (2 * h)).cpu().numpy().tolist()
+    ok = bool((info == 0).all().item())
+    del ws
+    torch.cuda.empty_cache()
+    return {"points": 2 * d + 1, "ms_per_gradient": ms,
+            "evals_per_s": (2 * d + 1) * 1000.0 / ms,
+            "speedup_vs_sequential": (2 * d + 1) * single_ms / ms,
+            "gradient": grad, "all_spd": ok}
+
+
+def mixed(D, wl, model, errors, tiles):
+    """f_obj with FP32 off-diagonal blocks (FP64 diagonal blocks, tip and
+    refinement of the mean) at the same theta."""
+    import torch
+    ws = D.Workspace(model, mixed=True)
+    if tiles:
+        ws.autotune(tiles)
+    th = torch.tensor(wl.theta, dtype=torch.float64, device="cuda")
+    ms = _events_ms(torch, lambda: ws.fobj(th), 3)
+    f, parts, info = ws.fobj(th)
+    torch.cuda.synchronize()
+    p = parts.cpu().numpy()[0]
+    del ws
+    torch.cuda.empty_cache()
+    return {"evals_per_s": 1000.0 / ms, "ms": ms,
+            "err_vs_fp64_oracle": errors(p),
+            "refined_mean_rel_residual": float(p[7])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +149,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nt", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FD-batch and mixed-precision measurements")
+    ap.add_argument("--tiles", default=os.path.join(
+        ROOT, "paper_2507_06938_amd", "tiles_gfx950.txt"),
+        help="autotuner cache ('' disables tuning: default tiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the "
@@ -101,6 +171,7 @@ def main():
     wl = W.config1()
     model = D.Model.from_workload(wl)
     ws = D.Workspace(model, selinv=True)
+    tiles = ws.autotune(args.tiles) if args.tiles else None
     dev = torch.device("cuda")
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev)
     f = torch.empty(1, dtype=torch.float64, device=dev)
@@ -157,12 +228,15 @@ def main():
     pr = parts.cpu().numpy()[0]
 
     golden_path = os.path.join(ROOT, "tests", "golden", "c1_golden.json")
-    err = None
-    if os.path.exists(golden_path):
-        g = json.load(open(golden_path))
-        err = {"logdet_p": abs(pr[1] - g["logdet_p"]) / abs(g["logdet_p"]),
-               "logdet_c": abs(pr[2] - g["logdet_c"]) / abs(g["logdet_c"]),
-               "f_abs": abs(pr[0] - g["f"])}
+    g = json.load(open(golden_path)) if os.path.exists(golden_path) else None
+
+    def errors(p):
+        if g is None:
+            return None
+        return {"logdet_p": abs(p[1] - g["logdet_p"]) / abs(g["logdet_p"]),
+                "logdet_c": abs(p[2] - g["logdet_c"]) / abs(g["logdet_c"]),
+                "f_abs": abs(p[0] - g["f"])}
+    err = errors(pr)
 
     gk = prof.get("k_gemm_tasks", {"ms": 0.0, "launches": 0, "flops": 0.0})
     achieved = gk["flops"] / (gk["ms"] * 1e-3) / 1e12 if gk["ms"] else 0.0
@@ -183,7 +257,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "ns": wl.ns, "nt": wl.nt,
                    "nb": wl.a, "m": wl.m, "b": wl.b, "N": wl.N,
-                   "step": "fobj_eval + bta_selinv (all marginal variances)"},
+                   "step": "fobj_eval + bta_selinv (all marginal variances)",
+                   "gemm_tiles": tiles},
         "fobj_only_evals_per_s": 1000.0 / fobj_ms,
         "bta_cholesky_tflops": F / (fac_ms * 1e-3) / 1e12,
         "bta_cholesky_ms": fac_ms,
@@ -192,6 +267,10 @@ def main():
         "cpu_baseline": None,
     }
     del ws
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles)
+        out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt)
     print(json.dumps(out), flush=True)

@@ -260,7 +260,8 @@ dl_status mlp_adam(dl_mlp* net, float lr, float beta1, float beta2, float eps,
 enum {
   DL_CAT_POTRF_TILE = 0,  /* 64x64 diagonal-tile Cholesky + inverse       */
   DL_CAT_PANEL_TRSM = 1,  /* tiles below a diagonal tile times its inverse */
-  DL_CAT_PANEL_SYRK = 2,  /* trailing update inside a diagonal block       */
+  DL_CAT_PANEL_SYRK = 2,  /* trailing update inside a diagonal block,
+                             fused with the next diagonal tile's factor   */
   DL_CAT_TRTRI = 3,       /* inverse of the diagonal-block factor          */
   DL_CAT_TRSM = 4,        /* [B_t; R_t] L_tt^{-T}                          */
   DL_CAT_UPDATE = 5,      /* D_{t+1}, R_{t+1}, tip Schur updates           */
@@ -279,7 +280,8 @@ enum {
   DL_KERNEL_POTRF_TILE = 1,  /* 64x64 Cholesky + inverse                 */
   DL_KERNEL_GEMV = 2,        /* solve matrix-vector products             */
   DL_KERNEL_ASSEMBLE = 3,    /* assembly                                 */
-  DL_KERNEL_OTHER = 4
+  DL_KERNEL_OTHER = 4,
+  DL_KERNEL_PANEL = 5        /* fused trailing update + next tile factor */
 };
 dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
                               int32_t max_launches);

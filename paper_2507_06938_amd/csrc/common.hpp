@@ -84,7 +84,9 @@ struct DeviceTasks {
 // of A <- L (upper zeroed), Ginv (64 x 64, ld 64, may be null) <- L^{-1};
 // mode 1: lower triangle of A <- L^{-1} (the factor itself is not kept).
 // logdiag[i] = log L_ii; on a non-positive pivot *info = row0 + i + 1 (first
-// failure only).  A batch of tiles is one launch, one workgroup per tile.
+// failure only).  M (64 x 64, ld 64, may be null) <- G^T G with G = L^{-1},
+// i.e. the inverse of the tile, exactly symmetric.  A batch of tiles is one
+// launch, one workgroup per tile.
 struct PotrfTileArgs {
   double* A;
   int64_t lda;
@@ -94,9 +96,40 @@ struct PotrfTileArgs {
   int64_t row0;
   int32_t mode;
   int32_t pad_;
+  double* M;
 };
 hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
                               hipStream_t s);
+
+// ---- fused panel step of a blocked diagonal-block Cholesky -------------------
+// For the n x n block A (nbk x nbk tiles of 64, column-major, ld) whose
+// tiles 0..j are factored (diagonal tiles hold G_kk = L_kk^{-1}, the tiles
+// below diagonal tile k still hold the unsolved panel P_k = A(:, k) as
+// updated by panels < k), one step j applies the trailing update of panel j
+// to the lower tiles (I, J), j < J <= I:
+//     A(I, J) -= P_j(I) M_j P_j(J)^T,   M_j = G_jj^T G_jj,
+// which equals L(I, j) L(J, j)^T with L(., j) = P_j G_jj^T, and in the same
+// launch factors the updated diagonal tile j+1 (mode 1, logdiag, info) and
+// writes M_{j+1} (if Mnext is not null).  The panels are solved afterwards,
+// all at once (L(I, k) = P_k(I) G_kk^T).  One workgroup per tile; the tiles
+// that factor are numbered first.
+struct PanelTask {
+  double* A;
+  int64_t ld;
+  const double* M;     // M_j, 64 x 64, ld 64
+  double* Mnext;       // M_{j+1} or null
+  double* logdiag;     // 64 entries for tile j+1
+  int64_t* info;
+  int64_t row0;        // global row of tile j+1
+  int32_t j, nbk;
+  int32_t tile_begin;  // first non-factor workgroup of this task (after the
+                       // count factor workgroups of the launch)
+  int32_t ntiles;      // lower tiles of the trailing grid, factor tile included
+};
+// Fill tile_begin/ntiles; return the grid size.
+int finalize_panels(PanelTask* t, int n);
+hipError_t launch_panel_updates(const PanelTask* tasks_dev, int ntask, int grid,
+                                hipStream_t s);
 
 // ---- small batched element-wise jobs ------------------------------------------
 enum : int { MJ_FILL = 0, MJ_COPY = 1, MJ_ZERO_I64 = 2, MJ_DIAG = 3,

@@ -30,7 +30,7 @@ namespace dl {
 enum OpKind : int {
   OP_GEMM, OP_POTRF, OP_MISC, OP_GEMV_N, OP_GEMV_T, OP_SUM, OP_FINISH,
   OP_ASM_COLS, OP_ASM_TIPS, OP_THETA, OP_QUAD, OP_COMBINE, OP_GEMM32, OP_RES,
-  OP_NKIND
+  OP_PANEL, OP_NKIND
 };
 
 // One step of one sequence (before merging).
@@ -41,6 +41,7 @@ struct Step {
   double flops = 0.0, bytes = 0.0;
   std::vector<GemmTask> gemm;
   PotrfTileArgs potrf{};
+  PanelTask panel{};
   MiscJob misc{};
   GemvN gn{};
   GemvT gt{};
@@ -86,6 +87,7 @@ struct Plan {
 struct Descs {
   std::vector<GemmTask> gemm;
   std::vector<PotrfTileArgs> potrf;
+  std::vector<PanelTask> panel;
   std::vector<MiscJob> misc;
   std::vector<GemvN> gn;
   std::vector<GemvT> gt;
@@ -101,6 +103,7 @@ struct Descs {
 struct DevDescs {
   GemmTask* gemm = nullptr;
   PotrfTileArgs* potrf = nullptr;
+  PanelTask* panel = nullptr;
   MiscJob* misc = nullptr;
   GemvN* gn = nullptr;
   GemvT* gt = nullptr;
@@ -157,6 +160,13 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
   L.count = (int)D.vec.size() - L.off;                  \
   break;
       case OP_POTRF: PUSH(potrf, potrf)
+      case OP_PANEL: {
+        L.off = (int)D.panel.size();
+        for (const Step* st : g) D.panel.push_back(st->panel);
+        L.count = (int)D.panel.size() - L.off;
+        L.gx = finalize_panels(D.panel.data() + L.off, L.count);
+        break;
+      }
       case OP_MISC: PUSH(misc, misc)
       case OP_GEMV_N: PUSH(gn, gn)
       case OP_GEMV_T: PUSH(gt, gt)
@@ -229,41 +239,66 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
 
 // Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
 // panels of 64 columns.  Diagonal tiles are overwritten by their inverses
-// (they are used only through them); L(I, j) = A(I, j) G_jj^T; trailing
-// update A(I, J) -= L(I, j) L(J, j)^T.  `breal`: unpadded size (operation
-// count).  Keys (major, group 1, panel j, sub 0..2).
+// G_jj (they are used only through them).  Tile 0 is factored alone; step j
+// then updates the trailing tiles with the unsolved panel j through
+// M_j = G_jj^T G_jj and factors tile j+1 in the same launch (M alternates
+// between the two 64 x 64 buffers at mbuf); finally all panels are solved
+// in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`: unpadded size (operation
+// count).  Keys (major, group 1, j, sub): (0, 0) tile 0, (j, 1) step j,
+// (255, 0) the panel solves.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
-                      int breal) {
+                      int breal, double* mbuf) {
   const int nbk = n / 64;
-  for (int j = 0; j < nbk; ++j) {
-    const double w = (double)std::max(0, std::min(64, breal - j * 64));
-    const double below = (double)std::max(0, breal - (j + 1) * 64);
-    double* Ajj = A + (int64_t)j * 64 * (ld + 1);
+  auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
+  auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
+  {
+    const double w = width(0);
     Step s;
-    s.key = K(major, 1, j, 0);
+    s.key = K(major, 1, 0, 0);
     s.kind = OP_POTRF;
     s.cat = DL_CAT_POTRF_TILE;
     s.flops = w * w * w / 3.0;
-    s.potrf.A = Ajj;
+    s.potrf.A = A;
     s.potrf.lda = ld;
-    s.potrf.Ginv = nullptr;
-    s.potrf.logdiag = logdiag + (int64_t)j * 64;
+    s.potrf.logdiag = logdiag;
     s.potrf.info = info;
-    s.potrf.row0 = row0 + (int64_t)j * 64;
+    s.potrf.row0 = row0;
     s.potrf.mode = 1;
+    s.potrf.M = nbk > 1 ? mbuf : nullptr;
     q.push_back(s);
-    if (j + 1 < nbk) {
+  }
+  for (int j = 0; j + 1 < nbk; ++j) {
+    const double w = width(j), w1 = width(j + 1), bl = below(j);
+    Step s;
+    s.key = K(major, 1, j, 1);
+    s.kind = OP_PANEL;
+    s.cat = DL_CAT_PANEL_SYRK;
+    // the trailing update of a right-looking Cholesky plus the tile factor
+    s.flops = bl * bl * w + w1 * w1 * w1 / 3.0;
+    PanelTask& t = s.panel;
+    t.A = A;
+    t.ld = ld;
+    t.M = mbuf + (j & 1) * 64 * 64;
+    t.Mnext = (j + 2 < nbk) ? mbuf + ((j + 1) & 1) * 64 * 64 : nullptr;
+    t.logdiag = logdiag + (int64_t)(j + 1) * 64;
+    t.info = info;
+    t.row0 = row0 + (int64_t)(j + 1) * 64;
+    t.j = j;
+    t.nbk = nbk;
+    q.push_back(s);
+  }
+  if (nbk > 1) {
+    std::vector<GemmTask> ts;
+    double fl = 0.0;
+    for (int j = 0; j + 1 < nbk; ++j) {
       const int rows = n - (j + 1) * 64;
-      double* panel = A + (int64_t)(j + 1) * 64 + (int64_t)j * 64 * ld;
-      q.push_back(gemm_step(K(major, 1, j, 1), DL_CAT_PANEL_TRSM, below * w * w,
-                            {mk(panel, ld, Ajj, ld, panel, ld, rows, 64, 64,
-                                F_TB | F_BETA0, 1.0, 0.0)}));
-      q.push_back(gemm_step(K(major, 1, j, 2), DL_CAT_PANEL_SYRK, below * below * w,
-                            {mk(panel, ld, panel, ld,
-                                A + (int64_t)(j + 1) * 64 * (ld + 1), ld, rows,
-                                rows, 64, F_TB | F_LOWER, -1.0, 1.0)}));
+      double* Ajj = A + (int64_t)j * 64 * (ld + 1);
+      double* panel = Ajj + 64;
+      ts.push_back(mk(panel, ld, Ajj, ld, panel, ld, rows, 64, 64, F_TB | F_BETA0, 1.0, 0.0));
+      fl += below(j) * width(j) * width(j);
     }
+    q.push_back(gemm_step(K(major, 1, 255, 0), DL_CAT_PANEL_TRSM, fl, std::move(ts)));
   }
 }
 
@@ -337,6 +372,7 @@ struct Inst {
   int64_t* info2 = nullptr;
   double *rhs = nullptr, *x = nullptr, *mu = nullptr, *u = nullptr, *gpart = nullptr;
   double* ttemp[2] = {nullptr, nullptr};
+  double* mbuf[2] = {nullptr, nullptr};  // two 64 x 64 M buffers per factorisation
   double *f = nullptr, *parts = nullptr;
   int64_t* info_out = nullptr;
   // selected inversion
@@ -409,6 +445,7 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
     int kk = DL_KERNEL_OTHER;
     if (L.kind == OP_GEMM || L.kind == OP_GEMM32) kk = DL_KERNEL_GEMM;
     else if (L.kind == OP_POTRF) kk = DL_KERNEL_POTRF_TILE;
+    else if (L.kind == OP_PANEL) kk = DL_KERNEL_PANEL;
     else if (L.kind == OP_GEMV_N || L.kind == OP_GEMV_T) kk = DL_KERNEL_GEMV;
     else if (L.kind == OP_ASM_COLS) kk = DL_KERNEL_ASSEMBLE;
     const int pk = prof_begin(W, L.cat, kk, s);
@@ -420,6 +457,7 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
         break;
       case OP_RES: e = launch_residual(d.res + L.off, L.count, s); break;
       case OP_POTRF: e = launch_potrf_tiles(d.potrf + L.off, L.count, s); break;
+      case OP_PANEL: e = launch_panel_updates(d.panel + L.off, L.count, L.gx, s); break;
       case OP_MISC: e = launch_misc(d.misc + L.off, L.count, s); break;
       case OP_GEMV_N: e = launch_gemv_n(d.gn + L.off, L.count, L.gx, s); break;
       case OP_GEMV_T: e = launch_gemv_t(d.gt + L.off, L.count, L.gx, s); break;
@@ -550,7 +588,7 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     const bool last = (t + 1 == m.nt);
     if (ring && !last) asm_qp(t + 1, K(major, 0));
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
-              (int64_t)t * m.b, m.b);
+              (int64_t)t * m.b, m.b, I.mbuf[w]);
     seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0);
     const int rows_lo = last ? bp : 0;
     const int M = (last ? 0 : bp) + apr;
@@ -942,6 +980,7 @@ static dl_status build_plans(dl_ws* W) {
   };
   up(H.gemm, W->Dd.gemm);
   up(H.potrf, W->Dd.potrf);
+  up(H.panel, W->Dd.panel);
   up(H.misc, W->Dd.misc);
   up(H.gn, W->Dd.gn);
   up(H.gt, W->Dd.gt);
@@ -1019,6 +1058,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(tip, (void**)&I.GPp);
     for (int w = 0; w < 2; ++w) {
       A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttemp[w]);
+      A(sizeof(double) * 2 * 64 * 64, (void**)&I.mbuf[w]);
       A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
     }
     A(sizeof(double) * (I.dim + 1), (void**)&I.theta);

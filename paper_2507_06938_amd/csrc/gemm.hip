@@ -1,10 +1,15 @@
 // FP64 MFMA tile GEMM over a list of tasks (gfx950).
 //
-// One workgroup (256 threads = 4 wave64) computes one 64x64 or 128x128 tile
-// of C for one task of a launch (the tile size is fixed per launch).  Tiles of all tasks of a launch are numbered
-// consecutively; a workgroup finds its task by binary search over the
-// tasks' first tile.  The inner product runs on v_mfma_f64_16x16x4_f64 with
-// operands staged through double-buffered LDS (16-deep k chunks).
+// One workgroup computes one 64x64 tile (4 wave64, 32x32 per wave) or one
+// 128x128 tile (8 wave64, 64x32 per wave; two workgroups fit one compute
+// unit) of C for one task of a launch (the tile size is fixed per launch).
+// Tiles of all tasks of a launch are numbered consecutively; a workgroup
+// finds its task by binary search over the tasks' first tile.  Workgroups
+// are renumbered so that those one XCD receives take consecutive tiles (the
+// operand tiles they share then stay in that XCD's L2).  The inner product
+// runs on v_mfma_f64_16x16x4_f64 with operands staged through
+// double-buffered LDS (16-deep k chunks, next chunk prefetched into
+// registers while the current one is multiplied).
 //
 // MFMA lane layout used (f64 16x16x4, wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; its accumulator register r holds D[l/16 + 4r][l%16]
@@ -31,14 +36,23 @@ __device__ __forceinline__ int find_task(const GemmTask* __restrict__ tasks,
   return lo;
 }
 
-// Stage PER = BR*BK/256 doubles of op(X) per thread: op(X)[r][k] for a
+// Workgroups go to the 8 XCDs in turn (workgroup b to XCD b % 8): map them
+// so that XCD x takes the consecutive tiles [x q + min(x, r), ...) of the
+// nb = 8 q + r tiles.  A bijection of 0..nb-1.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = bid & 7, i = bid >> 3;
+  return x * q + min(x, r) + i;
+}
+
+// Stage PER = BR*BK/NT doubles of op(X) per thread: op(X)[r][k] for a
 // BR-row, BK-deep chunk.  `trans` = X stored K x R (contiguous along k).
-template <int BR>
+template <int BR, int NT>
 __device__ __forceinline__ void load_chunk(const double* __restrict__ X,
                                            int64_t ldx, bool trans, int r0,
                                            int R, int k0, int kend, int tid,
-                                           double (&v)[BR * BK / 256]) {
-  constexpr int PER = BR * BK / 256;
+                                           double (&v)[BR * BK / NT]) {
+  constexpr int PER = BR * BK / NT;
   if (!trans) {
     // X[r + k*ldx]; lanes run along r (BR consecutive rows per k).
     const int r = r0 + (tid % BR);
@@ -60,10 +74,10 @@ __device__ __forceinline__ void load_chunk(const double* __restrict__ X,
   }
 }
 
-template <int BR>
+template <int BR, int NT>
 __device__ __forceinline__ void store_chunk(double* __restrict__ S, bool trans,
-                                            int tid, const double (&v)[BR * BK / 256]) {
-  constexpr int PER = BR * BK / 256;
+                                            int tid, const double (&v)[BR * BK / NT]) {
+  constexpr int PER = BR * BK / NT;
   constexpr int LD = BR + 2;
   if (!trans) {
     const int r = tid % BR;
@@ -94,22 +108,26 @@ __device__ __forceinline__ void tile_coords(const GemmTask& T, int lt, int& tm,
 }
 }  // namespace
 
-// One workgroup of 4 waves computes one BT x BT tile (2 x 2 waves, each
-// (BT/2) x (BT/2) = FxF MFMA blocks of 16 x 16).
-template <int BT>
-__global__ __launch_bounds__(256) void k_gemm_tasks(
+// One workgroup of WM x WN waves computes one BT x BT tile; wave (wm, wn)
+// owns rows wm*BT/WM .. and columns wn*BT/WN .. of it, FM x FN MFMA blocks
+// of 16 x 16.
+template <int BT, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_tasks(
     const GemmTask* __restrict__ tasks, int ntask) {
+  constexpr int NT = WM * WN * 64;
   constexpr int LD = BT + 2;
-  constexpr int F = BT / 32;          // MFMA blocks per wave per dimension
-  constexpr int PER = BT * BK / 256;  // staged doubles per thread per operand
+  constexpr int SM = BT / WM, SN = BT / WN;  // wave sub-tile
+  constexpr int FM = SM / 16, FN = SN / 16;
+  constexpr int PER = BT * BK / NT;  // staged doubles per thread per operand
   __shared__ double As[2][BK * LD];
   __shared__ double Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
-  const int ti = find_task(tasks, ntask, blockIdx.x);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int ti = find_task(tasks, ntask, tile);
   const GemmTask T = tasks[ti];
   int tm, tn;
-  tile_coords(T, blockIdx.x - T.tile_begin, tm, tn);
+  tile_coords(T, tile - T.tile_begin, tm, tn);
   const int m0 = tm * BT;
   const int n0 = tn * BT;
   const bool ta = T.flags & F_TA;
@@ -125,21 +143,21 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(
 
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM, wn = wave / WM;
   const int lrow = lane & 15, lk = lane >> 4;
 
-  v4d acc[F][F];
+  v4d acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < F; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < F; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
   double va[PER], vb[PER];
   if (nchunks > 0) {
-    load_chunk<BT>(T.A, T.lda, ta, m0, T.M, kb, ke, tid, va);
-    load_chunk<BT>(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
-    store_chunk<BT>(As[0], ta, tid, va);
-    store_chunk<BT>(Bs[0], !tb, tid, vb);
+    load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, kb, ke, tid, va);
+    load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
+    store_chunk<BT, NT>(As[0], ta, tid, va);
+    store_chunk<BT, NT>(Bs[0], !tb, tid, vb);
   }
   __syncthreads();
 
@@ -148,29 +166,29 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(
     const bool more = (c + 1) < nchunks;
     if (more) {
       const int k1 = kb + (c + 1) * BK;
-      load_chunk<BT>(T.A, T.lda, ta, m0, T.M, k1, ke, tid, va);
-      load_chunk<BT>(T.B, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
+      load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, k1, ke, tid, va);
+      load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
     }
     const double* __restrict__ as = As[buf];
     const double* __restrict__ bs = Bs[buf];
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + lk;
-      double fa[F], fb[F];
+      double fa[FM], fb[FN];
 #pragma unroll
-      for (int i = 0; i < F; ++i) fa[i] = as[kk * LD + wm * (BT / 2) + i * 16 + lrow];
+      for (int i = 0; i < FM; ++i) fa[i] = as[kk * LD + wm * SM + i * 16 + lrow];
 #pragma unroll
-      for (int j = 0; j < F; ++j) fb[j] = bs[kk * LD + wn * (BT / 2) + j * 16 + lrow];
+      for (int j = 0; j < FN; ++j) fb[j] = bs[kk * LD + wn * SN + j * 16 + lrow];
 #pragma unroll
-      for (int i = 0; i < F; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < F; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i],
                                                            acc[i][j], 0, 0, 0);
     }
     if (more) {
-      store_chunk<BT>(As[buf ^ 1], ta, tid, va);
-      store_chunk<BT>(Bs[buf ^ 1], !tb, tid, vb);
+      store_chunk<BT, NT>(As[buf ^ 1], ta, tid, va);
+      store_chunk<BT, NT>(Bs[buf ^ 1], !tb, tid, vb);
     }
     __syncthreads();
   }
@@ -179,14 +197,14 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(
   const bool lower = T.flags & F_LOWER;
   const bool beta0 = T.flags & F_BETA0;
 #pragma unroll
-  for (int i = 0; i < F; ++i) {
-    const int m = m0 + wm * (BT / 2) + i * 16 + lrow;
+  for (int i = 0; i < FM; ++i) {
+    const int m = m0 + wm * SM + i * 16 + lrow;
     if (m >= T.M) continue;
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
+    for (int j = 0; j < FN; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = n0 + wn * (BT / 2) + j * 16 + lk + 4 * r;
+        const int n = n0 + wn * SN + j * 16 + lk + 4 * r;
         if (n >= T.N || (lower && n > m)) continue;
         double* p = T.C + (int64_t)m + (int64_t)n * T.ldc;
         double v = T.alpha * acc[i][j][r];
@@ -220,10 +238,10 @@ hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
                              int total_tiles, hipStream_t s, int tile) {
   if (total_tiles <= 0) return hipSuccess;
   if (tile == 128)
-    hipLaunchKernelGGL(k_gemm_tasks<128>, dim3(total_tiles), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4>), dim3(total_tiles), dim3(512), 0, s,
                        tasks_dev, ntask);
   else
-    hipLaunchKernelGGL(k_gemm_tasks<64>, dim3(total_tiles), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2>), dim3(total_tiles), dim3(256), 0, s,
                        tasks_dev, ntask);
   return hipGetLastError();
 }
@@ -299,10 +317,11 @@ __global__ __launch_bounds__(256) void k_gemm32_tasks(
   __shared__ float Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
-  const int ti = find_task(tasks, ntask, blockIdx.x);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int ti = find_task(tasks, ntask, tile);
   const GemmTask T = tasks[ti];
   int tm, tn;
-  tile_coords(T, blockIdx.x - T.tile_begin, tm, tn);
+  tile_coords(T, tile - T.tile_begin, tm, tn);
   const int m0 = tm * BT;
   const int n0 = tn * BT;
   const bool ta = T.flags & F_TA;

@@ -21,7 +21,8 @@ DL_QP, DL_QC, DL_BOTH = 0, 1, 2
 DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH, DL_WS_MIXED = 1, 2, 4, 8
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
-KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other")
+KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
+           "k_panel_update")
 STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
           3: "not positive definite", 4: "HIP runtime error",
           5: "call order violated", 6: "refinement did not converge"}

@@ -182,11 +182,18 @@ def surrogate_bfgs(ev: Evaluator, theta0, surrogate: Surrogate, h=1e-3, ftol=1e-
                    gtol=1e-4, max_iter=100, f_target: Optional[float] = None,
                    target_rtol: float = 1e-6, train_steps=200,
                    min_archive: Optional[int] = None) -> Trace:
+    """BFGS in which, after every exact finite-difference step, the surrogate
+    (refitted on all exact pairs so far) proposes the next direction from its
+    own gradient.  Proposals are judged only by exact values (Armijo on the
+    exact F); a rejected proposal hands over to an exact step.  Convergence is
+    decided on exact gradients only: when a surrogate step would stop the run
+    (tiny change), an exact gradient is taken at the point first."""
     t0 = time.perf_counter()
     tr = Trace()
     x = np.asarray(theta0, np.float64).copy()
     d = x.shape[0]
     F, g = fd_gradient(ev, x, h)
+    g_exact = True
     H = np.eye(d)
     min_archive = min_archive or 3 * (2 * d + 1)
 
@@ -194,18 +201,22 @@ def surrogate_bfgs(ev: Evaluator, theta0, surrogate: Surrogate, h=1e-3, ftol=1e-
         tr.theta.append(x.copy()); tr.f.append(F); tr.exact_evals.append(ev.count)
         tr.wall.append(time.perf_counter() - t0); tr.kind.append(kind)
 
+    def converged(rel=None):
+        if f_target is not None:
+            return abs(F - f_target) <= target_rtol * abs(f_target)
+        if np.max(np.abs(g)) <= gtol:
+            return True
+        return rel is not None and rel <= ftol
+
     log("start")
     use_sur = False
+    rel = None
     for _ in range(max_iter):
-        if f_target is not None and abs(F - f_target) <= target_rtol * abs(f_target):
-            break
-        if np.max(np.abs(g)) <= gtol:
+        if g_exact and converged(rel):
             break
         if use_sur and len(ev.archive_f) >= min_archive:
-            # surrogate gradient sets the direction; exact values decide
-            Xa = np.asarray(ev.archive_x)
-            ya = np.asarray(ev.archive_f)
-            surrogate.fit(Xa, ya, steps=train_steps)
+            surrogate.fit(np.asarray(ev.archive_x), np.asarray(ev.archive_f),
+                          steps=train_steps)
             _, gs = surrogate.grad(x)
             p = -H @ gs
             if gs @ p < 0:
@@ -214,12 +225,19 @@ def surrogate_bfgs(ev: Evaluator, theta0, surrogate: Surrogate, h=1e-3, ftol=1e-
                     _, gsn = surrogate.grad(xn)
                     H = _bfgs_update(H, xn - x, gsn - gs)
                     rel = abs(Fn - F) / max(1.0, abs(F))
-                    x, F, g = xn, Fn, gsn
+                    x, F, g, g_exact = xn, Fn, gsn, False
                     log("surrogate")
-                    if f_target is None and rel <= ftol:
+                    if f_target is not None and converged():
                         break
+                    # a tiny change is checked by an exact step next
+                    use_sur = rel > ftol
                     continue
             use_sur = False   # rejected: take an exact step next
+        if not g_exact:
+            F, g = fd_gradient(ev, x, h)
+            g_exact = True
+            if converged():
+                break
         p = -H @ g
         if g @ p >= 0:
             H = np.eye(d)
@@ -233,6 +251,4 @@ def surrogate_bfgs(ev: Evaluator, theta0, surrogate: Surrogate, h=1e-3, ftol=1e-
         x, F, g = xn, Fn2, gn
         log("fd")
         use_sur = True
-        if f_target is None and rel <= ftol:
-            break
     return tr
