@@ -127,7 +127,7 @@ def mixed(D, wl, model, errors, tiles):
     """f_obj with FP32 off-diagonal blocks (FP64 diagonal blocks, tip and
     refinement of the mean) at the same theta."""
     import torch
-    ws = D.Workspace(model, mixed=True)
+    ws = D.Workspace(model, mixed=True, splitk=True)
     if tiles:
         ws.autotune(tiles)
     th = torch.tensor(wl.theta, dtype=torch.float64, device="cuda")
@@ -170,7 +170,7 @@ def main():
 
     wl = W.config1()
     model = D.Model.from_workload(wl)
-    ws = D.Workspace(model, selinv=True)
+    ws = D.Workspace(model, selinv=True, splitk=True)
     tiles = ws.autotune(args.tiles) if args.tiles else None
     dev = torch.device("cuda")
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev)

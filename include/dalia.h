@@ -119,7 +119,13 @@ enum {
                          diagonal blocks and tips); diagonal-block Cholesky,
                          inverses and log-determinants stay FP64; the mean
                          is refined in FP64 against the sparse Q_c
-                         (DL_REFINE_STEPS steps)                           */
+                         (DL_REFINE_STEPS steps)                           */,
+  DL_WS_SPLITK = 16   /* split the long inner dimensions of the FP64 block
+                         products (factor, inverse, selected inversion) into
+                         pieces of 512 summed in a fixed order: more
+                         parallelism for single evaluations; the results
+                         differ from an unsplit workspace by rounding only
+                         and do not depend on the tile sizes chosen         */
 };
 #define DL_REFINE_STEPS 3
 
@@ -216,6 +222,10 @@ dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
  * does).  Call before the first evaluation of a DL_WS_GRAPH workspace. */
 dl_status dl_autotune(dl_ws* ws, const char* cache_path, void* stream);
 dl_status dl_ws_tile_counts(const dl_ws* ws, int64_t* n64, int64_t* n128);
+/* Set the tile (64 or 128) of every matrix-product launch, overriding the
+ * default and any tuned choice (measurement and tests).  DL_EINVAL for
+ * other sizes, DL_ESTATE once a graph has been captured. */
+dl_status dl_ws_force_tile(dl_ws* ws, int32_t tile);
 
 /* ---- surrogate network (learned model of f_obj over theta) ----------------
  * Multi-layer perceptron sizes[0] -> ... -> sizes[n-1] = 1, SiLU between

@@ -40,7 +40,20 @@ enum : int {
   F_A64 = 256,
   F_B64 = 512,
   F_C64 = 1024,
+  // FP64 kernel: split the k range of long tiles (see below)
+  F_SPLIT = 2048,
 };
+
+// Split k.  For an F_SPLIT task with K > GEMM_KSPLIT, the k range [kb, ke) of
+// each tile is cut at the absolute multiples of GEMM_KSPLIT and every piece
+// is one workgroup.  A tile with several pieces writes each raw product to a
+// partial tile (BT x BT doubles, column-major) and a second launch forms
+// C = alpha * (sum of the pieces in k order) + beta * C; a tile with one
+// piece writes C directly.  Cutting at absolute k makes the result
+// independent of the tile size and of the other tasks of the launch.  The
+// launch has kslices workgroups per tile of such a task; those whose piece
+// is empty for their tile return at once.
+constexpr int GEMM_KSPLIT = 512;
 
 struct GemmTask {
   const double* A;
@@ -52,20 +65,30 @@ struct GemmTask {
   int32_t tiles_m, tiles_n;  // filled by finalize_tasks
   int32_t tile_begin;        // first linear tile of this task in its launch
   int32_t ntiles;
+  int32_t kslices;           // workgroups per tile (1 unless split)
+  int32_t unit_begin;        // first workgroup of this task in its launch
+  int32_t pslot_begin;       // first partial tile of this task
+  int32_t red_begin;         // first reduction workgroup of this task
 };
 
 constexpr int GEMM_BM = 64;
 constexpr int GEMM_BN = 64;
 
-// Fill tiles_m/n, ntiles, tile_begin for square tiles of `tile` (64 or 128)
-// rows; return total tiles.
-int finalize_tasks(GemmTask* t, int n, int tile = 64);
+// Fill the tiling fields for square tiles of `tile` (64 or 128) rows; return
+// the number of workgroups of the launch.  nred / nslots (optional) receive
+// the reduction workgroups and the partial tiles a split launch needs.
+int finalize_tasks(GemmTask* t, int n, int tile = 64, int* nred = nullptr,
+                   int64_t* nslots = nullptr);
 
 // Launch a batch of tasks already resident in device memory (tasks_dev) with
-// `total_tiles` workgroups of tile x tile outputs (tile 64 or 128, the value
-// the tasks were finalised with).
-hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
-                             int total_tiles, hipStream_t s, int tile = 64);
+// `units` workgroups of tile x tile outputs (tile 64 or 128, the value the
+// tasks were finalised with).  partials: nslots * tile * tile doubles (may be
+// null when nothing is split).
+hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask, int units,
+                             hipStream_t s, int tile = 64, double* partials = nullptr);
+// The reduction of a split launch (nred workgroups).
+hipError_t launch_gemm_reduce(const GemmTask* tasks_dev, int ntask, int nred,
+                              const double* partials, hipStream_t s, int tile);
 // FP32 MFMA variant; A/B/C pointers are float* unless F_A64/F_B64/F_C64.
 hipError_t launch_gemm32_tasks(const GemmTask* tasks_dev, int ntask,
                                int total_tiles, hipStream_t s, int tile = 64);

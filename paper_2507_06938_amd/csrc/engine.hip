@@ -63,6 +63,7 @@ struct Launch {
   int off, count;     // into the per-kind descriptor array
   int gx, gy, gz;     // grid bounds (max over merged steps)
   int tile;           // GEMM output tile (64 or 128)
+  int nred;           // GEMM: reduction workgroups of a split launch
 };
 
 // Default GEMM tile for a launch (before any measured choice): 128x128 when
@@ -149,8 +150,10 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
         L.off = (int)D.gemm.size();
         for (const Step* st : g) D.gemm.insert(D.gemm.end(), st->gemm.begin(), st->gemm.end());
         L.count = (int)D.gemm.size() - L.off;
+        if (L.kind == OP_GEMM32)  // the FP32 kernel does not split k
+          for (int i = L.off; i < L.off + L.count; ++i) D.gemm[i].flags &= ~F_SPLIT;
         L.tile = default_tile(D.gemm, L.off, L.count);
-        L.gx = finalize_tasks(D.gemm.data() + L.off, L.count, L.tile);
+        L.gx = finalize_tasks(D.gemm.data() + L.off, L.count, L.tile, &L.nred);
         if (L.gx == 0) continue;
         break;
       }
@@ -318,7 +321,7 @@ static void collect_nodes(int lo, int hi, int depth,
 }
 
 static void seq_trtri(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
-                      int n, double* temp, int breal) {
+                      int n, double* temp, int breal, int xf) {
   const int nbk = n / 64;
   auto ext = [&](int lo, int hi) {
     return (double)std::max(0, std::min(hi * 64, breal) - lo * 64);
@@ -337,8 +340,8 @@ static void seq_trtri(std::vector<Step>& q, uint64_t major, double* A, int64_t l
       double* G11 = A + (int64_t)lo * 64 * (ld + 1);
       double* G22 = A + (int64_t)mid * 64 * (ld + 1);
       double* T = temp + (int64_t)lo * 64;
-      tT.push_back(mk(L21, ld, G11, ld, T, n, n2, n1, n1, F_KLO_COL | F_BETA0, 1.0, 0.0));
-      tG.push_back(mk(G22, ld, T, n, L21, ld, n2, n1, n2, F_KHI_ROW | F_BETA0, -1.0, 0.0));
+      tT.push_back(mk(L21, ld, G11, ld, T, n, n2, n1, n1, F_KLO_COL | F_BETA0 | xf, 1.0, 0.0));
+      tG.push_back(mk(G22, ld, T, n, L21, ld, n2, n1, n2, F_KHI_ROW | F_BETA0 | xf, -1.0, 0.0));
       const double r1 = ext(lo, mid), r2 = ext(mid, hi);
       fT += r2 * r1 * r1;
       fG += r1 * r2 * r2;
@@ -389,6 +392,8 @@ struct dl_ws {
   size_t bytes = 0;
   int flags = 0;
   bool sel = false, keep_qp = false, mixed = false;
+  bool splitk = false;
+  double* partials = nullptr;  // split-k partial tiles (shared by all launches)
   int dim_total = 0;
   double* theta_all = nullptr;   // packed theta of all instances
   double* f_all = nullptr;       // [B]
@@ -451,7 +456,11 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
     const int pk = prof_begin(W, L.cat, kk, s);
     hipError_t e = hipSuccess;
     switch (L.kind) {
-      case OP_GEMM: e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile); break;
+      case OP_GEMM:
+        e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile, W->partials);
+        if (e == hipSuccess && L.nred > 0)
+          e = launch_gemm_reduce(d.gemm + L.off, L.count, L.nred, W->partials, s, L.tile);
+        break;
       case OP_GEMM32:
         e = launch_gemm32_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile);
         break;
@@ -583,13 +592,15 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
   };
   if (ring) asm_qp(0, K(0, 3));
   const bool count_inv = (w == 1) && W->sel;
+  // split k of the FP64 products (FP32 launches drop the flag)
+  const int xf = W->splitk ? F_SPLIT : 0;
   for (int t = 0; t < m.nt; ++t) {
     const uint64_t major = (uint64_t)t + 1;
     const bool last = (t + 1 == m.nt);
     if (ring && !last) asm_qp(t + 1, K(major, 0));
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
               (int64_t)t * m.b, m.b, I.mbuf[w]);
-    seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0);
+    seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0, xf);
     const int rows_lo = last ? bp : 0;
     const int M = (last ? 0 : bp) + apr;
     if (M <= 0) continue;
@@ -605,7 +616,7 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     };
     q.push_back(gs(K(major, 3), DL_CAT_TRSM, mreal * b * b,
                    {mk(BRo(src, rows_lo), ldbr, Dt(t), bp, BRo(nw, rows_lo), ldbr, M, bp,
-                       bp, F_TB | F_KHI_COL | F_BETA0 | x64, 1.0, 0.0)}));
+                       bp, F_TB | F_KHI_COL | F_BETA0 | x64 | xf, 1.0, 0.0)}));
     if (!ring) {
       spare = slot[t];
       slot[t] = nw;
@@ -616,14 +627,14 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     std::vector<GemmTask> up;
     if (!last) {
       up.push_back(mk(BRt, ldbr, BRt, ldbr, Dt(t + 1), bp, bp, bp, bp,
-                      F_TB | F_LOWER | c64, -1.0, 1.0));
+                      F_TB | F_LOWER | c64 | xf, -1.0, 1.0));
       if (apr)
         up.push_back(mk(RRt, ldbr, BRt, ldbr, BRo(slot[t + 1], bp), ldbr, apr, bp, bp,
-                        F_TB, -1.0, 1.0));
+                        F_TB | xf, -1.0, 1.0));
     }
     if (apr)
       up.push_back(mk(RRt, ldbr, RRt, ldbr, P, m.ap, apr, apr, bp,
-                      F_TB | F_LOWER | c64, -1.0, 1.0));
+                      F_TB | F_LOWER | c64 | xf, -1.0, 1.0));
     const double upd = (last ? 0.0 : b * b * b + 2.0 * ar * b * b) + ar * ar * b;
     q.push_back(gs(K(major, 4), DL_CAT_UPDATE, upd, up));
   }
@@ -765,6 +776,7 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     return mx ? gemm32_step(key, cat, fl, std::move(ts)) : gemm_step(key, cat, fl, std::move(ts));
   };
   const int fB64 = mx ? F_B64 : 0, fA64 = mx ? F_A64 : 0, fC64 = mx ? F_C64 : 0;
+  const int xf = W->splitk ? F_SPLIT : 0;  // dropped by FP32 launches
   double* WVr = eoff(I.WV, bp, eb);  // arrow rows of WV
   for (int k = 0; k < 2; ++k)
     q.push_back(misc_step(K(0, 0, 0, k), DL_CAT_SELINV, MJ_FILL, I.XC[k], nullptr,
@@ -793,25 +805,26 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
       if (ap > 0)
         q.push_back(gs(K(mj, 1), DL_CAT_SELINV, a * b * b,
                        {mk(BRo(t, bp), ld, G(t), bp, WVr, ld, ap, bp, bp,
-                           F_KLO_COL | F_BETA0 | fB64, 1.0, 0.0)}));
+                           F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0)}));
     } else {
       // [W_t; V_t] = [B_t; R_t]_factor G_t
       q.push_back(gs(K(mj, 1), DL_CAT_SELINV, (b + a) * b * b,
                      {mk(BRs(t), ld, G(t), bp, I.WV, ld, bp + ap, bp, bp,
-                         F_KLO_COL | F_BETA0 | fB64, 1.0, 0.0)}));
+                         F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0)}));
     }
     const double ba = b + a;
     // [X_{t+1,t}; X_{P,t}] = -[[X_{t+1,t+1}, X_{t+1,P}]; [X_{P,t+1}, X_P]] WV
     q.push_back(gs(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
                    {mk(I.XC[cur], ld, I.WV, ld, I.Y, ld, bp + ap, bp, bp + ap,
-                       F_BETA0 | fA64 | fC64, -1.0, 0.0)}));
+                       F_BETA0 | fA64 | fC64 | xf, -1.0, 0.0)}));
     // X_tt = G_t^T G_t - Y^T WV   (lower triangle)
     q.push_back(gemm_step(K(mj, 3), DL_CAT_SELINV, b * b * b / 3.0,
                           {mk(G(t), bp, G(t), bp, I.XC[nxt], ld, bp, bp, bp,
-                              F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0, 1.0, 0.0)}));
+                              F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0 | xf, 1.0,
+                              0.0)}));
     q.push_back(gs(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
                    {mk(I.Y, ld, I.WV, ld, I.XC[nxt], ld, bp, bp, bp + ap,
-                       F_TA | F_LOWER | fA64 | fC64, -1.0, 1.0)}));
+                       F_TA | F_LOWER | fA64 | fC64 | xf, -1.0, 1.0)}));
     Step fin;
     fin.key = K(mj, 5);
     fin.kind = OP_FINISH;
@@ -964,8 +977,21 @@ static dl_status build_plans(dl_ws* W) {
   append(W->eval_p, W->solve_p);
   append(W->eval_p, W->refine_p);
   append(W->eval_p, W->post_p);
+  // split-k partial tiles: the largest need of any launch, for either tile
+  int64_t pmax = 0;
+  for (const Launch& L : W->table) {
+    if (L.kind != OP_GEMM) continue;
+    for (int tile : {64, 128}) {
+      std::vector<GemmTask> tmp(H.gemm.begin() + L.off, H.gemm.begin() + L.off + L.count);
+      int64_t slots = 0;
+      (void)finalize_tasks(tmp.data(), L.count, tile, nullptr, &slots);
+      pmax = std::max(pmax, slots * tile * tile);
+    }
+  }
   // upload descriptor arrays
   dl_status st = DL_OK;
+  if (pmax > 0)
+    st = dev_alloc(W->allocs, sizeof(double) * pmax, (void**)&W->partials, &W->bytes);
   auto up = [&](auto& vec, auto*& dptr) {
     using T = typename std::remove_reference<decltype(vec)>::type::value_type;
     if (st != DL_OK) return;
@@ -1017,6 +1043,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->keep_qp = (flags & DL_WS_KEEP_QP) != 0;
   W->mixed = (flags & DL_WS_MIXED) != 0;
   W->use_graph = (flags & DL_WS_GRAPH) != 0;
+  W->splitk = (flags & DL_WS_SPLITK) != 0;
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
   auto A = [&](size_t bytes, void** p) {
@@ -1416,7 +1443,7 @@ static std::string gemm_signature(const dl_ws* W, const Launch& L) {
 
 static dl_status retile(dl_ws* W, Launch& L, int tile) {
   L.tile = tile;
-  L.gx = finalize_tasks(W->H.gemm.data() + L.off, L.count, tile);
+  L.gx = finalize_tasks(W->H.gemm.data() + L.off, L.count, tile, &L.nred);
   DL_HIP_CHECK(hipMemcpy(W->Dd.gemm + L.off, W->H.gemm.data() + L.off,
                          sizeof(GemmTask) * L.count, hipMemcpyHostToDevice));
   return DL_OK;
@@ -1474,6 +1501,17 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
     for (const auto& sig : fresh) out << sig << " " << best[sig] << "\n";
   }
   return st;
+}
+
+extern "C" dl_status dl_ws_force_tile(dl_ws* W, int32_t tile) {
+  if (!W || (tile != 64 && tile != 128)) return DL_EINVAL;
+  if (W->graph_exec) return DL_ESTATE;
+  for (Launch& L : W->table) {
+    if (L.kind != OP_GEMM && L.kind != OP_GEMM32) continue;
+    const dl_status st = retile(W, L, tile);
+    if (st != DL_OK) return st;
+  }
+  return DL_OK;
 }
 
 // Number of GEMM launches of the workspace using each tile size.

@@ -92,28 +92,65 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ S, bool trans,
   }
 }
 
+// Tile order within a task: bands of GROUP tile rows, each band swept
+// column by column (lower-triangular tasks: the columns left of the band,
+// then its triangular diagonal block).  Consecutive tiles -- and so the
+// tiles one XCD holds at a time -- then form a compact patch whose operand
+// rows and columns are reused from that XCD's L2.
+constexpr int GROUP = 8;
+
 __device__ __forceinline__ void tile_coords(const GemmTask& T, int lt, int& tm,
                                             int& tn) {
   if (T.flags & F_LOWER) {
-    // row-major enumeration of the lower triangle of a square tile grid
-    int I = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= lt) ++I;
-    while (I * (I + 1) / 2 > lt) --I;
-    tm = I;
-    tn = lt - I * (I + 1) / 2;
+    const int nt = T.tiles_m;  // square tile grid
+    int g = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5) / GROUP;
+    while (g > 0 && (g * GROUP) * (g * GROUP + 1) / 2 > lt) --g;
+    while (((g + 1) * GROUP) * ((g + 1) * GROUP + 1) / 2 <= lt) ++g;
+    const int r0 = g * GROUP;
+    const int gm = min(nt - r0, GROUP);
+    int loc = lt - r0 * (r0 + 1) / 2;
+    if (loc < r0 * gm) {
+      tm = r0 + loc % gm;
+      tn = loc / gm;
+      return;
+    }
+    loc -= r0 * gm;
+    int c = 0;
+    while (loc >= gm - c) {
+      loc -= gm - c;
+      ++c;
+    }
+    tm = r0 + c + loc;
+    tn = r0 + c;
   } else {
-    tm = lt % T.tiles_m;
-    tn = lt / T.tiles_m;
+    const int gs = GROUP * T.tiles_n;
+    const int first = (lt / gs) * GROUP;
+    const int gm = min(T.tiles_m - first, GROUP);
+    const int loc = lt % gs;
+    tm = first + loc % gm;
+    tn = loc / gm;
   }
 }
 }  // namespace
 
 // One workgroup of WM x WN waves computes one BT x BT tile; wave (wm, wn)
 // owns rows wm*BT/WM .. and columns wn*BT/WN .. of it, FM x FN MFMA blocks
-// of 16 x 16.
-template <int BT, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_tasks(
-    const GemmTask* __restrict__ tasks, int ntask) {
+// of 16 x 16.  MINW: waves per SIMD the register budget must allow.
+// Task of workgroup (or reduction workgroup) `u`: the last task whose
+// first index is <= u (tasks with no work share their successor's first).
+__device__ __forceinline__ int find_unit_task(const GemmTask* __restrict__ tasks,
+                                              int ntask, int u, bool red) {
+  int lo = 0, hi = ntask - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((red ? tasks[mid].red_begin : tasks[mid].unit_begin) <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int BT, int WM, int WN, int MINW>
+__global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
+    const GemmTask* __restrict__ tasks, int ntask, double* __restrict__ partials) {
   constexpr int NT = WM * WN * 64;
   constexpr int LD = BT + 2;
   constexpr int SM = BT / WM, SN = BT / WN;  // wave sub-tile
@@ -123,11 +160,13 @@ __global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_task
   __shared__ double Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int ti = find_task(tasks, ntask, tile);
+  const int wid = xcd_tile(blockIdx.x, gridDim.x);
+  const int ti = find_unit_task(tasks, ntask, wid, false);
   const GemmTask T = tasks[ti];
+  const int local = wid - T.unit_begin;
+  const int lt = local / T.kslices, sl = local % T.kslices;
   int tm, tn;
-  tile_coords(T, tile - T.tile_begin, tm, tn);
+  tile_coords(T, lt, tm, tn);
   const int m0 = tm * BT;
   const int n0 = tn * BT;
   const bool ta = T.flags & F_TA;
@@ -139,6 +178,17 @@ __global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_task
   if (T.flags & F_KLO_ROW) kb = max(kb, m0);
   if (T.flags & F_KHI_ROW) ke = min(ke, m0 + BT);
   kb = (kb / BK) * BK;
+  int slot = -1;  // partial tile of this piece (split tiles only)
+  if (T.kslices > 1 && ke > kb) {
+    const int s0 = kb / GEMM_KSPLIT;
+    const int npieces = (ke - 1) / GEMM_KSPLIT - s0 + 1;
+    if (sl >= npieces) return;  // no piece here for this tile
+    if (npieces > 1) slot = T.pslot_begin + lt * T.kslices + sl;
+    kb = max(kb, (s0 + sl) * GEMM_KSPLIT);
+    ke = min(ke, (s0 + sl + 1) * GEMM_KSPLIT);
+  } else if (sl > 0) {
+    return;
+  }
   const int nchunks = ke > kb ? (ke - kb + BK - 1) / BK : 0;
 
   const int lane = tid & 63;
@@ -193,6 +243,18 @@ __global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_task
     __syncthreads();
   }
 
+  if (slot >= 0) {
+    // one piece of a split tile: the raw product, tile-local column-major
+    double* P = partials + (int64_t)slot * BT * BT;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          P[(wm * SM + i * 16 + lrow) + (wn * SN + j * 16 + lk + 4 * r) * BT] = acc[i][j][r];
+    return;
+  }
   // epilogue: lane holds C[m][n0' + lk + 4r], m = row of lane
   const bool lower = T.flags & F_LOWER;
   const bool beta0 = T.flags & F_BETA0;
@@ -215,8 +277,45 @@ __global__ __launch_bounds__(WM * WN * 64, (BT == 128 ? 2 : 1)) void k_gemm_task
   }
 }
 
-int finalize_tasks(GemmTask* t, int n, int tile) {
-  int total = 0;
+// C = alpha * sum of the pieces + beta * C for the split tiles, one
+// workgroup per tile; the pieces are added in k order.
+template <int BT>
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict__ tasks,
+                                                     int ntask,
+                                                     const double* __restrict__ partials) {
+  const int ti = find_unit_task(tasks, ntask, blockIdx.x, true);
+  const GemmTask T = tasks[ti];
+  const int lt = blockIdx.x - T.red_begin;
+  int tm, tn;
+  tile_coords(T, lt, tm, tn);
+  const int m0 = tm * BT, n0 = tn * BT;
+  int kb = 0, ke = T.K;
+  if (T.flags & F_KLO_COL) kb = max(kb, n0);
+  if (T.flags & F_KHI_COL) ke = min(ke, n0 + BT);
+  if (T.flags & F_KLO_ROW) kb = max(kb, m0);
+  if (T.flags & F_KHI_ROW) ke = min(ke, m0 + BT);
+  kb = (kb / BK) * BK;
+  if (ke <= kb) return;
+  const int npieces = (ke - 1) / GEMM_KSPLIT - kb / GEMM_KSPLIT + 1;
+  if (npieces < 2) return;  // written directly by the product launch
+  const bool lower = T.flags & F_LOWER;
+  const bool beta0 = T.flags & F_BETA0;
+  const double* P = partials + (int64_t)(T.pslot_begin + lt * T.kslices) * BT * BT;
+  for (int e = threadIdx.x; e < BT * BT; e += 256) {
+    const int m = m0 + e % BT, n = n0 + e / BT;
+    if (m >= T.M || n >= T.N || (lower && n > m)) continue;
+    double sum = P[e];
+    for (int q = 1; q < npieces; ++q) sum += P[(int64_t)q * BT * BT + e];
+    double* c = T.C + (int64_t)m + (int64_t)n * T.ldc;
+    double v = T.alpha * sum;
+    if (!beta0) v += T.beta * (*c);
+    *c = v;
+  }
+}
+
+int finalize_tasks(GemmTask* t, int n, int tile, int* nred, int64_t* nslots) {
+  int total = 0, units = 0, red = 0;
+  int64_t slots = 0;
   for (int i = 0; i < n; ++i) {
     t[i].tiles_m = (t[i].M + tile - 1) / tile;
     t[i].tiles_n = (t[i].N + tile - 1) / tile;
@@ -230,19 +329,43 @@ int finalize_tasks(GemmTask* t, int n, int tile) {
     }
     t[i].tile_begin = total;
     total += t[i].ntiles;
+    const bool split = (t[i].flags & F_SPLIT) && t[i].K > GEMM_KSPLIT;
+    t[i].kslices = split ? (t[i].K + GEMM_KSPLIT - 1) / GEMM_KSPLIT : 1;
+    t[i].unit_begin = units;
+    units += t[i].ntiles * t[i].kslices;
+    t[i].pslot_begin = (int32_t)slots;
+    t[i].red_begin = red;
+    if (split) {
+      slots += (int64_t)t[i].ntiles * t[i].kslices;
+      red += t[i].ntiles;
+    }
   }
-  return total;
+  if (nred) *nred = red;
+  if (nslots) *nslots = slots;
+  return units;
 }
 
-hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask,
-                             int total_tiles, hipStream_t s, int tile) {
-  if (total_tiles <= 0) return hipSuccess;
+hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask, int units,
+                             hipStream_t s, int tile, double* partials) {
+  if (units <= 0) return hipSuccess;
   if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4>), dim3(total_tiles), dim3(512), 0, s,
-                       tasks_dev, ntask);
+    hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4, 4>), dim3(units), dim3(512), 0, s,
+                       tasks_dev, ntask, partials);
   else
-    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2>), dim3(total_tiles), dim3(256), 0, s,
-                       tasks_dev, ntask);
+    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2, 1>), dim3(units), dim3(256), 0, s,
+                       tasks_dev, ntask, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_reduce(const GemmTask* tasks_dev, int ntask, int nred,
+                              const double* partials, hipStream_t s, int tile) {
+  if (nred <= 0) return hipSuccess;
+  if (tile == 128)
+    hipLaunchKernelGGL(k_gemm_reduce<128>, dim3(nred), dim3(256), 0, s, tasks_dev, ntask,
+                       partials);
+  else
+    hipLaunchKernelGGL(k_gemm_reduce<64>, dim3(nred), dim3(256), 0, s, tasks_dev, ntask,
+                       partials);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
 
 DL_QP, DL_QC, DL_BOTH = 0, 1, 2
 DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH, DL_WS_MIXED = 1, 2, 4, 8
+DL_WS_SPLITK = 16
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
@@ -83,6 +84,7 @@ def lib():
             "dl_ws_profile_begin": (i32, [vp, i32, i32]),
             "dl_autotune": (i32, [vp, C.c_char_p, vp]),
             "dl_ws_tile_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+            "dl_ws_force_tile": (i32, [vp, i32]),
             "dl_mlp_create": (i32, [vp, i32, i32, C.POINTER(vp)]),
             "dl_mlp_destroy": (None, [vp]),
             "dl_mlp_params": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)]),
@@ -176,13 +178,14 @@ class Workspace:
     together.  Per-instance vectors are packed in instance order."""
 
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
-                 graph: bool = False, mixed: bool = False):
+                 graph: bool = False, mixed: bool = False, splitk: bool = False):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
         self.model = self.models[0]
         flags = ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
-                 | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0))
+                 | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
+                 | (DL_WS_SPLITK if splitk else 0))
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
         _check("dl_ws_create_batch",
@@ -260,6 +263,15 @@ class Workspace:
         """Measure and fix the GEMM tile of every launch (see dl_autotune)."""
         p = cache_path.encode() if cache_path else None
         _check("dl_autotune", lib().dl_autotune(self.h, p, _stream()))
+        a, b = C.c_int64(), C.c_int64()
+        _check("dl_ws_tile_counts", lib().dl_ws_tile_counts(self.h, C.byref(a), C.byref(b)))
+        return {"tile64": a.value, "tile128": b.value}
+
+    def force_tile(self, tile: int):
+        """Use `tile` (64 or 128) for every matrix-product launch."""
+        _check("dl_ws_force_tile", lib().dl_ws_force_tile(self.h, int(tile)))
+
+    def tile_counts(self) -> dict:
         a, b = C.c_int64(), C.c_int64()
         _check("dl_ws_tile_counts", lib().dl_ws_tile_counts(self.h, C.byref(a), C.byref(b)))
         return {"tile64": a.value, "tile128": b.value}

@@ -25,15 +25,16 @@ def D():
     return dalia
 
 
+@pytest.mark.parametrize("splitk", [False, True])
 @pytest.mark.parametrize("name,make", [("c1", W.config1), ("c2", W.config2)])
-def test_fullsize_against_banded_oracle(D, name, make):
+def test_fullsize_against_banded_oracle(D, name, make, splitk):
     path = os.path.join(GOLD, f"{name}_golden.json")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     g = json.load(open(path))
     wl = make()
     model = D.Model.from_workload(wl)
-    ws = D.Workspace(model, selinv=True)
+    ws = D.Workspace(model, selinv=True, splitk=splitk)
     f, parts, info = ws.fobj(np.asarray(g["theta"]))
     mu = ws.mean()
     var = ws.selinv()
