@@ -291,7 +291,8 @@ enum {
   DL_KERNEL_GEMV = 2,        /* solve matrix-vector products             */
   DL_KERNEL_ASSEMBLE = 3,    /* assembly                                 */
   DL_KERNEL_OTHER = 4,
-  DL_KERNEL_PANEL = 5        /* fused trailing update + next tile factor */
+  DL_KERNEL_PANEL = 5,       /* fused trailing update + next tile factor */
+  DL_KERNEL_GEMM_REDUCE = 6  /* sum of the pieces of split-k products    */
 };
 dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
                               int32_t max_launches);

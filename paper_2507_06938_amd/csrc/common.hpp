@@ -51,8 +51,9 @@ enum : int {
 // C = alpha * (sum of the pieces in k order) + beta * C; a tile with one
 // piece writes C directly.  Cutting at absolute k makes the result
 // independent of the tile size and of the other tasks of the launch.  The
-// launch has kslices workgroups per tile of such a task; those whose piece
-// is empty for their tile return at once.
+// launch has kslices workgroups per tile of such a task (ordered piece by
+// piece over the task's tiles); those whose piece is empty for their tile
+// return at once.
 constexpr int GEMM_KSPLIT = 512;
 
 struct GemmTask {

@@ -458,8 +458,15 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
     switch (L.kind) {
       case OP_GEMM:
         e = launch_gemm_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile, W->partials);
-        if (e == hipSuccess && L.nred > 0)
+        if (e == hipSuccess && L.nred > 0) {
+          // the reduction of a split launch: its own record (kernel-level
+          // profiles then see the product kernel alone)
+          prof_end(W, pk, L.flops, L.bytes, s);
+          const int pr = prof_begin(W, L.cat, DL_KERNEL_GEMM_REDUCE, s);
           e = launch_gemm_reduce(d.gemm + L.off, L.count, L.nred, W->partials, s, L.tile);
+          prof_end(W, pr, 0.0, 0.0, s);
+          return e;
+        }
         break;
       case OP_GEMM32:
         e = launch_gemm32_tasks(d.gemm + L.off, L.count, L.gx, s, L.tile);
@@ -777,7 +784,8 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   };
   const int fB64 = mx ? F_B64 : 0, fA64 = mx ? F_A64 : 0, fC64 = mx ? F_C64 : 0;
   const int xf = W->splitk ? F_SPLIT : 0;  // dropped by FP32 launches
-  double* WVr = eoff(I.WV, bp, eb);  // arrow rows of WV
+  // [W_t; V_t] of every step, eb bytes per element, ld x bp each
+  auto WVt = [&](int t) { return eoff(I.WV, (int64_t)t * ld * bp, eb); };
   for (int k = 0; k < 2; ++k)
     q.push_back(misc_step(K(0, 0, 0, k), DL_CAT_SELINV, MJ_FILL, I.XC[k], nullptr,
                           ld * ld, 0.0));
@@ -794,36 +802,49 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     dg.misc.lds = ld;
     q.push_back(dg);
   }
+  // [W_t; V_t] = [B_t; R_t]_factor G_t for all t: independent of the
+  // recursion, so one launch (the last step has only the arrow rows; its
+  // W block is zero)
+  {
+    const int tl = m.nt - 1;
+    q.push_back(misc_step(K(0, 3), DL_CAT_SELINV, MJ_FILL, WVt(tl), nullptr,
+                          ld * bp * eb / 8));
+    std::vector<GemmTask> wv;
+    double fl = 0.0;
+    for (int t = 0; t < m.nt; ++t) {
+      if (t == tl) {
+        if (ap > 0) {
+          wv.push_back(mk(BRo(t, bp), ld, G(t), bp, eoff(WVt(t), bp, eb), ld, ap, bp, bp,
+                          F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0));
+          fl += a * b * b;
+        }
+      } else {
+        wv.push_back(mk(BRs(t), ld, G(t), bp, WVt(t), ld, bp + ap, bp, bp,
+                        F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0));
+        fl += (b + a) * b * b;
+      }
+    }
+    if (!wv.empty()) q.push_back(gs(K(0, 4), DL_CAT_SELINV, fl, wv));
+  }
   int cur = 0;
   for (int t = m.nt - 1; t >= 0; --t) {
     const uint64_t mj = 1 + (uint64_t)(m.nt - 1 - t);
     const int nxt = cur ^ 1;
     const bool last = (t + 1 == m.nt);
-    if (last) {
-      q.push_back(misc_step(K(mj, 0), DL_CAT_SELINV, MJ_FILL, I.WV, nullptr,
-                            ld * bp * eb / 8));
-      if (ap > 0)
-        q.push_back(gs(K(mj, 1), DL_CAT_SELINV, a * b * b,
-                       {mk(BRo(t, bp), ld, G(t), bp, WVr, ld, ap, bp, bp,
-                           F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0)}));
-    } else {
-      // [W_t; V_t] = [B_t; R_t]_factor G_t
-      q.push_back(gs(K(mj, 1), DL_CAT_SELINV, (b + a) * b * b,
-                     {mk(BRs(t), ld, G(t), bp, I.WV, ld, bp + ap, bp, bp,
-                         F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0)}));
-    }
     const double ba = b + a;
     // [X_{t+1,t}; X_{P,t}] = -[[X_{t+1,t+1}, X_{t+1,P}]; [X_{P,t+1}, X_P]] WV
+    // and, independent of it (same launch when both run in FP64),
+    // X_tt = G_t^T G_t (lower triangle)
     q.push_back(gs(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
-                   {mk(I.XC[cur], ld, I.WV, ld, I.Y, ld, bp + ap, bp, bp + ap,
+                   {mk(I.XC[cur], ld, WVt(t), ld, I.Y, ld, bp + ap, bp, bp + ap,
                        F_BETA0 | fA64 | fC64 | xf, -1.0, 0.0)}));
-    // X_tt = G_t^T G_t - Y^T WV   (lower triangle)
-    q.push_back(gemm_step(K(mj, 3), DL_CAT_SELINV, b * b * b / 3.0,
+    q.push_back(gemm_step(K(mj, 2), DL_CAT_SELINV, b * b * b / 3.0,
                           {mk(G(t), bp, G(t), bp, I.XC[nxt], ld, bp, bp, bp,
                               F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0 | xf, 1.0,
                               0.0)}));
+    // X_tt -= Y^T WV   (lower triangle)
     q.push_back(gs(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
-                   {mk(I.Y, ld, I.WV, ld, I.XC[nxt], ld, bp, bp, bp + ap,
+                   {mk(I.Y, ld, WVt(t), ld, I.XC[nxt], ld, bp, bp, bp + ap,
                        F_TA | F_LOWER | fA64 | fC64 | xf, -1.0, 1.0)}));
     Step fin;
     fin.key = K(mj, 5);
@@ -1101,7 +1122,8 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(sizeof(double) * I.ldbr, (void**)&I.u);
     A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
     if (W->sel) {
-      A(sizeof(double) * I.ldbr * bp, (void**)&I.WV);
+      // [W_t; V_t] = [B_t; R_t] G_t of every time step (formed up front)
+      A((size_t)I.eb * m.nt * I.ldbr * bp, (void**)&I.WV);
       A(sizeof(double) * I.ldbr * bp, (void**)&I.Y);
       A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[0]);
       A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[1]);

@@ -163,8 +163,10 @@ __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
   const int wid = xcd_tile(blockIdx.x, gridDim.x);
   const int ti = find_unit_task(tasks, ntask, wid, false);
   const GemmTask T = tasks[ti];
+  // slice-major: the workgroups of one XCD take one k piece of a compact
+  // patch of tiles
   const int local = wid - T.unit_begin;
-  const int lt = local / T.kslices, sl = local % T.kslices;
+  const int lt = local % T.ntiles, sl = local / T.ntiles;
   int tm, tn;
   tile_coords(T, lt, tm, tn);
   const int m0 = tm * BT;

@@ -23,7 +23,7 @@ DL_WS_SPLITK = 16
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
-           "k_panel_update")
+           "k_panel_update", "k_gemm_reduce")
 STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
           3: "not positive definite", 4: "HIP runtime error",
           5: "call order violated", 6: "refinement did not converge"}
