@@ -8,9 +8,14 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 The paper minimises -f_obj with BFGS (Nocedal & Wright) and approximates
 each partial derivative by a central difference with step h; the
 2*dim(theta)+1 evaluations of one gradient are independent.  The paper does
-not fix the line search or the stopping rule; read here as Armijo
-backtracking (c1 = 1e-4, halving) and stop when the relative change of f is
-at most ftol or the largest gradient component is at most gtol.
+not fix the line search, the initial inverse Hessian or the stopping rule;
+read here as: the search direction is capped at length max_step (theta holds
+log-scale parameters, so a unit step already changes a scale by e), the
+initial inverse Hessian is the identity rescaled by y^T s / y^T y before the
+first update (Nocedal & Wright, Sec. 6.1), Armijo backtracking (c1 = 1e-4,
+halving), one restart along the steepest-descent direction when the line
+search fails, and stop when the relative change of f is at most ftol or the
+largest gradient component is at most gtol.
 """
 from __future__ import annotations
 
@@ -41,8 +46,14 @@ def central_gradient(f, theta, h: float = 1e-3) -> np.ndarray:
     return central_gradient_from_values([f(p) for p in pts], h)
 
 
+def _capped(p, max_step):
+    nrm = float(np.linalg.norm(p))
+    return p * (max_step / nrm) if nrm > max_step else p
+
+
 def bfgs_minimize(fun_and_grad, x0, max_iter: int = 100, ftol: float = 1e-6,
-                  gtol: float = 1e-4, c1: float = 1e-4, max_halvings: int = 30):
+                  gtol: float = 1e-4, c1: float = 1e-4, max_halvings: int = 30,
+                  max_step: float = 1.0):
     """Minimise a smooth function given f and its gradient at a point.
 
     fun_and_grad(x) -> (f, g).  Inverse-Hessian BFGS update
@@ -52,6 +63,7 @@ def bfgs_minimize(fun_and_grad, x0, max_iter: int = 100, ftol: float = 1e-6,
     f, g = fun_and_grad(x)
     n = x.shape[0]
     H = np.eye(n)
+    first = True
     hist = [dict(x=x.copy(), f=f, gnorm=float(np.max(np.abs(g))), evals=1)]
     for it in range(max_iter):
         if np.max(np.abs(g)) <= gtol:
@@ -60,21 +72,30 @@ def bfgs_minimize(fun_and_grad, x0, max_iter: int = 100, ftol: float = 1e-6,
         if g @ p >= 0:          # not a descent direction: restart
             H = np.eye(n)
             p = -g
-        alpha = 1.0
         accepted = False
-        for _ in range(max_halvings):
-            xn = x + alpha * p
-            fn, gn = fun_and_grad(xn)
-            if np.isfinite(fn) and fn <= f + c1 * alpha * (g @ p):
-                accepted = True
+        for attempt in range(2):
+            p = _capped(p, max_step)
+            alpha = 1.0
+            for _ in range(max_halvings):
+                xn = x + alpha * p
+                fn, gn = fun_and_grad(xn)
+                if np.isfinite(fn) and fn <= f + c1 * alpha * (g @ p):
+                    accepted = True
+                    break
+                alpha *= 0.5
+            if accepted or attempt == 1:
                 break
-            alpha *= 0.5
+            H = np.eye(n)        # one restart along steepest descent
+            p = -g
         if not accepted:
             break
         s = xn - x
         y = gn - g
         ys = y @ s
         if ys > 1e-12:
+            if first:
+                H = (ys / (y @ y)) * np.eye(n)
+                first = False
             r = 1.0 / ys
             I = np.eye(n)
             H = (I - r * np.outer(s, y)) @ H @ (I - r * np.outer(y, s)) + r * np.outer(s, s)

@@ -1,0 +1,116 @@
+"""Mode-search study (Eq. 9): plain batched finite-difference BFGS against the
+surrogate-guided variant, from seeded starts theta_0 = theta* + 0.25 z.
+
+    python -m paper_2507_06938_amd.opt_study --nx 12 --nt 12 --runs 16
+
+theta* and F* = -f_obj(theta*) come from a reference FD-BFGS run started at
+the generator's theta and driven to a small gradient.  Each method then runs
+from every start until |F - F*| <= rtol |F*| (or its iteration cap), and the
+study reports exact f_obj evaluations and wall time per run.  Every f_obj
+value comes from the batched GPU evaluator; the surrogate network is trained
+by the library's MLP kernels.  Prints one JSON document.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+
+def main(argv=None):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import workloads as W
+    from . import dalia as D
+    from . import optimize as O
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--nx", type=int, default=12)
+    ap.add_argument("--nt", type=int, default=12)
+    ap.add_argument("--nv", type=int, default=3)
+    ap.add_argument("--nr", type=int, default=2)
+    ap.add_argument("--m-per", type=int, default=0,
+                    help="observations (0: nv * nt * nx^2, one per node and step)")
+    ap.add_argument("--runs", type=int, default=16)
+    ap.add_argument("--scale", type=float, default=0.25)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    m_per = args.m_per or args.nv * args.nt * args.nx * args.nx
+    wl = W.scaled(f"opt_{args.nv}v_{args.nx}x{args.nx}_nt{args.nt}", args.nx, args.nt,
+                  args.nv, args.nr, m_per, seed=args.seed)
+    model = D.Model.from_workload(wl)
+    d = wl.dim_theta
+    B = 2 * d + 1
+    ev = O.Evaluator(model, B, graph=True)
+
+    # reference optimum
+    t0 = time.perf_counter()
+    ref = O.fd_bfgs(ev, wl.theta, h=1e-3, ftol=0.0, gtol=1e-5, max_iter=400)
+    theta_star, F_star = ref.theta[-1], ref.f[-1]
+    t_ref = time.perf_counter() - t0
+
+    def fresh():
+        ev.count = 0
+        ev.archive_x.clear()
+        ev.archive_f.clear()
+
+    runs = []
+    rng = np.random.default_rng(12345 + args.seed)
+    starts = [theta_star + args.scale * rng.standard_normal(d) for _ in range(args.runs)]
+    for k, th0 in enumerate(starts):
+        row = {"run": k}
+        fresh()
+        t0 = time.perf_counter()
+        tr = O.fd_bfgs(ev, th0, h=1e-3, ftol=0.0, gtol=0.0, max_iter=args.max_iter,
+                       f_target=F_star, target_rtol=args.rtol)
+        torch.cuda.synchronize()
+        row["fd"] = {"exact_evals": tr.exact_evals[-1], "wall_s": time.perf_counter() - t0,
+                     "F": float(tr.f[-1]),
+                     "iters": len(tr.f) - 1,
+                     "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
+                     "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
+        fresh()
+        sur = O.Surrogate(d, hidden=(256, 256, 256),
+                          max_batch=(args.max_iter + 2) * 3 * B, seed=k)
+        t0 = time.perf_counter()
+        tr = O.surrogate_bfgs(ev, th0, sur, h=1e-3, ftol=0.0, gtol=0.0,
+                              max_iter=args.max_iter, f_target=F_star,
+                              target_rtol=args.rtol, train_steps=args.train_steps)
+        torch.cuda.synchronize()
+        row["surrogate"] = {"exact_evals": tr.exact_evals[-1], "F": float(tr.f[-1]),
+                            "wall_s": time.perf_counter() - t0,
+                            "iters": len(tr.f) - 1,
+                            "surrogate_steps": tr.kind.count("surrogate"),
+                            "fd_steps": tr.kind.count("fd"),
+                            "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
+                            "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
+        runs.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+
+    def summ(key):
+        ok = [r[key] for r in runs if r[key]["reached"]]
+        return {"reached": len(ok), "of": len(runs),
+                "median_exact_evals": float(np.median([r["exact_evals"] for r in ok])) if ok else None,
+                "median_wall_s": float(np.median([r["wall_s"] for r in ok])) if ok else None,
+                "mean_exact_evals": float(np.mean([r["exact_evals"] for r in ok])) if ok else None}
+    out = {"workload": wl.name, "N": wl.N, "b": wl.b, "dim_theta": d, "batch": B,
+           "F_star": float(F_star), "theta_star": list(map(float, theta_star)),
+           "reference": {"iters": len(ref.f) - 1, "exact_evals": ref.exact_evals[-1],
+                         "wall_s": t_ref, "F_start": float(ref.f[0])},
+           "rtol": args.rtol, "start_scale": args.scale,
+           "fd_bfgs": summ("fd"), "surrogate_bfgs": summ("surrogate"), "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,15 +4,23 @@ Two drivers minimise F(theta) = -f_obj(theta):
 
 * ``fd_bfgs``: BFGS with the central-difference gradient of Eq. 10.  The
   2*dim+1 stencil points of one gradient are one batched evaluation pass;
-  the line search evaluates a ladder of trial step lengths (1, 1/2, 1/4, ...)
-  as one more pass and keeps the longest step with sufficient (Armijo)
-  decrease.
-* ``surrogate_bfgs``: the same, but between exact gradients a learned
-  surrogate (the GPU MLP, trained online on every exact (theta, f) pair)
-  supplies the gradient that sets the search direction and the secant
-  update; every proposed point is still evaluated exactly, and the exact
-  values alone decide acceptance.  When a surrogate step is rejected the
-  driver falls back to an exact finite-difference step.
+  the line search evaluates a short ladder of step lengths (1, 1/2, 1/4,
+  1/8, then the next four if none qualifies, ...) as one small batched pass
+  and keeps the longest step with sufficient (Armijo) decrease.  The search
+  direction is capped at length ``max_step`` (theta holds log-scale
+  parameters), the initial inverse Hessian is rescaled by y^T s / y^T y
+  before the first update, and a failed line search is retried once along
+  the steepest-descent direction.
+* ``surrogate_bfgs``: the same exact steps, but after each one a learned
+  surrogate -- the GPU MLP, trained online (warm-started) on every exact
+  (theta, F) pair so far -- supplies the gradient for up to ``max_sur``
+  further quasi-Newton steps, each costing one line-search pass instead of a
+  finite-difference gradient.  Every proposed point is evaluated exactly and
+  accepted only on exact values (Armijo along the surrogate's slope); the
+  surrogate streak ends as soon as the exact decrease falls below ``eta``
+  times the decrease the surrogate predicted.  The BFGS matrix is updated
+  only from exact gradients (one secant pair per finite-difference pass) and
+  convergence is decided on exact gradients only.
 
 Host-side logic only (vectors of length dim theta); every f_obj value comes
 from the library's kernels.
@@ -40,12 +48,16 @@ class Trace:
 
 
 class Evaluator:
-    """Batched exact evaluation of F = -f_obj on one model (B instances)."""
+    """Batched exact evaluation of F = -f_obj on one model: a workspace of
+    `batch` instances for gradient stencils and one of `ntrial` instances for
+    line searches."""
 
-    def __init__(self, model: "D.Model", batch: int, graph: bool = True):
+    def __init__(self, model: "D.Model", batch: int, graph: bool = True, ntrial: int = 4):
         self.model = model
         self.B = batch
+        self.ntrial = ntrial
         self.ws = D.Workspace([model] * batch, graph=graph)
+        self.ws_ls = D.Workspace([model] * ntrial, graph=graph)
         self.dim = model.dim_theta
         self.count = 0
         self.archive_x: List[np.ndarray] = []
@@ -53,9 +65,17 @@ class Evaluator:
 
     def __call__(self, thetas: np.ndarray) -> np.ndarray:
         thetas = np.atleast_2d(np.asarray(thetas, np.float64))
-        f, _, _ = self.ws.fobj(thetas)
-        vals = -f.cpu().numpy()
-        self.count += thetas.shape[0]
+        n = thetas.shape[0]
+        if n > self.B:
+            return np.concatenate([self(thetas[i:i + self.B]) for i in range(0, n, self.B)])
+        ws, size = (self.ws_ls, self.ntrial) if n <= self.ntrial else (self.ws, self.B)
+        if n < size:  # pad with copies of the first point (not counted)
+            thetas_p = np.concatenate([thetas, np.repeat(thetas[:1], size - n, axis=0)])
+        else:
+            thetas_p = thetas
+        f, _, _ = ws.fobj(thetas_p)
+        vals = -f.cpu().numpy()[:n]
+        self.count += n
         for t, v in zip(thetas, vals):
             if np.isfinite(v):
                 self.archive_x.append(t.copy())
@@ -78,35 +98,59 @@ def fd_gradient(ev: Evaluator, theta: np.ndarray, h: float):
     return v[0], (v[1::2] - v[2::2]) / (2.0 * h)
 
 
-def _line_search(ev: Evaluator, theta, F0, g, p, c1=1e-4, ntrial=None):
-    """Evaluate theta + alpha p for alpha = 1, 1/2, ... in one pass; return
-    the longest step with F <= F0 + c1 alpha g.p, else (None, None, None)."""
-    n = ntrial or ev.B
-    alphas = 0.5 ** np.arange(n)
-    vals = ev(theta[None, :] + alphas[:, None] * p[None, :])
+def _capped(p, max_step):
+    nrm = float(np.linalg.norm(p))
+    return p * (max_step / nrm) if nrm > max_step else p
+
+
+def _line_search(ev: Evaluator, theta, F0, g, p, c1=1e-4, max_passes=4):
+    """Evaluate theta + alpha p for alpha = 1, 1/2, ... (ev.ntrial per pass);
+    return the longest step with F <= F0 + c1 alpha g.p, else
+    (None, None, None)."""
     slope = float(g @ p)
-    for a, v in zip(alphas, vals):
-        if np.isfinite(v) and v <= F0 + c1 * a * slope:
-            return a, theta + a * p, v
+    for k in range(max_passes):
+        alphas = 0.5 ** (k * ev.ntrial + np.arange(ev.ntrial))
+        vals = ev(theta[None, :] + alphas[:, None] * p[None, :])
+        for a, v in zip(alphas, vals):
+            if np.isfinite(v) and v <= F0 + c1 * a * slope:
+                return a, theta + a * p, v
     return None, None, None
 
 
-def _bfgs_update(H, s, y):
+def _bfgs_update(H, s, y, first=False):
     ys = float(y @ s)
     if ys <= 1e-12:
         return H
+    if first:
+        H = (ys / float(y @ y)) * np.eye(H.shape[0])
     r = 1.0 / ys
     I = np.eye(H.shape[0])
     return (I - r * np.outer(s, y)) @ H @ (I - r * np.outer(y, s)) + r * np.outer(s, s)
 
 
+def _exact_step(ev, x, F, g, H, max_step):
+    """Quasi-Newton step with the capped direction; one retry along the
+    steepest-descent direction.  Returns (alpha, x_new, F_new, H)."""
+    p = -H @ g
+    if g @ p >= 0:
+        H = np.eye(x.shape[0])
+        p = -g
+    a, xn, Fn = _line_search(ev, x, F, g, _capped(p, max_step))
+    if a is None:
+        H = np.eye(x.shape[0])
+        a, xn, Fn = _line_search(ev, x, F, g, _capped(-g, max_step))
+    return a, xn, Fn, H
+
+
 def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
-            f_target: Optional[float] = None, target_rtol: float = 1e-6) -> Trace:
+            f_target: Optional[float] = None, target_rtol: float = 1e-6,
+            max_step: float = 1.0) -> Trace:
     t0 = time.perf_counter()
     tr = Trace()
     x = np.asarray(theta0, np.float64).copy()
     F, g = fd_gradient(ev, x, h)
     H = np.eye(x.shape[0])
+    first = True
 
     def log(kind):
         tr.theta.append(x.copy()); tr.f.append(F); tr.exact_evals.append(ev.count)
@@ -118,15 +162,12 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
             break
         if np.max(np.abs(g)) <= gtol:
             break
-        p = -H @ g
-        if g @ p >= 0:
-            H = np.eye(x.shape[0])
-            p = -g
-        a, xn, Fn = _line_search(ev, x, F, g, p)
+        a, xn, Fn, H = _exact_step(ev, x, F, g, H, max_step)
         if a is None:
             break
         Fn2, gn = fd_gradient(ev, xn, h)
-        H = _bfgs_update(H, xn - x, gn - g)
+        H = _bfgs_update(H, xn - x, gn - g, first)
+        first = False
         rel = abs(Fn2 - F) / max(1.0, abs(F))
         x, F, g = xn, Fn2, gn
         log("fd")
@@ -136,8 +177,9 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
 
 
 class Surrogate:
-    """Online MLP model of F over theta (inputs centred and scaled by the
-    archive, output standardised), trained with the GPU kernels."""
+    """Online MLP model of F over theta, trained with the GPU kernels.  The
+    input centring/scaling and output standardisation are fixed at the first
+    fit, so later fits continue from the current weights (online training)."""
 
     def __init__(self, dim: int, hidden=(256, 256, 256), max_batch=4096, seed=0):
         sizes = (dim, *hidden, 1)
@@ -153,20 +195,30 @@ class Surrogate:
         self.sx = np.ones(dim)
         self.my = 0.0
         self.sy = 1.0
+        self.fitted = False
 
     def fit(self, X: np.ndarray, y: np.ndarray, steps=200, lr=2e-3):
-        self.mx = X.mean(axis=0)
-        self.sx = X.std(axis=0) + 1e-3
-        self.my = float(y.mean())
-        self.sy = float(y.std() + 1e-12)
+        if not self.fitted:
+            self.mx = X.mean(axis=0)
+            self.sx = X.std(axis=0) + 1e-2
+            self.my = float(y.mean())
+            self.sy = float(y.std() + 1e-12)
+            self.fitted = True
+        if X.shape[0] > self.net.max_batch:  # the most recent pairs
+            X, y = X[-self.net.max_batch:], y[-self.net.max_batch:]
         Xn = torch.from_numpy(((X - self.mx) / self.sx).astype(np.float32)).cuda()
         yn = torch.from_numpy(((y - self.my) / self.sy).astype(np.float32)).cuda()
+        loss = None
         for _ in range(steps):
             self.net.forward(Xn)
             dy, loss = self.net.mse_grad(yn)
             self.net.backward(dy)
             self.net.adam(lr=lr)
-        return float(loss.item())
+        return float(loss.item()) if loss is not None else float("nan")
+
+    def predict(self, x: np.ndarray) -> float:
+        xn = torch.from_numpy(((x - self.mx) / self.sx).astype(np.float32)[None]).cuda()
+        return float(self.net.forward(xn).item()) * self.sy + self.my
 
     def grad(self, x: np.ndarray):
         """(F_hat(x), dF_hat/dx) from the network's input gradient."""
@@ -180,75 +232,56 @@ class Surrogate:
 
 def surrogate_bfgs(ev: Evaluator, theta0, surrogate: Surrogate, h=1e-3, ftol=1e-6,
                    gtol=1e-4, max_iter=100, f_target: Optional[float] = None,
-                   target_rtol: float = 1e-6, train_steps=200,
-                   min_archive: Optional[int] = None) -> Trace:
-    """BFGS in which, after every exact finite-difference step, the surrogate
-    (refitted on all exact pairs so far) proposes the next direction from its
-    own gradient.  Proposals are judged only by exact values (Armijo on the
-    exact F); a rejected proposal hands over to an exact step.  Convergence is
-    decided on exact gradients only: when a surrogate step would stop the run
-    (tiny change), an exact gradient is taken at the point first."""
+                   target_rtol: float = 1e-6, train_steps=100,
+                   min_archive: Optional[int] = None, max_step: float = 1.0,
+                   max_sur: int = 3, eta: float = 0.25) -> Trace:
     t0 = time.perf_counter()
     tr = Trace()
     x = np.asarray(theta0, np.float64).copy()
     d = x.shape[0]
     F, g = fd_gradient(ev, x, h)
-    g_exact = True
     H = np.eye(d)
-    min_archive = min_archive or 3 * (2 * d + 1)
+    first = True
+    min_archive = min_archive or 2 * (2 * d + 1)
 
-    def log(kind):
-        tr.theta.append(x.copy()); tr.f.append(F); tr.exact_evals.append(ev.count)
+    def log(kind, xx, FF):
+        tr.theta.append(xx.copy()); tr.f.append(FF); tr.exact_evals.append(ev.count)
         tr.wall.append(time.perf_counter() - t0); tr.kind.append(kind)
 
-    def converged(rel=None):
-        if f_target is not None:
-            return abs(F - f_target) <= target_rtol * abs(f_target)
-        if np.max(np.abs(g)) <= gtol:
-            return True
-        return rel is not None and rel <= ftol
+    def reached(FF):
+        return f_target is not None and abs(FF - f_target) <= target_rtol * abs(f_target)
 
-    log("start")
-    use_sur = False
-    rel = None
+    log("start", x, F)
     for _ in range(max_iter):
-        if g_exact and converged(rel):
+        if reached(F) or np.max(np.abs(g)) <= gtol:
             break
-        if use_sur and len(ev.archive_f) >= min_archive:
-            surrogate.fit(np.asarray(ev.archive_x), np.asarray(ev.archive_f),
-                          steps=train_steps)
-            _, gs = surrogate.grad(x)
-            p = -H @ gs
-            if gs @ p < 0:
-                a, xn, Fn = _line_search(ev, x, F, gs, p)
-                if a is not None and Fn < F:
-                    _, gsn = surrogate.grad(xn)
-                    H = _bfgs_update(H, xn - x, gsn - gs)
-                    rel = abs(Fn - F) / max(1.0, abs(F))
-                    x, F, g, g_exact = xn, Fn, gsn, False
-                    log("surrogate")
-                    if f_target is not None and converged():
-                        break
-                    # a tiny change is checked by an exact step next
-                    use_sur = rel > ftol
-                    continue
-            use_sur = False   # rejected: take an exact step next
-        if not g_exact:
-            F, g = fd_gradient(ev, x, h)
-            g_exact = True
-            if converged():
-                break
-        p = -H @ g
-        if g @ p >= 0:
-            H = np.eye(d)
-            p = -g
-        a, xn, Fn = _line_search(ev, x, F, g, p)
+        a, xs, Fs, H = _exact_step(ev, x, F, g, H, max_step)
         if a is None:
             break
-        Fn2, gn = fd_gradient(ev, xn, h)
-        H = _bfgs_update(H, xn - x, gn - g)
+        log("exact-step", xs, Fs)
+        if len(ev.archive_f) >= min_archive and not reached(Fs):
+            surrogate.fit(np.asarray(ev.archive_x), np.asarray(ev.archive_f),
+                          steps=train_steps)
+            for _ in range(max_sur):
+                Fh, gs = surrogate.grad(xs)
+                p = _capped(-H @ gs, max_step)
+                if gs @ p >= 0:
+                    break
+                a2, x2, F2 = _line_search(ev, xs, Fs, gs, p, max_passes=1)
+                if a2 is None:
+                    break
+                pred = Fh - surrogate.predict(x2)
+                actual = Fs - F2
+                xs, Fs = x2, F2
+                log("surrogate", xs, Fs)
+                if pred <= 0 or actual < eta * pred or reached(Fs):
+                    break
+        Fn2, gn = fd_gradient(ev, xs, h)
+        H = _bfgs_update(H, xs - x, gn - g, first)
+        first = False
         rel = abs(Fn2 - F) / max(1.0, abs(F))
-        x, F, g = xn, Fn2, gn
-        log("fd")
-        use_sur = True
+        x, F, g = xs, Fn2, gn
+        log("fd", x, F)
+        if f_target is None and rel <= ftol:
+            break
     return tr
