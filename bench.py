@@ -181,8 +181,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the "
-              "evaluation path is single-GPU; see DESIGN.md for how it would "
-              "shard.", file=sys.stderr)
+              "evaluation path is built for a single GPU and does not shard "
+              "over several.", file=sys.stderr)
         sys.exit(2)
 
     import torch

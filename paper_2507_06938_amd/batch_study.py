@@ -1,0 +1,135 @@
+"""Batched f_obj throughput: a central-difference gradient of the trivariate
+30x30, nt = 48 model (31 theta points, Eq. 10) and the uneven 64-instance
+mix, each as batched, graph-replayed workspaces in FP64 and mixed precision.
+
+    python -m paper_2507_06938_amd.batch_study [--skip-uneven] [--skip-fd]
+
+The uneven mix needs more device memory than one GPU holds at once, so it is
+packed (largest first) into waves of at most --mem-gb of workspace each; a
+wave is one workspace of uneven instances evaluated together.  Prints one
+JSON document: evals/s of every configuration, the sequential single-
+instance rate for comparison, device bytes, and whether every evaluation
+reported positive-definite factors.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def _ws_bytes_estimate(wl, mixed):
+    """Device bytes of an f_obj workspace (dense Q_c blocks dominate)."""
+    bp = (wl.b + 63) // 64 * 64
+    ap = 64 if wl.a > 0 else 0
+    eb = 4 if mixed else 8
+    qc = wl.nt * bp * bp * 8 + (wl.nt + 1) * (bp + ap) * bp * eb
+    ring = 2 * bp * bp * 8 + 3 * bp * bp * eb
+    return int(1.05 * (qc + ring)) + (64 << 20)
+
+
+def main(argv=None):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import numpy as np
+    import torch
+    import workloads as W
+    from . import dalia as D
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--mem-gb", type=float, default=240.0)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--skip-uneven", action="store_true")
+    ap.add_argument("--skip-fd", action="store_true")
+    ap.add_argument("--tiles", default=os.path.join(root, "paper_2507_06938_amd",
+                                                    "tiles_gfx950.txt"))
+    args = ap.parse_args(argv)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    if not args.skip_fd:
+        wl = W.config2()
+        model = D.Model.from_workload(wl)
+        h = 1e-3
+        d = wl.dim_theta
+        pts = np.repeat(wl.theta[None], 2 * d + 1, axis=0)
+        for i in range(d):
+            pts[1 + 2 * i, i] += h
+            pts[2 + 2 * i, i] -= h
+        th = torch.tensor(pts, dtype=torch.float64, device="cuda")
+        res = {"workload": wl.name, "points": 2 * d + 1}
+        single = D.Workspace(model)
+        single.autotune(args.tiles)
+        t1 = timed(lambda: single.fobj(th[:1]), args.reps)
+        res["single_fp64_evals_per_s"] = 1.0 / t1
+        del single
+        torch.cuda.empty_cache()
+        for mixed in (False, True):
+            ws = D.Workspace([model] * (2 * d + 1), graph=True, mixed=mixed)
+            ws.autotune(args.tiles)
+            t = timed(lambda: ws.fobj(th), args.reps)
+            f, parts, info = ws.fobj(th)
+            torch.cuda.synchronize()
+            key = "mixed" if mixed else "fp64"
+            res[key] = {"s_per_gradient": t, "evals_per_s": (2 * d + 1) / t,
+                        "speedup_vs_single_fp64": (2 * d + 1) / t * t1,
+                        "device_gb": ws.nbytes / 1e9,
+                        "all_spd": bool((info == 0).all().item()),
+                        "f0": float(f[0].item())}
+            print(key, json.dumps(res[key]), file=sys.stderr, flush=True)
+            del ws
+            torch.cuda.empty_cache()
+        out["fd_gradient_c2"] = res
+
+    if not args.skip_uneven:
+        wls = [W.uneven_instance(k) for k in range(64)]
+        models = [D.Model.from_workload(w) for w in wls]
+        res = {"instances": 64}
+        for mixed in (False, True):
+            cap = args.mem_gb * 1e9
+            order = sorted(range(64), key=lambda k: -_ws_bytes_estimate(wls[k], mixed))
+            waves, cur, used = [], [], 0
+            for k in order:
+                b = _ws_bytes_estimate(wls[k], mixed)
+                if cur and used + b > cap:
+                    waves.append(cur)
+                    cur, used = [], 0
+                cur.append(k)
+                used += b
+            if cur:
+                waves.append(cur)
+            total_t, ok, gb = 0.0, True, []
+            for wave in waves:
+                ws = D.Workspace([models[k] for k in wave], graph=True, mixed=mixed)
+                ws.autotune(args.tiles)
+                th = np.concatenate([wls[k].theta for k in wave])
+                t = timed(lambda: ws.fobj(th), args.reps)
+                f, parts, info = ws.fobj(th)
+                torch.cuda.synchronize()
+                ok = ok and bool((info == 0).all().item())
+                total_t += t
+                gb.append(ws.nbytes / 1e9)
+                print(("mixed" if mixed else "fp64"), "wave", len(wave), "instances",
+                      f"{t:.3f} s", f"{ws.nbytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+                del ws
+                torch.cuda.empty_cache()
+            res["mixed" if mixed else "fp64"] = {
+                "waves": [len(w) for w in waves], "wave_gb": gb, "s_all": total_t,
+                "evals_per_s": 64 / total_t, "all_spd": ok}
+        out["uneven_64"] = res
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
