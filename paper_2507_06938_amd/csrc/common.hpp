@@ -108,9 +108,7 @@ struct DeviceTasks {
 // of A <- L (upper zeroed), Ginv (64 x 64, ld 64, may be null) <- L^{-1};
 // mode 1: lower triangle of A <- L^{-1} (the factor itself is not kept).
 // logdiag[i] = log L_ii; on a non-positive pivot *info = row0 + i + 1 (first
-// failure only).  M (64 x 64, ld 64, may be null) <- G^T G with G = L^{-1},
-// i.e. the inverse of the tile, exactly symmetric.  A batch of tiles is one
-// launch, one workgroup per tile.
+// failure only).  A batch of tiles is one launch, one workgroup per tile.
 struct PotrfTileArgs {
   double* A;
   int64_t lda;
@@ -120,7 +118,6 @@ struct PotrfTileArgs {
   int64_t row0;
   int32_t mode;
   int32_t pad_;
-  double* M;
 };
 hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
                               hipStream_t s);
@@ -131,17 +128,14 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
 // below diagonal tile k still hold the unsolved panel P_k = A(:, k) as
 // updated by panels < k), one step j applies the trailing update of panel j
 // to the lower tiles (I, J), j < J <= I:
-//     A(I, J) -= P_j(I) M_j P_j(J)^T,   M_j = G_jj^T G_jj,
-// which equals L(I, j) L(J, j)^T with L(., j) = P_j G_jj^T, and in the same
-// launch factors the updated diagonal tile j+1 (mode 1, logdiag, info) and
-// writes M_{j+1} (if Mnext is not null).  The panels are solved afterwards,
-// all at once (L(I, k) = P_k(I) G_kk^T).  One workgroup per tile; the tiles
-// that factor are numbered first.
+//     A(I, J) -= L(I, j) L(J, j)^T,   L(., j) = P_j G_jj^T
+// (L formed in the workgroup, not stored), and in the same launch factors
+// the updated diagonal tile j+1 (mode 1, logdiag, info).  The panels are
+// solved afterwards, all at once (L(I, k) = P_k(I) G_kk^T).  One workgroup
+// per tile; the tiles that factor are numbered first.
 struct PanelTask {
   double* A;
   int64_t ld;
-  const double* M;     // M_j, 64 x 64, ld 64
-  double* Mnext;       // M_{j+1} or null
   double* logdiag;     // 64 entries for tile j+1
   int64_t* info;
   int64_t row0;        // global row of tile j+1

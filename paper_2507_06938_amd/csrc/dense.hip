@@ -31,17 +31,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// Two 16x16 blocks of a 64-deep product of LDS tiles stored S[k*LDL + c]:
-//   D[a][b] = sum_k P[k][p0 + a] Q[k][q0 + b]   (and q0 + 16 for acc1),
+// Two 16x16 blocks of a product of LDS tiles stored S[k*LDL + c]:
+//   D[a][b] = sum_{k < kmax} P[k][p0 + a] Q[k][q0 + b]   (and q0 + 16 for acc1),
 // on v_mfma_f64_16x16x4_f64 (lane l supplies P[k0 + l/16][p0 + l%16] as the
 // "A" operand and Q[k0 + l/16][q0 + l%16] as "B"; register r of lane l
-// receives D[l/16 + 4r][l%16]).
+// receives D[l/16 + 4r][l%16]).  kmax: multiple of 4, at most 64.
 __device__ __forceinline__ void mfma2_k64(const double* P, int p0, const double* Q,
-                                          int q0, v4d& acc0, v4d& acc1) {
+                                          int q0, v4d& acc0, v4d& acc1, int kmax = NB) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = l >> 4;
-#pragma unroll
-  for (int k0 = 0; k0 < NB; k0 += 4) {
+#pragma unroll 4
+  for (int k0 = 0; k0 < kmax; k0 += 4) {
     const double a = P[(k0 + lk) * LDL + p0 + lr];
     const double b0 = Q[(k0 + lk) * LDL + q0 + lr];
     const double b1 = Q[(k0 + lk) * LDL + q0 + 16 + lr];
@@ -87,7 +87,7 @@ template <int CW>
 __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, double* Lc,
                                            double* Gk, int* sbad, double* A, int64_t lda,
                                            double* Ginv, double* logdiag, int64_t* info,
-                                           int64_t row0, int mode, double* Mout) {
+                                           int64_t row0, int mode) {
   constexpr int NW = NB / CW;
   constexpr int NT = NW * 64;
   const int i = threadIdx.x & 63;
@@ -154,28 +154,6 @@ __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, doubl
       dst[rr + cc * ldd] = (rr >= cc) ? Gk[rr * LDL + cc] : 0.0;
     }
   }
-  if (Mout) {
-    // M = G^T G: M(a, b) = sum_k G(k, a) G(k, b); only a >= b is taken from
-    // the product and written to both halves (exact symmetry).
-    static_assert(NW == 8, "M product assumes 8 waves");
-    const int l = threadIdx.x & 63;
-    const int a0 = 16 * (wv >> 1), b0 = 32 * (wv & 1);
-    v4d m0 = {0.0, 0.0, 0.0, 0.0}, m1 = {0.0, 0.0, 0.0, 0.0};
-    mfma2_k64(Gk, a0, Gk, b0, m0, m1);
-#pragma unroll
-    for (int rg = 0; rg < 4; ++rg) {
-      const int a = a0 + (l >> 4) + 4 * rg;
-      const int b = b0 + (l & 15);
-      if (a >= b) {
-        Mout[a + b * NB] = m0[rg];
-        Mout[b + a * NB] = m0[rg];
-      }
-      if (a >= b + 16) {
-        Mout[a + (b + 16) * NB] = m1[rg];
-        Mout[(b + 16) + a * NB] = m1[rg];
-      }
-    }
-  }
 }
 
 __global__ __launch_bounds__(POTRF_NT) void k_potrf_tile(const PotrfTileArgs* __restrict__ args) {
@@ -184,7 +162,7 @@ __global__ __launch_bounds__(POTRF_NT) void k_potrf_tile(const PotrfTileArgs* __
   __shared__ __align__(16) double Gk[TILE_LDS];
   __shared__ int sbad;
   potrf_body<POTRF_CW>(a.A, a.lda, Lc, Gk, &sbad, a.A, a.lda, a.Ginv, a.logdiag, a.info,
-                       a.row0, a.mode, a.M);
+                       a.row0, a.mode);
 }
 
 hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
@@ -198,13 +176,16 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
 //
 // Workgroup g < ntask factors: it updates diagonal tile j+1 of task g and then
 // factors it; the others update one lower tile (I, J) each.  Per tile, with
-// the 64 x 64 operands staged in LDS (S0 = P_j(I), S1 = M_j, S2 = P_j(J)):
-//   T^T = M_j P_j(I)^T               (S1, S0)  -> T stored back over S0,
-//   (T P_j(J)^T)^T = P_j(J) T^T      (S2, S0)  -> subtracted from A(I, J),
-// both on FP64 MFMA with the operand roles chosen so that a lane's results
-// lie along the rows of the column-major output (coalesced stores).  The
-// factoring workgroup stages the updated tile in LDS (S1) instead and runs
-// the tile factor on it with S0 and S2 as its scratch tiles.
+// the 64 x 64 operands staged in LDS (S0 = P_j(I), S1 = G_jj, S2 = P_j(J)):
+//   L_I = P_j(I) G_jj^T and L_J = P_j(J) G_jj^T  (G_jj lower triangular:
+//        block column c of L needs k < 16 (c + 1) only),
+//   A(I, J) -= L_I L_J^T,
+// on FP64 MFMA with the operand roles chosen so that a lane's results lie
+// along the rows of the column-major output (coalesced stores).  Every
+// global load (the operand tiles and the elements of A(I, J) a lane updates)
+// is issued before the first LDS store, so their latencies overlap.  The
+// factoring workgroup (I = J) forms L_I once, stages the updated tile in LDS
+// (S1) and runs the tile factor on it with S0 and S2 as its scratch tiles.
 __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __restrict__ tasks,
                                                            int ntask) {
   __shared__ __align__(16) double pool[3 * TILE_LDS];
@@ -235,47 +216,81 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   const int J = lt - I * (I + 1) / 2;
   const int64_t ti0 = (int64_t)(T.j + 1 + I) * NB, tj0 = (int64_t)(T.j + 1 + J) * NB;
   const int64_t pc = (int64_t)T.j * NB * T.ld;
-  stage_tile<POTRF_NT>(T.A + ti0 + pc, T.ld, S0);
-  stage_tile<POTRF_NT>(T.M, NB, S1);
-  stage_tile<POTRF_NT>(T.A + tj0 + pc, T.ld, S2);
-  __syncthreads();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = l >> 4;
   const int p0 = 16 * (wv >> 1), q0 = 32 * (wv & 1);
-  v4d t0 = {0.0, 0.0, 0.0, 0.0}, t1 = {0.0, 0.0, 0.0, 0.0};
-  mfma2_k64(S1, p0, S0, q0, t0, t1);  // t: T(m = q0 + lr (+16), c = p0 + lk + 4r)
+  double* C = T.A + ti0 + tj0 * T.ld;
+  constexpr int PER = NB * NB / POTRF_NT;
+  double vp[PER], vg[PER], vq[PER], cpre[8];
+  {
+    const double* Pi = T.A + ti0 + pc;
+    const double* Gj = T.A + (int64_t)T.j * NB * (T.ld + 1);  // G_jj
+    const double* Pj = T.A + tj0 + pc;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + e * POTRF_NT;
+      const int64_t o = (idx & 63) + (int64_t)(idx >> 6) * T.ld;
+      vp[e] = Pi[o];
+      vg[e] = Gj[o];
+      vq[e] = (I != J) ? Pj[o] : 0.0;
+    }
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) {
+      const double* c0 = C + (q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld;
+      cpre[rg] = c0[0];
+      cpre[4 + rg] = c0[16];
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + e * POTRF_NT;
+      const int o = (idx >> 6) * LDL + (idx & 63);
+      S0[o] = vp[e];
+      S1[o] = vg[e];
+      if (I != J) S2[o] = vq[e];
+    }
+  }
+  __syncthreads();
+  // L^T = G P^T: D[c][m] = sum_k G(c, k) P(m, k), k <= c < p0 + 16
+  v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  v4d b0 = {0.0, 0.0, 0.0, 0.0}, b1 = {0.0, 0.0, 0.0, 0.0};
+  mfma2_k64(S1, p0, S0, q0, a0, a1, p0 + 16);  // L_I(m = q0 + lr (+16), c = p0 + lk + 4r)
+  if (I != J) mfma2_k64(S1, p0, S2, q0, b0, b1, p0 + 16);
   __syncthreads();
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg) {
     const int c = p0 + lk + 4 * rg;
-    S0[c * LDL + q0 + lr] = t0[rg];
-    S0[c * LDL + q0 + 16 + lr] = t1[rg];
+    S0[c * LDL + q0 + lr] = a0[rg];
+    S0[c * LDL + q0 + 16 + lr] = a1[rg];
+    if (I != J) {
+      S2[c * LDL + q0 + lr] = b0[rg];
+      S2[c * LDL + q0 + 16 + lr] = b1[rg];
+    }
   }
   __syncthreads();
+  // (L_I L_J^T)^T = L_J L_I^T: D[n][m] = sum_c L_J(n, c) L_I(m, c)
+  const double* LJ = (I != J) ? S2 : S0;
   v4d u0 = {0.0, 0.0, 0.0, 0.0}, u1 = {0.0, 0.0, 0.0, 0.0};
-  mfma2_k64(S2, p0, S0, q0, u0, u1);  // u: update(m = q0 + lr (+16), n = p0 + lk + 4r)
-  double* C = T.A + ti0 + tj0 * T.ld;
+  mfma2_k64(LJ, p0, S0, q0, u0, u1);  // u: update(m = q0 + lr (+16), n = p0 + lk + 4r)
   if (!fac) {
 #pragma unroll
     for (int rg = 0; rg < 4; ++rg) {
-      const int64_t n = p0 + lk + 4 * rg;
-      double* c0 = C + (q0 + lr) + n * T.ld;
-      *c0 -= u0[rg];
-      c0[16] -= u1[rg];
+      double* c0 = C + (q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld;
+      c0[0] = cpre[rg] - u0[rg];
+      c0[16] = cpre[4 + rg] - u1[rg];
     }
     return;
   }
+  __syncthreads();  // S1 (G_jj) is read no more
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg) {
     const int n = p0 + lk + 4 * rg;
-    const double* c0 = C + (q0 + lr) + (int64_t)n * T.ld;
-    S1[n * LDL + q0 + lr] = c0[0] - u0[rg];
-    S1[n * LDL + q0 + 16 + lr] = c0[16] - u1[rg];
+    S1[n * LDL + q0 + lr] = cpre[rg] - u0[rg];
+    S1[n * LDL + q0 + 16 + lr] = cpre[4 + rg] - u1[rg];
   }
   __syncthreads();
   potrf_body<POTRF_CW>(S1, LDL, S0, S2, &sbad, C, T.ld, nullptr, T.logdiag, T.info,
-                       T.row0, 1, T.Mnext);
+                       T.row0, 1);
 }
 
 int finalize_panels(PanelTask* t, int n) {

@@ -243,15 +243,14 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
 // Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
 // panels of 64 columns.  Diagonal tiles are overwritten by their inverses
 // G_jj (they are used only through them).  Tile 0 is factored alone; step j
-// then updates the trailing tiles with the unsolved panel j through
-// M_j = G_jj^T G_jj and factors tile j+1 in the same launch (M alternates
-// between the two 64 x 64 buffers at mbuf); finally all panels are solved
-// in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`: unpadded size (operation
+// then updates the trailing tiles with L(., j) = P_j G_jj^T formed from the
+// unsolved panel j and factors tile j+1 in the same launch; finally all
+// panels are solved in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`: unpadded size (operation
 // count).  Keys (major, group 1, j, sub): (0, 0) tile 0, (j, 1) step j,
 // (255, 0) the panel solves.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
-                      int breal, double* mbuf) {
+                      int breal) {
   const int nbk = n / 64;
   auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
   auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
@@ -268,7 +267,6 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     s.potrf.info = info;
     s.potrf.row0 = row0;
     s.potrf.mode = 1;
-    s.potrf.M = nbk > 1 ? mbuf : nullptr;
     q.push_back(s);
   }
   for (int j = 0; j + 1 < nbk; ++j) {
@@ -282,8 +280,6 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     PanelTask& t = s.panel;
     t.A = A;
     t.ld = ld;
-    t.M = mbuf + (j & 1) * 64 * 64;
-    t.Mnext = (j + 2 < nbk) ? mbuf + ((j + 1) & 1) * 64 * 64 : nullptr;
     t.logdiag = logdiag + (int64_t)(j + 1) * 64;
     t.info = info;
     t.row0 = row0 + (int64_t)(j + 1) * 64;
@@ -375,7 +371,6 @@ struct Inst {
   int64_t* info2 = nullptr;
   double *rhs = nullptr, *x = nullptr, *mu = nullptr, *u = nullptr, *gpart = nullptr;
   double* ttemp[2] = {nullptr, nullptr};
-  double* mbuf[2] = {nullptr, nullptr};  // two 64 x 64 M buffers per factorisation
   double *f = nullptr, *parts = nullptr;
   int64_t* info_out = nullptr;
   // selected inversion
@@ -606,7 +601,7 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     const bool last = (t + 1 == m.nt);
     if (ring && !last) asm_qp(t + 1, K(major, 0));
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
-              (int64_t)t * m.b, m.b, I.mbuf[w]);
+              (int64_t)t * m.b, m.b);
     seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0, xf);
     const int rows_lo = last ? bp : 0;
     const int M = (last ? 0 : bp) + apr;
@@ -1106,7 +1101,6 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(tip, (void**)&I.GPp);
     for (int w = 0; w < 2; ++w) {
       A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttemp[w]);
-      A(sizeof(double) * 2 * 64 * 64, (void**)&I.mbuf[w]);
       A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
     }
     A(sizeof(double) * (I.dim + 1), (void**)&I.theta);
