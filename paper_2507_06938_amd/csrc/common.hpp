@@ -42,6 +42,11 @@ enum : int {
   F_C64 = 1024,
   // FP64 kernel: split the k range of long tiles (see below)
   F_SPLIT = 2048,
+  // set by finalize_tasks on every task of a launch in which some task's k
+  // range varies from tile to tile (any F_KLO_* / F_KHI_* flag): the tiles
+  // of such a task are ordered longest first and the launch's workgroups are
+  // dealt to the XCDs in turn, so each XCD gets the same mix of lengths
+  F_KVAR = 4096,
 };
 
 // Split k.  For an F_SPLIT task with K > GEMM_KSPLIT, the k range [kb, ke) of

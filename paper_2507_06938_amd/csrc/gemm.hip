@@ -8,8 +8,11 @@
 // are renumbered so that those one XCD receives take consecutive tiles (the
 // operand tiles they share then stay in that XCD's L2).  The inner product
 // runs on v_mfma_f64_16x16x4_f64 with operands staged through
-// double-buffered LDS (16-deep k chunks, next chunk prefetched into
-// registers while the current one is multiplied).
+// double-buffered LDS in 16-deep k chunks.  Aligned operands with even
+// extents are staged with 16-byte global loads (two doubles per slot, a
+// fixed number of loads per chunk, zeros for slots outside the operand),
+// the next one or two chunks in flight in registers while the current one
+// is multiplied; other operands take a per-element bounds-checked path.
 //
 // MFMA lane layout used (f64 16x16x4, wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; its accumulator register r holds D[l/16 + 4r][l%16]
@@ -92,6 +95,88 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ S, bool trans,
   }
 }
 
+// Vector staging (the usual case: operand 16-byte aligned, even leading
+// dimension, even row count / k extent).  Each thread owns PV slots of two
+// consecutive doubles of memory per BK-deep chunk of op(X) (BR rows).
+// Untransposed X (X[r + k ldx]): slot j holds rows rl, rl+1 (rl even) of
+// chunk column kq + j KS.  Transposed X (X[k + r ldx]): slot j holds chunk
+// columns kq, kq+1 (kq even) of row rl + j RS.  Invalid slots (outside the
+// operand or the k range) read the operand's first pair and stage zeros, so
+// every chunk issues exactly PV global loads per operand and thread.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) v2d* gv2d_ptr;
+
+template <int BR, int NT>
+struct VStage {
+  static constexpr int PV = BR * BK / (2 * NT);
+  static constexpr int NP = BR / 2, KS = NT / NP;   // untransposed
+  static constexpr int NQ = BK / 2, RS = NT / NQ;   // transposed
+  static_assert(NT % NP == 0 && BK % KS == 0 && NT % NQ == 0 && BR % RS == 0, "map");
+  const double* base;  // operand origin (the safe address of invalid slots)
+  const double* p;     // slot 0 of the current chunk
+  int64_t step, adv;
+  int rl, kq;          // tile-relative row, chunk-relative k of slot 0
+  int kc, kend;        // current chunk's first k, k limit
+  bool trans;
+  unsigned rowok;      // bit j: slot j's row(s) inside the operand
+
+  __device__ __forceinline__ void init(const double* X, int64_t ldx, bool tr, int r0, int R,
+                                       int k0, int ke, int tid) {
+    base = X;
+    trans = tr;
+    kc = k0;
+    kend = ke;
+    rowok = 0;
+    if (!tr) {
+      rl = 2 * (tid % NP);
+      kq = tid / NP;
+      p = X + (r0 + rl) + (int64_t)(k0 + kq) * ldx;
+      step = (int64_t)KS * ldx;
+      adv = (int64_t)BK * ldx;
+      if (r0 + rl < R) rowok = (1u << PV) - 1;
+    } else {
+      kq = 2 * (tid % NQ);
+      rl = tid / NQ;
+      p = X + (k0 + kq) + (int64_t)(r0 + rl) * ldx;
+      step = (int64_t)RS * ldx;
+      adv = BK;
+#pragma unroll
+      for (int j = 0; j < PV; ++j)
+        if (r0 + rl + j * RS < R) rowok |= 1u << j;
+    }
+  }
+
+  __device__ __forceinline__ void load(v2d (&v)[PV]) const {
+#pragma unroll
+    for (int j = 0; j < PV; ++j) {
+      const int k = kc + kq + (trans ? 0 : j * KS);
+      const bool ok = ((rowok >> j) & 1u) && k < kend;
+      const double* a = ok ? p + j * step : base;
+      const v2d x = *(gv2d_ptr)a;
+      v[j] = ok ? x : (v2d){0.0, 0.0};
+    }
+  }
+
+  __device__ __forceinline__ void next() {
+    p += adv;
+    kc += BK;
+  }
+
+  __device__ __forceinline__ void store(double* __restrict__ S, const v2d (&v)[PV]) const {
+    constexpr int LD = BR + 2;
+    if (!trans) {
+#pragma unroll
+      for (int j = 0; j < PV; ++j) *(v2d*)(S + (kq + j * KS) * LD + rl) = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < PV; ++j) {
+        S[kq * LD + rl + j * RS] = v[j].x;
+        S[(kq + 1) * LD + rl + j * RS] = v[j].y;
+      }
+    }
+  }
+};
+
 // Tile order within a task: bands of GROUP tile rows, each band swept
 // column by column (lower-triangular tasks: the columns left of the band,
 // then its triangular diagonal block).  Consecutive tiles -- and so the
@@ -101,6 +186,21 @@ constexpr int GROUP = 8;
 
 __device__ __forceinline__ void tile_coords(const GemmTask& T, int lt, int& tm,
                                             int& tn) {
+  constexpr int KCOL = F_KLO_COL | F_KHI_COL, KROW = F_KLO_ROW | F_KHI_ROW;
+  if (!(T.flags & F_LOWER) && (T.flags & (KCOL | KROW))) {
+    // k range set by the tile column (or row): whole columns (rows) in
+    // order of decreasing length
+    if (T.flags & KCOL) {
+      const int c = lt / T.tiles_m;
+      tm = lt - c * T.tiles_m;
+      tn = (T.flags & F_KHI_COL) ? T.tiles_n - 1 - c : c;
+    } else {
+      const int r = lt / T.tiles_n;
+      tn = lt - r * T.tiles_n;
+      tm = (T.flags & F_KHI_ROW) ? T.tiles_m - 1 - r : r;
+    }
+    return;
+  }
   if (T.flags & F_LOWER) {
     const int nt = T.tiles_m;  // square tile grid
     int g = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5) / GROUP;
@@ -133,6 +233,41 @@ __device__ __forceinline__ void tile_coords(const GemmTask& T, int lt, int& tm,
 }
 }  // namespace
 
+// Whether an operand can be staged with VStage: 16-byte aligned, even
+// leading dimension, and pairs that never straddle the row count (staged
+// untransposed) or the k range (staged transposed).
+__device__ __forceinline__ bool vec_operand(const double* X, int64_t ldx, bool strans, int R,
+                                            int kb, int ke) {
+  if ((reinterpret_cast<uintptr_t>(X) & 15) != 0 || (ldx & 1) != 0) return false;
+  return strans ? ((kb & 1) == 0 && (ke & 1) == 0) : ((R & 1) == 0);
+}
+
+// acc += the product of one staged BK-deep chunk: wave (wm, wn) multiplies
+// its FM x FN blocks of 16 x 16.
+template <int BT, int WM, int WN>
+__device__ __forceinline__ void mma_chunk(const double* __restrict__ as,
+                                          const double* __restrict__ bs,
+                                          v4d (&acc)[BT / WM / 16][BT / WN / 16], int wm,
+                                          int wn, int lrow, int lk) {
+  constexpr int LD = BT + 2;
+  constexpr int SM = BT / WM, SN = BT / WN;
+  constexpr int FM = SM / 16, FN = SN / 16;
+#pragma unroll
+  for (int ks = 0; ks < BK / 4; ++ks) {
+    const int kk = ks * 4 + lk;
+    double fa[FM], fb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) fa[i] = as[kk * LD + wm * SM + i * 16 + lrow];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) fb[j] = bs[kk * LD + wn * SN + j * 16 + lrow];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
+  }
+}
+
 // One workgroup of WM x WN waves computes one BT x BT tile; wave (wm, wn)
 // owns rows wm*BT/WM .. and columns wn*BT/WN .. of it, FM x FN MFMA blocks
 // of 16 x 16.  MINW: waves per SIMD the register budget must allow.
@@ -148,7 +283,7 @@ __device__ __forceinline__ int find_unit_task(const GemmTask* __restrict__ tasks
   return lo;
 }
 
-template <int BT, int WM, int WN, int MINW>
+template <int BT, int WM, int WN, int MINW, int PF>
 __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
     const GemmTask* __restrict__ tasks, int ntask, double* __restrict__ partials) {
   constexpr int NT = WM * WN * 64;
@@ -156,11 +291,11 @@ __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
   constexpr int SM = BT / WM, SN = BT / WN;  // wave sub-tile
   constexpr int FM = SM / 16, FN = SN / 16;
   constexpr int PER = BT * BK / NT;  // staged doubles per thread per operand
-  __shared__ double As[2][BK * LD];
-  __shared__ double Bs[2][BK * LD];
+  __shared__ __attribute__((aligned(16))) double As[2][BK * LD];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
-  const int wid = xcd_tile(blockIdx.x, gridDim.x);
+  const int wid = (tasks[0].flags & F_KVAR) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int ti = find_unit_task(tasks, ntask, wid, false);
   const GemmTask T = tasks[ti];
   // slice-major: the workgroups of one XCD take one k piece of a compact
@@ -204,45 +339,67 @@ __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-  double va[PER], vb[PER];
-  if (nchunks > 0) {
-    load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, kb, ke, tid, va);
-    load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
-    store_chunk<BT, NT>(As[0], ta, tid, va);
-    store_chunk<BT, NT>(Bs[0], !tb, tid, vb);
-  }
-  __syncthreads();
-
-  for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
-    const bool more = (c + 1) < nchunks;
-    if (more) {
-      const int k1 = kb + (c + 1) * BK;
-      load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, k1, ke, tid, va);
-      load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
+  const bool vec_a = vec_operand(T.A, T.lda, ta, T.M, kb, ke);
+  const bool vec_b = vec_operand(T.B, T.ldb, !tb, T.N, kb, ke);
+  if (vec_a && vec_b) {
+    VStage<BT, NT> sa, sb;
+    sa.init(T.A, T.lda, ta, m0, T.M, kb, ke, tid);
+    sb.init(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid);
+    constexpr int PV = VStage<BT, NT>::PV;
+    v2d a0[PV], b0[PV];
+    sa.load(a0); sb.load(b0); sa.next(); sb.next();
+    if constexpr (PF == 1) {
+      sa.store(As[0], a0); sb.store(Bs[0], b0);
+      __syncthreads();
+      for (int c = 0; c < nchunks; ++c) {
+        sa.load(a0); sb.load(b0); sa.next(); sb.next();  // chunk c + 1
+        mma_chunk<BT, WM, WN>(As[c & 1], Bs[c & 1], acc, wm, wn, lrow, lk);
+        sa.store(As[(c + 1) & 1], a0); sb.store(Bs[(c + 1) & 1], b0);
+        __syncthreads();
+      }
+    } else {
+      // two chunks in flight: a0/b0 and a1/b1 alternate
+      v2d a1[PV], b1[PV];
+      sa.load(a1); sb.load(b1); sa.next(); sb.next();    // chunk 1
+      sa.store(As[0], a0); sb.store(Bs[0], b0);
+      __syncthreads();
+      for (int c = 0; c < nchunks; c += 2) {
+        sa.load(a0); sb.load(b0); sa.next(); sb.next();  // chunk c + 2
+        mma_chunk<BT, WM, WN>(As[0], Bs[0], acc, wm, wn, lrow, lk);
+        sa.store(As[1], a1); sb.store(Bs[1], b1);        // chunk c + 1
+        __syncthreads();
+        if (c + 1 >= nchunks) break;
+        sa.load(a1); sb.load(b1); sa.next(); sb.next();  // chunk c + 3
+        mma_chunk<BT, WM, WN>(As[1], Bs[1], acc, wm, wn, lrow, lk);
+        sa.store(As[0], a0); sb.store(Bs[0], b0);        // chunk c + 2
+        __syncthreads();
+      }
     }
-    const double* __restrict__ as = As[buf];
-    const double* __restrict__ bs = Bs[buf];
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kk = ks * 4 + lk;
-      double fa[FM], fb[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) fa[i] = as[kk * LD + wm * SM + i * 16 + lrow];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) fb[j] = bs[kk * LD + wn * SN + j * 16 + lrow];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i],
-                                                           acc[i][j], 0, 0, 0);
-    }
-    if (more) {
-      store_chunk<BT, NT>(As[buf ^ 1], ta, tid, va);
-      store_chunk<BT, NT>(Bs[buf ^ 1], !tb, tid, vb);
+  } else {
+    // scalar staging with per-element bounds (odd sizes, unaligned operands)
+    double va[PER], vb[PER];
+    if (nchunks > 0) {
+      load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, kb, ke, tid, va);
+      load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
+      store_chunk<BT, NT>(As[0], ta, tid, va);
+      store_chunk<BT, NT>(Bs[0], !tb, tid, vb);
     }
     __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const int buf = c & 1;
+      const bool more = (c + 1) < nchunks;
+      if (more) {
+        const int k1 = kb + (c + 1) * BK;
+        load_chunk<BT, NT>(T.A, T.lda, ta, m0, T.M, k1, ke, tid, va);
+        load_chunk<BT, NT>(T.B, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
+      }
+      mma_chunk<BT, WM, WN>(As[buf], Bs[buf], acc, wm, wn, lrow, lk);
+      if (more) {
+        store_chunk<BT, NT>(As[buf ^ 1], ta, tid, va);
+        store_chunk<BT, NT>(Bs[buf ^ 1], !tb, tid, vb);
+      }
+      __syncthreads();
+    }
   }
 
   if (slot >= 0) {
@@ -318,7 +475,11 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict_
 int finalize_tasks(GemmTask* t, int n, int tile, int* nred, int64_t* nslots) {
   int total = 0, units = 0, red = 0;
   int64_t slots = 0;
+  bool kvar = false;
+  for (int i = 0; i < n; ++i)
+    kvar = kvar || (t[i].flags & (F_KLO_COL | F_KHI_COL | F_KLO_ROW | F_KHI_ROW));
   for (int i = 0; i < n; ++i) {
+    t[i].flags = kvar ? (t[i].flags | F_KVAR) : (t[i].flags & ~F_KVAR);
     t[i].tiles_m = (t[i].M + tile - 1) / tile;
     t[i].tiles_n = (t[i].N + tile - 1) / tile;
     if (t[i].M <= 0 || t[i].N <= 0) {
@@ -351,10 +512,10 @@ hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask, int units,
                              hipStream_t s, int tile, double* partials) {
   if (units <= 0) return hipSuccess;
   if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4, 4>), dim3(units), dim3(512), 0, s,
+    hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4, 4, 1>), dim3(units), dim3(512), 0, s,
                        tasks_dev, ntask, partials);
   else
-    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2, 1>), dim3(units), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2, 4, 2>), dim3(units), dim3(256), 0, s,
                        tasks_dev, ntask, partials);
   return hipGetLastError();
 }
@@ -442,7 +603,7 @@ __global__ __launch_bounds__(256) void k_gemm32_tasks(
   __shared__ float Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = (tasks[0].flags & F_KVAR) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const int ti = find_task(tasks, ntask, tile);
   const GemmTask T = tasks[ti];
   int tm, tn;

@@ -30,6 +30,10 @@ def _colmajor(x):
 @pytest.mark.parametrize("M,N,K,ta,tb", [
     (64, 64, 64, 0, 1), (130, 70, 33, 0, 0), (128, 192, 100, 1, 0),
     (65, 200, 17, 1, 1), (256, 256, 256, 0, 1), (1, 1, 1, 0, 0),
+    # vector-staged operands: even extents, 16-byte aligned columns; odd and
+    # even chunk counts, partial edge tiles inside the vector path
+    (384, 320, 272, 0, 1), (320, 384, 208, 1, 0), (130, 66, 48, 1, 1),
+    (66, 130, 32, 0, 0), (192, 64, 16, 1, 1),
 ])
 def test_dgemm_matches_numpy(D, M, N, K, ta, tb):
     rng = np.random.default_rng(M * 7 + N)
