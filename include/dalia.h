@@ -214,16 +214,21 @@ dl_status dl_dgemm(int32_t transa, int32_t transb, int32_t lower, int64_t M,
 dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
                     double* logdet_dev, int64_t* info_dev, void* stream);
 
-/* Pick the FP64 GEMM tile (64x64 or 128x128 outputs per workgroup) of every
- * matrix-product launch of the workspace by timing both on the device,
- * once per distinct launch shape; choices are appended to / read from the
- * text file cache_path (may be NULL).  Synchronises the stream; the
+/* Pick the GEMM tile (64x64 or 128x128 outputs per workgroup) of every
+ * matrix-product launch of the workspace, and for FP64 launches with a k
+ * extent above 512 whether to split k (pieces summed by a second launch),
+ * by timing the candidates on the device once per distinct launch shape;
+ * choices are appended to / read from the text file cache_path (may be
+ * NULL; one line per shape ending in the tile, suffixed "s" when split).
+ * May grow the workspace's device memory by the split partial tiles.
+ * Synchronises the stream; the
  * workspace's matrices must be re-assembled afterwards (fobj_eval always
  * does).  Call before the first evaluation of a DL_WS_GRAPH workspace. */
 dl_status dl_autotune(dl_ws* ws, const char* cache_path, void* stream);
 dl_status dl_ws_tile_counts(const dl_ws* ws, int64_t* n64, int64_t* n128);
 /* Set the tile (64 or 128) of every matrix-product launch, overriding the
- * default and any tuned choice (measurement and tests).  DL_EINVAL for
+ * default and any tuned choice; each launch keeps its split-k setting
+ * (measurement and tests).  DL_EINVAL for
  * other sizes, DL_ESTATE once a graph has been captured. */
 dl_status dl_ws_force_tile(dl_ws* ws, int32_t tile);
 

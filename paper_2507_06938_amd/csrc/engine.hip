@@ -389,6 +389,7 @@ struct dl_ws {
   bool sel = false, keep_qp = false, mixed = false;
   bool splitk = false;
   double* partials = nullptr;  // split-k partial tiles (shared by all launches)
+  int64_t partials_cap = 0;    // doubles allocated at `partials`
   int dim_total = 0;
   double* theta_all = nullptr;   // packed theta of all instances
   double* f_all = nullptr;       // [B]
@@ -412,6 +413,26 @@ struct dl_ws {
   std::vector<int> prof_cat;
   std::vector<double> prof_flops, prof_bytes;
 };
+
+// Grow the split-k partial-tile buffer to at least `elems` doubles (work on
+// `s` that may still read the old buffer is waited for first).
+static dl_status ensure_partials(dl_ws* W, int64_t elems, hipStream_t s) {
+  if (elems <= W->partials_cap) return DL_OK;
+  if (W->partials) {
+    DL_HIP_CHECK(hipStreamSynchronize(s));
+    DL_HIP_CHECK(hipFree(W->partials));
+    W->bytes -= sizeof(double) * (size_t)W->partials_cap;
+    W->partials = nullptr;
+    W->partials_cap = 0;
+  }
+  if (hipMalloc((void**)&W->partials, sizeof(double) * (size_t)elems) != hipSuccess) {
+    W->partials = nullptr;
+    return DL_ENOMEM;
+  }
+  W->partials_cap = elems;
+  W->bytes += sizeof(double) * (size_t)elems;
+  return DL_OK;
+}
 
 static int prof_begin(dl_ws* W, int cat, int kind, hipStream_t s) {
   if (!W->prof_mask || !((W->prof_mask >> cat) & 1)) return -1;
@@ -1006,8 +1027,7 @@ static dl_status build_plans(dl_ws* W) {
   }
   // upload descriptor arrays
   dl_status st = DL_OK;
-  if (pmax > 0)
-    st = dev_alloc(W->allocs, sizeof(double) * pmax, (void**)&W->partials, &W->bytes);
+  if (pmax > 0) st = ensure_partials(W, pmax, nullptr);
   auto up = [&](auto& vec, auto*& dptr) {
     using T = typename std::remove_reference<decltype(vec)>::type::value_type;
     if (st != DL_OK) return;
@@ -1042,6 +1062,7 @@ static void ws_free(dl_ws* W) {
   if (W->graph_exec) (void)hipGraphExecDestroy(W->graph_exec);
   if (W->graph) (void)hipGraphDestroy(W->graph);
   if (W->cap_stream) (void)hipStreamDestroy(W->cap_stream);
+  if (W->partials) (void)hipFree(W->partials);
   free_all(W->allocs);
   delete W;
 }
@@ -1452,31 +1473,48 @@ static std::string gemm_signature(const dl_ws* W, const Launch& L) {
     << " n" << L.count;
   for (int i = 0; i < L.count && i < 8; ++i) {
     const GemmTask& t = W->H.gemm[L.off + i];
-    o << " " << t.M << "x" << t.N << "x" << t.K << "f" << (t.flags & ~F_BETA0);
+    o << " " << t.M << "x" << t.N << "x" << t.K << "f" << (t.flags & ~(F_BETA0 | F_SPLIT));
   }
   return o.str();
 }
 
-static dl_status retile(dl_ws* W, Launch& L, int tile) {
+// Tile size and split k of one matrix-product launch (split applies to the
+// FP64 kernel only).
+static dl_status retile(dl_ws* W, Launch& L, int tile, bool split, hipStream_t s) {
+  GemmTask* t = W->H.gemm.data() + L.off;
+  if (L.kind == OP_GEMM)
+    for (int i = 0; i < L.count; ++i)
+      t[i].flags = split ? (t[i].flags | F_SPLIT) : (t[i].flags & ~F_SPLIT);
+  int64_t slots = 0;
   L.tile = tile;
-  L.gx = finalize_tasks(W->H.gemm.data() + L.off, L.count, tile, &L.nred);
-  DL_HIP_CHECK(hipMemcpy(W->Dd.gemm + L.off, W->H.gemm.data() + L.off,
-                         sizeof(GemmTask) * L.count, hipMemcpyHostToDevice));
+  L.gx = finalize_tasks(t, L.count, tile, &L.nred, &slots);
+  if (slots > 0) {
+    const dl_status st = ensure_partials(W, slots * tile * tile, s);
+    if (st != DL_OK) return st;
+  }
+  DL_HIP_CHECK(hipMemcpy(W->Dd.gemm + L.off, t, sizeof(GemmTask) * L.count,
+                         hipMemcpyHostToDevice));
   return DL_OK;
+}
+
+static bool launch_split(const dl_ws* W, const Launch& L) {
+  return L.kind == OP_GEMM && L.count > 0 && (W->H.gemm[L.off].flags & F_SPLIT);
 }
 
 extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream) {
   if (!W) return DL_EINVAL;
   if (W->graph_exec) return DL_ESTATE;  // tune before the first graph capture
   hipStream_t s = (hipStream_t)stream;
-  std::unordered_map<std::string, int> best;
+  // cache lines: "<signature> <tile>" or "<signature> <tile>s" (split k)
+  std::unordered_map<std::string, std::pair<int, bool>> best;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       const size_t sp = line.rfind(' ');
-      if (sp == std::string::npos) continue;
-      best[line.substr(0, sp)] = atoi(line.c_str() + sp + 1);
+      if (sp == std::string::npos || sp + 1 >= line.size()) continue;
+      const std::string v = line.substr(sp + 1);
+      best[line.substr(0, sp)] = {atoi(v.c_str()), v.back() == 's'};
     }
   }
   std::vector<std::string> fresh;
@@ -1489,32 +1527,43 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
     const std::string sig = gemm_signature(W, L);
     auto it = best.find(sig);
     if (it == best.end()) {
+      // split k is a candidate when some task has more than one k piece
+      bool can_split = false;
+      if (L.kind == OP_GEMM)
+        for (int i = 0; i < L.count; ++i)
+          can_split = can_split || W->H.gemm[L.off + i].K > GEMM_KSPLIT;
       float tbest = 1e30f;
-      int choice = 64;
-      for (int tile : {64, 128}) {
-        if ((st = retile(W, L, tile)) != DL_OK) break;
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-          (void)hipEventRecord(e0, s);
-          (void)run_launch(W, L, s);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          tmin = std::min(tmin, ms);
+      std::pair<int, bool> choice{64, false};
+      for (int sp = 0; sp < (can_split ? 2 : 1) && st == DL_OK; ++sp)
+        for (int tile : {64, 128}) {
+          if ((st = retile(W, L, tile, sp == 1, s)) != DL_OK) break;
+          float tmin = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, s);
+            (void)run_launch(W, L, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+          }
+          if (tmin < tbest) {
+            tbest = tmin;
+            choice = {tile, sp == 1};
+          }
         }
-        if (tmin < tbest) { tbest = tmin; choice = tile; }
-      }
       it = best.emplace(sig, choice).first;
       fresh.push_back(sig);
     }
-    if (st == DL_OK && L.tile != it->second) st = retile(W, L, it->second);
+    if (st == DL_OK && (L.tile != it->second.first || launch_split(W, L) != it->second.second))
+      st = retile(W, L, it->second.first, it->second.second, s);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st == DL_OK && cache_path && !fresh.empty()) {
     std::ofstream out(cache_path, std::ios::app);
-    for (const auto& sig : fresh) out << sig << " " << best[sig] << "\n";
+    for (const auto& sig : fresh)
+      out << sig << " " << best[sig].first << (best[sig].second ? "s" : "") << "\n";
   }
   return st;
 }
@@ -1524,7 +1573,7 @@ extern "C" dl_status dl_ws_force_tile(dl_ws* W, int32_t tile) {
   if (W->graph_exec) return DL_ESTATE;
   for (Launch& L : W->table) {
     if (L.kind != OP_GEMM && L.kind != OP_GEMM32) continue;
-    const dl_status st = retile(W, L, tile);
+    const dl_status st = retile(W, L, tile, launch_split(W, L), nullptr);
     if (st != DL_OK) return st;
   }
   return DL_OK;

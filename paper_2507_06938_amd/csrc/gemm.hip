@@ -28,6 +28,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int BK = 16;
+// LDS row padding of the staged chunks (doubles)
+constexpr int LPAD = 2;
 
 __device__ __forceinline__ int find_task(const GemmTask* __restrict__ tasks,
                                          int ntask, int tile) {
@@ -81,7 +83,7 @@ template <int BR, int NT>
 __device__ __forceinline__ void store_chunk(double* __restrict__ S, bool trans,
                                             int tid, const double (&v)[BR * BK / NT]) {
   constexpr int PER = BR * BK / NT;
-  constexpr int LD = BR + 2;
+  constexpr int LD = BR + LPAD;
   if (!trans) {
     const int r = tid % BR;
     const int kb = (tid / BR) * PER;
@@ -163,7 +165,7 @@ struct VStage {
   }
 
   __device__ __forceinline__ void store(double* __restrict__ S, const v2d (&v)[PV]) const {
-    constexpr int LD = BR + 2;
+    constexpr int LD = BR + LPAD;
     if (!trans) {
 #pragma unroll
       for (int j = 0; j < PV; ++j) *(v2d*)(S + (kq + j * KS) * LD + rl) = v[j];
@@ -243,28 +245,51 @@ __device__ __forceinline__ bool vec_operand(const double* X, int64_t ldx, bool s
 }
 
 // acc += the product of one staged BK-deep chunk: wave (wm, wn) multiplies
-// its FM x FN blocks of 16 x 16.
+// its FM x FN blocks of 16 x 16.  With few blocks per wave (64-wide tiles)
+// all fragments of the chunk are read from LDS first, so the MFMAs of one
+// k step overlap the reads of the next.
 template <int BT, int WM, int WN>
 __device__ __forceinline__ void mma_chunk(const double* __restrict__ as,
                                           const double* __restrict__ bs,
                                           v4d (&acc)[BT / WM / 16][BT / WN / 16], int wm,
                                           int wn, int lrow, int lk) {
-  constexpr int LD = BT + 2;
+  constexpr int LD = BT + LPAD;
   constexpr int SM = BT / WM, SN = BT / WN;
   constexpr int FM = SM / 16, FN = SN / 16;
+  if constexpr (FM + FN <= 4) {
+    double fa[BK / 4][FM], fb[BK / 4][FN];
 #pragma unroll
-  for (int ks = 0; ks < BK / 4; ++ks) {
-    const int kk = ks * 4 + lk;
-    double fa[FM], fb[FN];
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
 #pragma unroll
-    for (int i = 0; i < FM; ++i) fa[i] = as[kk * LD + wm * SM + i * 16 + lrow];
+      for (int i = 0; i < FM; ++i) fa[ks][i] = as[kk * LD + wm * SM + i * 16 + lrow];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) fb[j] = bs[kk * LD + wn * SN + j * 16 + lrow];
+      for (int j = 0; j < FN; ++j) fb[ks][j] = bs[kk * LD + wn * SN + j * 16 + lrow];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int ks = 0; ks < BK / 4; ++ks)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[ks][j], fa[ks][i], acc[i][j],
+                                                           0, 0, 0);
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      double fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[i] = as[kk * LD + wm * SM + i * 16 + lrow];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) fb[j] = bs[kk * LD + wn * SN + j * 16 + lrow];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j], fa[i], acc[i][j], 0, 0, 0);
+    }
   }
 }
 
@@ -287,7 +312,7 @@ template <int BT, int WM, int WN, int MINW, int PF>
 __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
     const GemmTask* __restrict__ tasks, int ntask, double* __restrict__ partials) {
   constexpr int NT = WM * WN * 64;
-  constexpr int LD = BT + 2;
+  constexpr int LD = BT + LPAD;
   constexpr int SM = BT / WM, SN = BT / WN;  // wave sub-tile
   constexpr int FM = SM / 16, FN = SN / 16;
   constexpr int PER = BT * BK / NT;  // staged doubles per thread per operand
@@ -515,7 +540,7 @@ hipError_t launch_gemm_tasks(const GemmTask* tasks_dev, int ntask, int units,
     hipLaunchKernelGGL((k_gemm_tasks<128, 2, 4, 4, 1>), dim3(units), dim3(512), 0, s,
                        tasks_dev, ntask, partials);
   else
-    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2, 4, 2>), dim3(units), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gemm_tasks<64, 2, 2, 4, 1>), dim3(units), dim3(256), 0, s,
                        tasks_dev, ntask, partials);
   return hipGetLastError();
 }

@@ -125,8 +125,9 @@ def test_graph_replays_match_eager(D):
 
 def test_autotuned_tiles_give_identical_results(D, tmp_path):
     """Both GEMM tile sizes sum each output over the same k sequence (extra
-    terms are exact zeros), so a tuned workspace reproduces the default one
-    bit for bit; the cache file is written and reused."""
+    terms are exact zeros), so a tuned workspace whose products are too short
+    to split (k <= 512) reproduces the default one bit for bit; the cache
+    file is written and reused."""
     wl = W.scaled("tune", 12, 4, 1, 2, 200, seed=9)
     model = D.Model.from_workload(wl)
     ws = D.Workspace(model, selinv=True)
@@ -144,3 +145,29 @@ def test_autotuned_tiles_give_identical_results(D, tmp_path):
     assert lines and all(l.rsplit(" ", 1)[1] in ("64", "128") for l in lines)
     ws2 = D.Workspace(model, selinv=True)
     assert ws2.autotune(cache) == counts   # read back from the cache
+
+
+def test_autotune_with_split_candidates(D, tmp_path):
+    """Blocks of 576 (k > 512): the tuner may also choose split k, which sums
+    the k pieces separately, so results agree with the default workspace to
+    rounding; a second workspace reads every choice back from the cache."""
+    wl = W.scaled("tune_split", 24, 3, 1, 2, 400, seed=4)
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True)
+    f0, p0, _ = ws.fobj(wl.theta)
+    v0 = ws.selinv().cpu().numpy()
+    cache = str(tmp_path / "tiles.txt")
+    counts = ws.autotune(cache)
+    f1, p1, _ = ws.fobj(wl.theta)
+    v1 = ws.selinv().cpu().numpy()
+    torch.cuda.synchronize()
+    assert abs(f1.item() - f0.item()) <= 1e-12 * abs(f0.item())
+    np.testing.assert_allclose(p1.cpu().numpy(), p0.cpu().numpy(), rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(v1, v0, rtol=1e-10)
+    lines = open(cache).read().splitlines()
+    assert lines and all(l.rsplit(" ", 1)[1] in ("64", "128", "64s", "128s") for l in lines)
+    ws2 = D.Workspace(model, selinv=True)
+    assert ws2.autotune(cache) == counts
+    f2, _, _ = ws2.fobj(wl.theta)
+    torch.cuda.synchronize()
+    assert f2.item() == f1.item()
