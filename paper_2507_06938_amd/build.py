@@ -55,7 +55,20 @@ def build(verbose: bool = True) -> str:
     shutil.move(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_microbench(verbose)
     return LIB
+
+
+def build_microbench(verbose: bool = True) -> str:
+    """The GEMM microbenchmark executable (microbench/gemm_bench)."""
+    src = os.path.join(HERE, "microbench", "gemm_bench.hip")
+    exe = os.path.join(HERE, "microbench", "gemm_bench")
+    r = subprocess.run([HIPCC, *FLAGS, src, "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    if verbose:
+        print(f"built {exe}")
+    return exe
 
 
 if __name__ == "__main__":
