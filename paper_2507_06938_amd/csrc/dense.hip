@@ -8,8 +8,8 @@ namespace {
 constexpr int NB = 64;
 constexpr int LDL = NB + 2;         // LDS row stride: 528 B, 16-byte aligned rows
 constexpr int TILE_LDS = NB * LDL;  // doubles of one staged 64 x 64 tile
-constexpr int POTRF_CW = 8;         // columns per wave of the tile factor
-constexpr int POTRF_NT = NB / POTRF_CW * 64;  // threads of a tile-factor workgroup
+constexpr int POTRF_CW = 4;         // columns per wave (one panel) of the tile factor
+constexpr int POTRF_NT = NB / POTRF_CW * 64;  // threads of a tile-factor workgroup (16 waves)
 typedef double v4d __attribute__((ext_vector_type(4)));
 }
 
@@ -31,22 +31,20 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// Two 16x16 blocks of a product of LDS tiles stored S[k*LDL + c]:
-//   D[a][b] = sum_{k < kmax} P[k][p0 + a] Q[k][q0 + b]   (and q0 + 16 for acc1),
+// One 16x16 block of a product of LDS tiles stored S[k*LDL + c]:
+//   D[a][b] = sum_{k < kmax} P[k][p0 + a] Q[k][q0 + b],
 // on v_mfma_f64_16x16x4_f64 (lane l supplies P[k0 + l/16][p0 + l%16] as the
 // "A" operand and Q[k0 + l/16][q0 + l%16] as "B"; register r of lane l
 // receives D[l/16 + 4r][l%16]).  kmax: multiple of 4, at most 64.
-__device__ __forceinline__ void mfma2_k64(const double* P, int p0, const double* Q,
-                                          int q0, v4d& acc0, v4d& acc1, int kmax = NB) {
+__device__ __forceinline__ void mfma1_k64(const double* P, int p0, const double* Q,
+                                          int q0, v4d& acc, int kmax = NB) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = l >> 4;
 #pragma unroll 4
   for (int k0 = 0; k0 < kmax; k0 += 4) {
     const double a = P[(k0 + lk) * LDL + p0 + lr];
-    const double b0 = Q[(k0 + lk) * LDL + q0 + lr];
-    const double b1 = Q[(k0 + lk) * LDL + q0 + 16 + lr];
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    const double b = Q[(k0 + lk) * LDL + q0 + lr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
 }
 
@@ -62,22 +60,20 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ X, int64_t
 }
 
 // Cholesky A = L L^T of one 64 x 64 SPD tile and G = L^{-1}, by one
-// workgroup of 8 waves.  Lane i of wave w keeps row i of columns
-// CW*w .. CW*w+CW-1 of the trailing matrix (r) and rows CW*w .. CW*w+CW-1 of
-// column i of the inverse being eliminated (g).  Step s (one barrier a step):
-//  * the wave owning column s reads the pivot from lane s, forms
-//    L(:, s) = A(:, s) / sqrt(A(s, s)) (zero above the diagonal) with one
-//    reciprocal square root, and publishes it to LDS;
-//  * the wave owning row s-1 of the inverse scales it by 1/L(s-1, s-1)
-//    (the reciprocal it formed one step earlier) and publishes it;
-//  * after the barrier every wave applies the rank-1 update of column s to
-//    its columns and the elimination of row s-1 to its rows of G.
-// Both updates are applied to every column / row a wave holds: the
-// multipliers above the diagonal are exact zeros, and the one column (row)
-// that an update spoils is already final in LDS, from where the results are
-// written.  Every LDS slot is written once, so one barrier a step suffices.
-// The loop over owners is rolled and the CW steps of one owner unrolled
-// (static register indices, code within the instruction cache).
+// workgroup of NB/CW waves.  Lane i of wave w keeps row i of the CW columns
+// CW*w .. CW*w+CW-1 (panel w) of the trailing matrix (r) and the same rows of
+// column i of the inverse being eliminated (g).  Panels are factored in
+// order, one barrier each.  Iteration k:
+//  * wave k factors panel k in its registers: per column s, the pivot from
+//    lane s (v_readlane), one reciprocal square root, L(:, s) = A(:, s) /
+//    sqrt(A(s, s)) (zero above the diagonal), and the update of the panel's
+//    later columns with L(c, s) taken from lane c; it then forms rows
+//    CW*k .. of G by the same eliminations on g, and publishes both to LDS;
+//  * after the barrier every later wave applies the rank-CW update of panel
+//    k to its columns and its rows of G (L and G rows read back from LDS).
+// Each element receives its updates one FMA per column, in column order, so
+// the results do not depend on CW.  Every LDS slot is written once, so one
+// barrier a panel suffices.
 //
 // src/lds: the tile (column-major, global or LDS); Lc, Gk: two LDS tiles of
 // TILE_LDS doubles (Lc[k*LDL + i] = L(i, k), Gk[k*LDL + c] = G(k, c)).
@@ -93,50 +89,66 @@ __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, doubl
   const int i = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (threadIdx.x == 0) *sbad = NB;
-  double r[CW], g[CW], lp[CW];
+  double r[CW], g[CW];
 #pragma unroll
   for (int q = 0; q < CW; ++q) {
     r[q] = src[(int64_t)i + (int64_t)(CW * wv + q) * lds];
     g[q] = (CW * wv + q == i) ? 1.0 : 0.0;
-    lp[q] = 0.0;
   }
-  double rsp = 0.0;  // owner's 1/L(s-1, s-1) from its previous step
   __syncthreads();
 #pragma unroll 1
-  for (int kb = 0; kb < NW; ++kb) {
+  for (int k = 0; k < NW; ++k) {
+    const int c0 = CW * k;
+    if (wv == k) {
+      double rsv[CW], Ls[CW][CW];
+      int bad = NB;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      const int s = kb * CW + q;
-      // row s-1 of the inverse: owned by the wave that owned column s-1
-      if (q > 0 ? (wv == kb) : (kb > 0 && wv == kb - 1)) {
-        Gk[(s - 1) * LDL + i] = g[(q + CW - 1) % CW] * rsp;
-      }
-      if (wv == kb) {
+      for (int q = 0; q < CW; ++q) {
+        const int s = c0 + q;
         const double d = readlane_f64(r[q], s);
         const bool ok = d > 0.0;  // false for NaN too
-        if (!ok && i == 0) atomicMin(sbad, s);
-        const double rs = ok ? rsqrt_nr(d) : __builtin_nan("");
-        Lc[s * LDL + i] = (i > s) ? r[q] * rs : (i == s ? d * rs : 0.0);
-        rsp = rs;
-      }
-      __syncthreads();
-      const double lik = Lc[s * LDL + i];
-      double ls[CW];
+        bad = ok ? bad : min(bad, s);
+        const double rs = rsqrt_nr(ok ? d : __builtin_nan(""));
+        rsv[q] = rs;
+        r[q] = (i > s) ? r[q] * rs : (i == s ? d * rs : 0.0);
 #pragma unroll
-      for (int qq = 0; qq < CW; ++qq) ls[qq] = Lc[s * LDL + CW * wv + qq];
-#pragma unroll
-      for (int qq = 0; qq < CW; ++qq) r[qq] = __builtin_fma(-lik, ls[qq], r[qq]);
-      if (s > 0) {
-        const double gk = Gk[(s - 1) * LDL + i];
-#pragma unroll
-        for (int qq = 0; qq < CW; ++qq) g[qq] = __builtin_fma(-lp[qq], gk, g[qq]);
+        for (int qq = q + 1; qq < CW; ++qq) {
+          Ls[qq][q] = readlane_f64(r[q], c0 + qq);  // L(c0 + qq, s)
+          r[qq] = __builtin_fma(-r[q], Ls[qq][q], r[qq]);
+        }
       }
 #pragma unroll
-      for (int qq = 0; qq < CW; ++qq) lp[qq] = ls[qq];
+      for (int q = 0; q < CW; ++q) Lc[(c0 + q) * LDL + i] = r[q];
+      // rows c0 .. of G: scale by 1/L(s, s), eliminate within the panel
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        g[q] *= rsv[q];
+#pragma unroll
+        for (int qq = q + 1; qq < CW; ++qq) g[qq] = __builtin_fma(-Ls[qq][q], g[q], g[qq]);
+      }
+#pragma unroll
+      for (int q = 0; q < CW; ++q) Gk[(c0 + q) * LDL + i] = g[q];
+      if (bad < NB && i == 0) atomicMin(sbad, bad);
+    }
+    __syncthreads();
+    if (wv > k) {
+      double li[CW], gi[CW];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        li[q] = Lc[(c0 + q) * LDL + i];
+        gi[q] = Gk[(c0 + q) * LDL + i];
+      }
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+#pragma unroll
+        for (int qq = 0; qq < CW; ++qq) {
+          const double ls = Lc[(c0 + q) * LDL + CW * wv + qq];  // L(CW*wv + qq, c0 + q)
+          r[qq] = __builtin_fma(-li[q], ls, r[qq]);
+          g[qq] = __builtin_fma(-ls, gi[q], g[qq]);
+        }
+      }
     }
   }
-  if (wv == NW - 1) Gk[(NB - 1) * LDL + i] = g[CW - 1] * rsp;
-  __syncthreads();
   if (wv == 0 && logdiag) logdiag[i] = log(Lc[i * LDL + i]);
   if (threadIdx.x == 0 && *sbad < NB && info)
     atomicCAS((unsigned long long*)info, 0ull, (unsigned long long)(row0 + *sbad + 1));
@@ -180,8 +192,9 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
 //   L_I = P_j(I) G_jj^T and L_J = P_j(J) G_jj^T  (G_jj lower triangular:
 //        block column c of L needs k < 16 (c + 1) only),
 //   A(I, J) -= L_I L_J^T,
-// on FP64 MFMA with the operand roles chosen so that a lane's results lie
-// along the rows of the column-major output (coalesced stores).  Every
+// on FP64 MFMA, one 16 x 16 block per wave, with the operand roles chosen so
+// that a lane's results lie along the rows of the column-major output
+// (coalesced stores).  Every
 // global load (the operand tiles and the elements of A(I, J) a lane updates)
 // is issued before the first LDS store, so their latencies overlap.  The
 // factoring workgroup (I = J) forms L_I once, stages the updated tile in LDS
@@ -219,10 +232,10 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = l >> 4;
-  const int p0 = 16 * (wv >> 1), q0 = 32 * (wv & 1);
+  const int p0 = 16 * (wv >> 2), q0 = 16 * (wv & 3);  // this wave's 16 x 16 block
   double* C = T.A + ti0 + tj0 * T.ld;
   constexpr int PER = NB * NB / POTRF_NT;
-  double vp[PER], vg[PER], vq[PER], cpre[8];
+  double vp[PER], vg[PER], vq[PER], cpre[4];
   {
     const double* Pi = T.A + ti0 + pc;
     const double* Gj = T.A + (int64_t)T.j * NB * (T.ld + 1);  // G_jj
@@ -236,11 +249,7 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
       vq[e] = (I != J) ? Pj[o] : 0.0;
     }
 #pragma unroll
-    for (int rg = 0; rg < 4; ++rg) {
-      const double* c0 = C + (q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld;
-      cpre[rg] = c0[0];
-      cpre[4 + rg] = c0[16];
-    }
+    for (int rg = 0; rg < 4; ++rg) cpre[rg] = C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = threadIdx.x + e * POTRF_NT;
@@ -252,42 +261,30 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   }
   __syncthreads();
   // L^T = G P^T: D[c][m] = sum_k G(c, k) P(m, k), k <= c < p0 + 16
-  v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-  v4d b0 = {0.0, 0.0, 0.0, 0.0}, b1 = {0.0, 0.0, 0.0, 0.0};
-  mfma2_k64(S1, p0, S0, q0, a0, a1, p0 + 16);  // L_I(m = q0 + lr (+16), c = p0 + lk + 4r)
-  if (I != J) mfma2_k64(S1, p0, S2, q0, b0, b1, p0 + 16);
+  v4d a0 = {0.0, 0.0, 0.0, 0.0}, b0 = {0.0, 0.0, 0.0, 0.0};
+  mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L_I(m = q0 + lr, c = p0 + lk + 4r)
+  if (I != J) mfma1_k64(S1, p0, S2, q0, b0, p0 + 16);
   __syncthreads();
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg) {
     const int c = p0 + lk + 4 * rg;
     S0[c * LDL + q0 + lr] = a0[rg];
-    S0[c * LDL + q0 + 16 + lr] = a1[rg];
-    if (I != J) {
-      S2[c * LDL + q0 + lr] = b0[rg];
-      S2[c * LDL + q0 + 16 + lr] = b1[rg];
-    }
+    if (I != J) S2[c * LDL + q0 + lr] = b0[rg];
   }
   __syncthreads();
   // (L_I L_J^T)^T = L_J L_I^T: D[n][m] = sum_c L_J(n, c) L_I(m, c)
   const double* LJ = (I != J) ? S2 : S0;
-  v4d u0 = {0.0, 0.0, 0.0, 0.0}, u1 = {0.0, 0.0, 0.0, 0.0};
-  mfma2_k64(LJ, p0, S0, q0, u0, u1);  // u: update(m = q0 + lr (+16), n = p0 + lk + 4r)
+  v4d u0 = {0.0, 0.0, 0.0, 0.0};
+  mfma1_k64(LJ, p0, S0, q0, u0);  // u: update(m = q0 + lr, n = p0 + lk + 4r)
   if (!fac) {
 #pragma unroll
-    for (int rg = 0; rg < 4; ++rg) {
-      double* c0 = C + (q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld;
-      c0[0] = cpre[rg] - u0[rg];
-      c0[16] = cpre[4 + rg] - u1[rg];
-    }
+    for (int rg = 0; rg < 4; ++rg)
+      C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld] = cpre[rg] - u0[rg];
     return;
   }
   __syncthreads();  // S1 (G_jj) is read no more
 #pragma unroll
-  for (int rg = 0; rg < 4; ++rg) {
-    const int n = p0 + lk + 4 * rg;
-    S1[n * LDL + q0 + lr] = cpre[rg] - u0[rg];
-    S1[n * LDL + q0 + 16 + lr] = cpre[4 + rg] - u1[rg];
-  }
+  for (int rg = 0; rg < 4; ++rg) S1[(p0 + lk + 4 * rg) * LDL + q0 + lr] = cpre[rg] - u0[rg];
   __syncthreads();
   potrf_body<POTRF_CW>(S1, LDL, S0, S2, &sbad, C, T.ld, nullptr, T.logdiag, T.info,
                        T.row0, 1);
