@@ -231,6 +231,13 @@ dl_status dl_ws_tile_counts(const dl_ws* ws, int64_t* n64, int64_t* n128);
  * (measurement and tests).  DL_EINVAL for
  * other sizes, DL_ESTATE once a graph has been captured. */
 dl_status dl_ws_force_tile(dl_ws* ws, int32_t tile);
+/* Split the k range of every FP64 matrix-product launch into pieces of
+ * ksplit (a multiple of 16, at least 64; cut at absolute multiples, so
+ * results do not depend on the tile size), or unsplit them (ksplit = 0),
+ * overriding the default and any tuned choice (measurement and tests).  May
+ * grow the workspace's device memory by the partial tiles.  DL_EINVAL for
+ * other values, DL_ESTATE once a graph has been captured. */
+dl_status dl_ws_force_split(dl_ws* ws, int32_t ksplit);
 
 /* ---- surrogate network (learned model of f_obj over theta) ----------------
  * Multi-layer perceptron sizes[0] -> ... -> sizes[n-1] = 1, SiLU between

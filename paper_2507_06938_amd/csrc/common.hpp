@@ -49,8 +49,9 @@ enum : int {
   F_KVAR = 4096,
 };
 
-// Split k.  For an F_SPLIT task with K > GEMM_KSPLIT, the k range [kb, ke) of
-// each tile is cut at the absolute multiples of GEMM_KSPLIT and every piece
+// Split k.  For an F_SPLIT task with K > ksplit (the task's piece length,
+// GEMM_KSPLIT when 0; a multiple of 16), the k range [kb, ke) of each tile is
+// cut at the absolute multiples of ksplit and every piece
 // is one workgroup.  A tile with several pieces writes each raw product to a
 // partial tile (BT x BT doubles, column-major) and a second launch forms
 // C = alpha * (sum of the pieces in k order) + beta * C; a tile with one
@@ -75,6 +76,9 @@ struct GemmTask {
   int32_t unit_begin;        // first workgroup of this task in its launch
   int32_t pslot_begin;       // first partial tile of this task
   int32_t red_begin;         // first reduction workgroup of this task
+  int32_t ksplit;            // split-k piece length (0: GEMM_KSPLIT; resolved
+                             // by finalize_tasks)
+  int32_t pad_;
 };
 
 constexpr int GEMM_BM = 64;

@@ -1480,11 +1480,14 @@ static std::string gemm_signature(const dl_ws* W, const Launch& L) {
 
 // Tile size and split k of one matrix-product launch (split applies to the
 // FP64 kernel only).
-static dl_status retile(dl_ws* W, Launch& L, int tile, bool split, hipStream_t s) {
+static dl_status retile(dl_ws* W, Launch& L, int tile, bool split, hipStream_t s,
+                        int ksplit = GEMM_KSPLIT) {
   GemmTask* t = W->H.gemm.data() + L.off;
   if (L.kind == OP_GEMM)
-    for (int i = 0; i < L.count; ++i)
+    for (int i = 0; i < L.count; ++i) {
       t[i].flags = split ? (t[i].flags | F_SPLIT) : (t[i].flags & ~F_SPLIT);
+      t[i].ksplit = ksplit;
+    }
   int64_t slots = 0;
   L.tile = tile;
   L.gx = finalize_tasks(t, L.count, tile, &L.nred, &slots);
@@ -1501,12 +1504,26 @@ static bool launch_split(const dl_ws* W, const Launch& L) {
   return L.kind == OP_GEMM && L.count > 0 && (W->H.gemm[L.off].flags & F_SPLIT);
 }
 
+static int launch_ksplit(const dl_ws* W, const Launch& L) {
+  return (L.kind == OP_GEMM && L.count > 0 && W->H.gemm[L.off].ksplit > 0)
+             ? W->H.gemm[L.off].ksplit
+             : GEMM_KSPLIT;
+}
+
+// One tuned choice of a matrix-product launch.
+struct TileChoice {
+  int tile = 64;
+  bool split = false;
+  int ksplit = GEMM_KSPLIT;
+};
+
 extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream) {
   if (!W) return DL_EINVAL;
   if (W->graph_exec) return DL_ESTATE;  // tune before the first graph capture
   hipStream_t s = (hipStream_t)stream;
-  // cache lines: "<signature> <tile>" or "<signature> <tile>s" (split k)
-  std::unordered_map<std::string, std::pair<int, bool>> best;
+  // cache lines: "<signature> <tile>", "<signature> <tile>s" (split k in
+  // pieces of 512) or "<signature> <tile>s<piece>"
+  std::unordered_map<std::string, TileChoice> best;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -1514,7 +1531,15 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
       const size_t sp = line.rfind(' ');
       if (sp == std::string::npos || sp + 1 >= line.size()) continue;
       const std::string v = line.substr(sp + 1);
-      best[line.substr(0, sp)] = {atoi(v.c_str()), v.back() == 's'};
+      TileChoice c;
+      c.tile = atoi(v.c_str());
+      const size_t sx = v.find('s');
+      if (sx != std::string::npos) {
+        c.split = true;
+        if (sx + 1 < v.size()) c.ksplit = atoi(v.c_str() + sx + 1);
+      }
+      if ((c.tile != 64 && c.tile != 128) || c.ksplit < 16 || c.ksplit % 16) continue;
+      best[line.substr(0, sp)] = c;
     }
   }
   std::vector<std::string> fresh;
@@ -1527,43 +1552,54 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
     const std::string sig = gemm_signature(W, L);
     auto it = best.find(sig);
     if (it == best.end()) {
-      // split k is a candidate when some task has more than one k piece
-      bool can_split = false;
+      // candidates: both tiles, unsplit and (FP64 products with a k extent
+      // above a piece length) split into pieces of 512 or 256
+      int kmax = 0;
       if (L.kind == OP_GEMM)
-        for (int i = 0; i < L.count; ++i)
-          can_split = can_split || W->H.gemm[L.off + i].K > GEMM_KSPLIT;
+        for (int i = 0; i < L.count; ++i) kmax = std::max(kmax, W->H.gemm[L.off + i].K);
+      std::vector<TileChoice> cand;
+      for (int tile : {64, 128}) {
+        cand.push_back({tile, false, GEMM_KSPLIT});
+        for (int ks : {512, 256})
+          if (kmax > ks) cand.push_back({tile, true, ks});
+      }
       float tbest = 1e30f;
-      std::pair<int, bool> choice{64, false};
-      for (int sp = 0; sp < (can_split ? 2 : 1) && st == DL_OK; ++sp)
-        for (int tile : {64, 128}) {
-          if ((st = retile(W, L, tile, sp == 1, s)) != DL_OK) break;
-          float tmin = 1e30f;
-          for (int rep = 0; rep < 3; ++rep) {
-            (void)hipEventRecord(e0, s);
-            (void)run_launch(W, L, s);
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            tmin = std::min(tmin, ms);
-          }
-          if (tmin < tbest) {
-            tbest = tmin;
-            choice = {tile, sp == 1};
-          }
+      TileChoice choice;
+      for (const TileChoice& c : cand) {
+        if ((st = retile(W, L, c.tile, c.split, s, c.ksplit)) != DL_OK) break;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          (void)hipEventRecord(e0, s);
+          (void)run_launch(W, L, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          tmin = std::min(tmin, ms);
         }
+        if (tmin < tbest) {
+          tbest = tmin;
+          choice = c;
+        }
+      }
       it = best.emplace(sig, choice).first;
       fresh.push_back(sig);
     }
-    if (st == DL_OK && (L.tile != it->second.first || launch_split(W, L) != it->second.second))
-      st = retile(W, L, it->second.first, it->second.second, s);
+    const TileChoice& c = it->second;
+    if (st == DL_OK && (L.tile != c.tile || launch_split(W, L) != c.split ||
+                        (c.split && launch_ksplit(W, L) != c.ksplit)))
+      st = retile(W, L, c.tile, c.split, s, c.ksplit);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st == DL_OK && cache_path && !fresh.empty()) {
     std::ofstream out(cache_path, std::ios::app);
-    for (const auto& sig : fresh)
-      out << sig << " " << best[sig].first << (best[sig].second ? "s" : "") << "\n";
+    for (const auto& sig : fresh) {
+      const TileChoice& c = best[sig];
+      out << sig << " " << c.tile;
+      if (c.split) out << "s" << (c.ksplit == GEMM_KSPLIT ? std::string() : std::to_string(c.ksplit));
+      out << "\n";
+    }
   }
   return st;
 }
@@ -1573,7 +1609,19 @@ extern "C" dl_status dl_ws_force_tile(dl_ws* W, int32_t tile) {
   if (W->graph_exec) return DL_ESTATE;
   for (Launch& L : W->table) {
     if (L.kind != OP_GEMM && L.kind != OP_GEMM32) continue;
-    const dl_status st = retile(W, L, tile, launch_split(W, L), nullptr);
+    const dl_status st = retile(W, L, tile, launch_split(W, L), nullptr, launch_ksplit(W, L));
+    if (st != DL_OK) return st;
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_force_split(dl_ws* W, int32_t ksplit) {
+  if (!W || ksplit < 0 || (ksplit > 0 && (ksplit < 64 || ksplit % 16))) return DL_EINVAL;
+  if (W->graph_exec) return DL_ESTATE;
+  for (Launch& L : W->table) {
+    if (L.kind != OP_GEMM) continue;
+    const dl_status st =
+        retile(W, L, L.tile, ksplit > 0, nullptr, ksplit > 0 ? ksplit : GEMM_KSPLIT);
     if (st != DL_OK) return st;
   }
   return DL_OK;

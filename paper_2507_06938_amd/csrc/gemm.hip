@@ -342,12 +342,13 @@ __global__ __launch_bounds__(WM * WN * 64, MINW) void k_gemm_tasks(
   kb = (kb / BK) * BK;
   int slot = -1;  // partial tile of this piece (split tiles only)
   if (T.kslices > 1 && ke > kb) {
-    const int s0 = kb / GEMM_KSPLIT;
-    const int npieces = (ke - 1) / GEMM_KSPLIT - s0 + 1;
+    const int ks = T.ksplit;
+    const int s0 = kb / ks;
+    const int npieces = (ke - 1) / ks - s0 + 1;
     if (sl >= npieces) return;  // no piece here for this tile
     if (npieces > 1) slot = T.pslot_begin + lt * T.kslices + sl;
-    kb = max(kb, (s0 + sl) * GEMM_KSPLIT);
-    ke = min(ke, (s0 + sl + 1) * GEMM_KSPLIT);
+    kb = max(kb, (s0 + sl) * ks);
+    ke = min(ke, (s0 + sl + 1) * ks);
   } else if (sl > 0) {
     return;
   }
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmTask* __restrict_
   if (T.flags & F_KHI_ROW) ke = min(ke, m0 + BT);
   kb = (kb / BK) * BK;
   if (ke <= kb) return;
-  const int npieces = (ke - 1) / GEMM_KSPLIT - kb / GEMM_KSPLIT + 1;
+  const int npieces = (ke - 1) / T.ksplit - kb / T.ksplit + 1;
   if (npieces < 2) return;  // written directly by the product launch
   const bool lower = T.flags & F_LOWER;
   const bool beta0 = T.flags & F_BETA0;
@@ -517,8 +518,10 @@ int finalize_tasks(GemmTask* t, int n, int tile, int* nred, int64_t* nslots) {
     }
     t[i].tile_begin = total;
     total += t[i].ntiles;
-    const bool split = (t[i].flags & F_SPLIT) && t[i].K > GEMM_KSPLIT;
-    t[i].kslices = split ? (t[i].K + GEMM_KSPLIT - 1) / GEMM_KSPLIT : 1;
+    if (t[i].ksplit <= 0) t[i].ksplit = GEMM_KSPLIT;
+    const int ks = t[i].ksplit;
+    const bool split = (t[i].flags & F_SPLIT) && t[i].K > ks;
+    t[i].kslices = split ? (t[i].K + ks - 1) / ks : 1;
     t[i].unit_begin = units;
     units += t[i].ntiles * t[i].kslices;
     t[i].pslot_begin = (int32_t)slots;

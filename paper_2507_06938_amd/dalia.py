@@ -85,6 +85,7 @@ def lib():
             "dl_autotune": (i32, [vp, C.c_char_p, vp]),
             "dl_ws_tile_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
             "dl_ws_force_tile": (i32, [vp, i32]),
+            "dl_ws_force_split": (i32, [vp, i32]),
             "dl_mlp_create": (i32, [vp, i32, i32, C.POINTER(vp)]),
             "dl_mlp_destroy": (None, [vp]),
             "dl_mlp_params": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)]),
@@ -270,6 +271,11 @@ class Workspace:
     def force_tile(self, tile: int):
         """Use `tile` (64 or 128) for every matrix-product launch."""
         _check("dl_ws_force_tile", lib().dl_ws_force_tile(self.h, int(tile)))
+
+    def force_split(self, ksplit: int):
+        """Split the k range of every FP64 product launch into pieces of
+        `ksplit` (0: unsplit)."""
+        _check("dl_ws_force_split", lib().dl_ws_force_split(self.h, int(ksplit)))
 
     def tile_counts(self) -> dict:
         a, b = C.c_int64(), C.c_int64()

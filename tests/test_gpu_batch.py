@@ -148,9 +148,10 @@ def test_autotuned_tiles_give_identical_results(D, tmp_path):
 
 
 def test_autotune_with_split_candidates(D, tmp_path):
-    """Blocks of 576 (k > 512): the tuner may also choose split k, which sums
-    the k pieces separately, so results agree with the default workspace to
-    rounding; a second workspace reads every choice back from the cache."""
+    """Blocks of 576 (k > 512): the tuner may also choose split k (pieces of
+    512 or 256), which sums the k pieces separately, so results agree with
+    the default workspace to rounding; a second workspace reads every choice
+    back from the cache."""
     wl = W.scaled("tune_split", 24, 3, 1, 2, 400, seed=4)
     model = D.Model.from_workload(wl)
     ws = D.Workspace(model, selinv=True)
@@ -165,7 +166,8 @@ def test_autotune_with_split_candidates(D, tmp_path):
     np.testing.assert_allclose(p1.cpu().numpy(), p0.cpu().numpy(), rtol=1e-12, atol=1e-9)
     np.testing.assert_allclose(v1, v0, rtol=1e-10)
     lines = open(cache).read().splitlines()
-    assert lines and all(l.rsplit(" ", 1)[1] in ("64", "128", "64s", "128s") for l in lines)
+    assert lines and all(l.rsplit(" ", 1)[1] in ("64", "128", "64s", "128s", "64s256", "128s256")
+                         for l in lines)
     ws2 = D.Workspace(model, selinv=True)
     assert ws2.autotune(cache) == counts
     f2, _, _ = ws2.fobj(wl.theta)

@@ -74,3 +74,29 @@ def test_splitk_independent_of_tile_size(D):
         del ws
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_split_piece_length_256_against_unsplit(D):
+    """Pieces of 256 (what the tuner may choose for launches with short k):
+    agree with the unsplit workspace to rounding and with the oracle, and
+    are again independent of the tile size."""
+    wl = W.scaled("pieces_b784", 28, 3, 1, 2, 200, seed=6)
+    model = D.Model.from_workload(wl)
+    res = {}
+    for key, ks, tile in (("unsplit", 0, 64), ("s256_64", 256, 64), ("s256_128", 256, 128)):
+        ws = D.Workspace(model, selinv=True)
+        ws.force_tile(tile)
+        ws.force_split(ks)
+        f, parts, info = ws.fobj(wl.theta)
+        var = ws.selinv().cpu().numpy()
+        torch.cuda.synchronize()
+        assert info.cpu().tolist() == [[0, 0]]
+        res[key] = (parts.cpu().numpy()[0].copy(), var)
+        del ws
+    ref = OF.fobj_parts(wl, wl.theta, method="dense")
+    p, v = res["s256_64"]
+    assert abs(p[2] - ref["logdet_c"]) <= 1e-10 * abs(ref["logdet_c"])
+    assert abs(p[2] - res["unsplit"][0][2]) <= 1e-13 * abs(p[2])
+    np.testing.assert_allclose(v, res["unsplit"][1], rtol=1e-11)
+    assert np.array_equal(res["s256_64"][0], res["s256_128"][0])
+    assert np.array_equal(res["s256_64"][1], res["s256_128"][1])
