@@ -619,6 +619,146 @@ __device__ __forceinline__ void store_chunk32(float* __restrict__ S, bool trans,
     for (int i = 0; i < PER; ++i) S[k * LD + rb + i] = v[i];
   }
 }
+// Vector staging of the FP32 kernel: each slot is one 16-byte load of E
+// consecutive elements of the stored operand (E = 4 floats, or 2 doubles
+// rounded to FP32 when staged).  Untransposed X (X[r + k ldx]): slot j holds
+// rows rl .. rl+E-1 of chunk column kq + j KS; transposed X (X[k + r ldx]):
+// chunk columns kq .. kq+E-1 of row rl + j RS.  Invalid slots read the
+// operand's origin and stage zeros.
+template <int BR, typename TE>
+struct VStage32 {
+  static constexpr int E = 16 / (int)sizeof(TE);
+  static constexpr int PV = BR * BK / (E * 256);
+  static constexpr int NP = BR / E, KS = 256 / NP;
+  static constexpr int NQ = BK / E, RS = 256 / NQ;
+  static_assert(256 % NP == 0 && BK % KS == 0 && 256 % NQ == 0 && BR % RS == 0, "map");
+  typedef TE vec_t __attribute__((ext_vector_type(E)));
+  const TE* base;
+  const TE* p;
+  int64_t step, adv;
+  int rl, kq, kc, kend;
+  bool trans;
+  unsigned rowok;
+
+  __device__ __forceinline__ void init(const void* Xv, int64_t ldx, bool tr, int r0, int R,
+                                       int k0, int ke, int tid) {
+    const TE* X = (const TE*)Xv;
+    base = X;
+    trans = tr;
+    kc = k0;
+    kend = ke;
+    rowok = 0;
+    if (!tr) {
+      rl = E * (tid % NP);
+      kq = tid / NP;
+      p = X + (r0 + rl) + (int64_t)(k0 + kq) * ldx;
+      step = (int64_t)KS * ldx;
+      adv = (int64_t)BK * ldx;
+      if (r0 + rl < R) rowok = (1u << PV) - 1;
+    } else {
+      kq = E * (tid % NQ);
+      rl = tid / NQ;
+      p = X + (k0 + kq) + (int64_t)(r0 + rl) * ldx;
+      step = (int64_t)RS * ldx;
+      adv = BK;
+#pragma unroll
+      for (int j = 0; j < PV; ++j)
+        if (r0 + rl + j * RS < R) rowok |= 1u << j;
+    }
+  }
+
+  __device__ __forceinline__ void load(float (&v)[PV][E]) const {
+#pragma unroll
+    for (int j = 0; j < PV; ++j) {
+      const int k = kc + kq + (trans ? 0 : j * KS);
+      const bool ok = ((rowok >> j) & 1u) && k < kend;
+      const TE* a = ok ? p + j * step : base;
+      const vec_t x = *(const __attribute__((address_space(1))) vec_t*)a;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[j][e] = ok ? (float)x[e] : 0.f;
+    }
+  }
+
+  __device__ __forceinline__ void next() {
+    p += adv;
+    kc += BK;
+  }
+
+  __device__ __forceinline__ void store(float* __restrict__ S, const float (&v)[PV][E]) const {
+    constexpr int LD = BR + 4;
+    if (!trans) {
+#pragma unroll
+      for (int j = 0; j < PV; ++j)
+#pragma unroll
+        for (int e = 0; e < E; ++e) S[(kq + j * KS) * LD + rl + e] = v[j][e];
+    } else {
+#pragma unroll
+      for (int j = 0; j < PV; ++j)
+#pragma unroll
+        for (int e = 0; e < E; ++e) S[(kq + e) * LD + rl + j * RS] = v[j][e];
+    }
+  }
+};
+
+// Whether an operand of the FP32 kernel can be staged with VStage32.
+__device__ __forceinline__ bool vec_operand32(const void* X, int esize, int64_t ldx,
+                                              bool strans, int R, int kb, int ke) {
+  const int E = 16 / esize;
+  if ((reinterpret_cast<uintptr_t>(X) & 15) != 0 || (ldx % E) != 0) return false;
+  return strans ? (kb % E == 0 && ke % E == 0) : (R % E == 0);
+}
+
+// acc += one staged chunk (wave (wm, wn) owns F x F blocks of 16 x 16); all
+// fragments of the chunk are read from LDS ahead of the MFMAs.
+template <int BT>
+__device__ __forceinline__ void mma_chunk32(const float* __restrict__ as,
+                                            const float* __restrict__ bs,
+                                            v4f_ (&acc)[BT / 32][BT / 32], int wm, int wn,
+                                            int lrow, int lk) {
+  constexpr int LD = BT + 4;
+  constexpr int F = BT / 32;
+  float fa[BK / 4][F], fb[BK / 4][F];
+#pragma unroll
+  for (int ks = 0; ks < BK / 4; ++ks) {
+    const int kk = ks * 4 + lk;
+#pragma unroll
+    for (int i = 0; i < F; ++i) fa[ks][i] = as[kk * LD + wm * (BT / 2) + i * 16 + lrow];
+#pragma unroll
+    for (int j = 0; j < F; ++j) fb[ks][j] = bs[kk * LD + wn * (BT / 2) + j * 16 + lrow];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+    for (int i = 0; i < F; ++i)
+#pragma unroll
+      for (int j = 0; j < F; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[ks][j], fa[ks][i], acc[i][j], 0, 0, 0);
+}
+
+template <int BT, typename TA, typename TB>
+__device__ __forceinline__ void gemm32_vec_loop(const GemmTask& T, bool ta, bool tb, int m0,
+                                                int n0, int kb, int ke, int nchunks, int tid,
+                                                float* As0, float* As1, float* Bs0, float* Bs1,
+                                                v4f_ (&acc)[BT / 32][BT / 32], int wm, int wn,
+                                                int lrow, int lk) {
+  VStage32<BT, TA> sa;
+  VStage32<BT, TB> sb;
+  sa.init(T.A, T.lda, ta, m0, T.M, kb, ke, tid);
+  sb.init(T.B, T.ldb, !tb, n0, T.N, kb, ke, tid);
+  float va[VStage32<BT, TA>::PV][VStage32<BT, TA>::E];
+  float vb[VStage32<BT, TB>::PV][VStage32<BT, TB>::E];
+  sa.load(va); sb.load(vb); sa.next(); sb.next();
+  sa.store(As0, va); sb.store(Bs0, vb);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    sa.load(va); sb.load(vb); sa.next(); sb.next();  // chunk c + 1
+    mma_chunk32<BT>((c & 1) ? As1 : As0, (c & 1) ? Bs1 : Bs0, acc, wm, wn, lrow, lk);
+    sa.store((c & 1) ? As0 : As1, va);
+    sb.store((c & 1) ? Bs0 : Bs1, vb);
+    __syncthreads();
+  }
+}
 }  // namespace
 
 template <int BT>
@@ -627,8 +767,8 @@ __global__ __launch_bounds__(256) void k_gemm32_tasks(
   constexpr int LD = BT + 4;
   constexpr int F = BT / 32;
   constexpr int PER = BT * BK / 256;
-  __shared__ float As[2][BK * LD];
-  __shared__ float Bs[2][BK * LD];
+  __shared__ __attribute__((aligned(16))) float As[2][BK * LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK * LD];
 
   const int tid = threadIdx.x;
   const int tile = (tasks[0].flags & F_KVAR) ? (int)blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
@@ -662,43 +802,60 @@ __global__ __launch_bounds__(256) void k_gemm32_tasks(
 #pragma unroll
     for (int j = 0; j < F; ++j) acc[i][j] = (v4f_){0.f, 0.f, 0.f, 0.f};
 
-  float va[PER], vb[PER];
-  if (nchunks > 0) {
-    load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, kb, ke, tid, va);
-    load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
-    store_chunk32<BT>(As[0], ta, tid, va);
-    store_chunk32<BT>(Bs[0], !tb, tid, vb);
-  }
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
-    const bool more = (c + 1) < nchunks;
-    if (more) {
-      const int k1 = kb + (c + 1) * BK;
-      load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, k1, ke, tid, va);
-      load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
-    }
-    const float* __restrict__ as = As[buf];
-    const float* __restrict__ bs = Bs[buf];
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kk = ks * 4 + lk;
-      float fa[F], fb[F];
-#pragma unroll
-      for (int i = 0; i < F; ++i) fa[i] = as[kk * LD + wm * (BT / 2) + i * 16 + lrow];
-#pragma unroll
-      for (int j = 0; j < F; ++j) fb[j] = bs[kk * LD + wn * (BT / 2) + j * 16 + lrow];
-#pragma unroll
-      for (int i = 0; i < F; ++i)
-#pragma unroll
-        for (int j = 0; j < F; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[j], fa[i], acc[i][j], 0, 0, 0);
-    }
-    if (more) {
-      store_chunk32<BT>(As[buf ^ 1], ta, tid, va);
-      store_chunk32<BT>(Bs[buf ^ 1], !tb, tid, vb);
+  const bool vec_a = vec_operand32(T.A, a64 ? 8 : 4, T.lda, ta, T.M, kb, ke);
+  const bool vec_b = vec_operand32(T.B, b64 ? 8 : 4, T.ldb, !tb, T.N, kb, ke);
+  if (vec_a && vec_b) {
+    if (a64 && b64)
+      gemm32_vec_loop<BT, double, double>(T, ta, tb, m0, n0, kb, ke, nchunks, tid, As[0], As[1],
+                                          Bs[0], Bs[1], acc, wm, wn, lrow, lk);
+    else if (a64)
+      gemm32_vec_loop<BT, double, float>(T, ta, tb, m0, n0, kb, ke, nchunks, tid, As[0], As[1],
+                                         Bs[0], Bs[1], acc, wm, wn, lrow, lk);
+    else if (b64)
+      gemm32_vec_loop<BT, float, double>(T, ta, tb, m0, n0, kb, ke, nchunks, tid, As[0], As[1],
+                                         Bs[0], Bs[1], acc, wm, wn, lrow, lk);
+    else
+      gemm32_vec_loop<BT, float, float>(T, ta, tb, m0, n0, kb, ke, nchunks, tid, As[0], As[1],
+                                        Bs[0], Bs[1], acc, wm, wn, lrow, lk);
+  } else {
+    float va[PER], vb[PER];
+    if (nchunks > 0) {
+      load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, kb, ke, tid, va);
+      load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, kb, ke, tid, vb);
+      store_chunk32<BT>(As[0], ta, tid, va);
+      store_chunk32<BT>(Bs[0], !tb, tid, vb);
     }
     __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const int buf = c & 1;
+      const bool more = (c + 1) < nchunks;
+      if (more) {
+        const int k1 = kb + (c + 1) * BK;
+        load_chunk32<BT>(T.A, a64, T.lda, ta, m0, T.M, k1, ke, tid, va);
+        load_chunk32<BT>(T.B, b64, T.ldb, !tb, n0, T.N, k1, ke, tid, vb);
+      }
+      const float* __restrict__ as = As[buf];
+      const float* __restrict__ bs = Bs[buf];
+  #pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kk = ks * 4 + lk;
+        float fa[F], fb[F];
+  #pragma unroll
+        for (int i = 0; i < F; ++i) fa[i] = as[kk * LD + wm * (BT / 2) + i * 16 + lrow];
+  #pragma unroll
+        for (int j = 0; j < F; ++j) fb[j] = bs[kk * LD + wn * (BT / 2) + j * 16 + lrow];
+  #pragma unroll
+        for (int i = 0; i < F; ++i)
+  #pragma unroll
+          for (int j = 0; j < F; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[j], fa[i], acc[i][j], 0, 0, 0);
+      }
+      if (more) {
+        store_chunk32<BT>(As[buf ^ 1], ta, tid, va);
+        store_chunk32<BT>(Bs[buf ^ 1], !tb, tid, vb);
+      }
+      __syncthreads();
+    }
   }
   const bool lower = T.flags & F_LOWER;
   const bool beta0 = T.flags & F_BETA0;
