@@ -204,8 +204,9 @@ def main():
     var = torch.empty(model.N, dtype=torch.float64, device=dev)
 
     def step():
-        ws.fobj(theta, out=(f, parts, info))
-        ws.selinv(out=var)
+        # f_obj and all marginal variances; the solve overlaps the selected
+        # inversion on a second stream
+        ws.fobj_selinv(theta, out=(f, parts, info, var))
 
     for _ in range(args.warmup):
         step()

@@ -188,6 +188,19 @@ dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                     double* fobj_dev, dl_fobj_parts* parts_dev,
                     int64_t* info_dev, void* stream);
 
+/* fobj_selinv_eval -- steps a1..a8 and a7 together: f_obj as fobj_eval for
+ * one pass of ntheta (1..B; B when the instances' models differ) thetas,
+ * and diag(Q_c^{-1}) of every instance as bta_selinv (diag_out_dev: the
+ * instances' N values in order).  The solve and quadratic forms run on a
+ * second, library-owned stream concurrently with the selected inversion
+ * (both only read the factor); every result is written to the caller's
+ * stream order.  Requires flags bit 0 (DL_WS_SELINV), else DL_ESTATE;
+ * DL_EINVAL for NULL pointers or an invalid ntheta.  Runs eagerly (also
+ * for DL_WS_GRAPH workspaces). */
+dl_status fobj_selinv_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
+                           double* fobj_dev, dl_fobj_parts* parts_dev, int64_t* info_dev,
+                           double* diag_out_dev, void* stream);
+
 /* Copy the conditional mean of the last solve (N doubles, BTA order). */
 dl_status dl_ws_mean(dl_ws* ws, double* out_dev, void* stream);
 

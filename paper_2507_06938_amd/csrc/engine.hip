@@ -406,6 +406,9 @@ struct dl_ws {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  // second stream and fork/join events of fobj_selinv_eval
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool use_graph = false;
   // launch profiling (measurement only)
   int prof_mask = 0, prof_by_kernel = 0, prof_used = 0;
@@ -1062,6 +1065,9 @@ static void ws_free(dl_ws* W) {
   if (W->graph_exec) (void)hipGraphExecDestroy(W->graph_exec);
   if (W->graph) (void)hipGraphDestroy(W->graph);
   if (W->cap_stream) (void)hipStreamDestroy(W->cap_stream);
+  if (W->aux_stream) (void)hipStreamDestroy(W->aux_stream);
+  if (W->ev_fork) (void)hipEventDestroy(W->ev_fork);
+  if (W->ev_join) (void)hipEventDestroy(W->ev_join);
   if (W->partials) (void)hipFree(W->partials);
   free_all(W->allocs);
   delete W;
@@ -1337,6 +1343,59 @@ extern "C" dl_status fobj_eval(dl_ws* W, const double* theta_dev, int32_t ntheta
       DL_HIP_CHECK(hipMemcpyAsync(info_dev + 2 * (int64_t)k0, W->info_all,
                                   sizeof(int64_t) * 2 * nk, hipMemcpyDeviceToDevice, s));
   }
+  W->assembled[0] = W->assembled[1] = false;
+  W->factored[0] = W->factored[1] = true;
+  W->solved = true;
+  return DL_OK;
+}
+
+// f_obj and the selected inversion of one batch of thetas: after the two
+// factorisations the solve, refinement and quadratic forms run on a second
+// stream while the selected inversion runs on the caller's stream (they read
+// the factor and write disjoint buffers); the caller's stream then waits for
+// both.  Results are those of fobj_eval followed by bta_selinv.
+extern "C" dl_status fobj_selinv_eval(dl_ws* W, const double* theta_dev, int32_t ntheta,
+                                      double* fobj_dev, dl_fobj_parts* parts_dev,
+                                      int64_t* info_dev, double* diag_out_dev,
+                                      void* stream) {
+  if (!W || !theta_dev || !diag_out_dev || (!fobj_dev && !parts_dev)) return DL_EINVAL;
+  if (!W->sel) return DL_ESTATE;
+  const int B = (int)W->inst.size();
+  bool uniform = true;
+  for (auto& I : W->inst)
+    if (I.model != W->inst[0].model) uniform = false;
+  if (ntheta < 1 || ntheta > B || (!uniform && ntheta != B)) return DL_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (!W->aux_stream)
+    DL_HIP_CHECK(hipStreamCreateWithFlags(&W->aux_stream, hipStreamNonBlocking));
+  if (!W->ev_fork) DL_HIP_CHECK(hipEventCreateWithFlags(&W->ev_fork, hipEventDisableTiming));
+  if (!W->ev_join) DL_HIP_CHECK(hipEventCreateWithFlags(&W->ev_join, hipEventDisableTiming));
+  dl_status st = copy_theta_in(W, theta_dev, ntheta, s);
+  if (st != DL_OK) return st;
+  DL_HIP_CHECK(run(W, W->asm_p[2], s));
+  DL_HIP_CHECK(run(W, W->fac_p[2], s));
+  DL_HIP_CHECK(hipEventRecord(W->ev_fork, s));
+  DL_HIP_CHECK(hipStreamWaitEvent(W->aux_stream, W->ev_fork, 0));
+  DL_HIP_CHECK(run(W, W->solve_p, W->aux_stream));
+  DL_HIP_CHECK(run(W, W->refine_p, W->aux_stream));
+  DL_HIP_CHECK(run(W, W->post_p, W->aux_stream));
+  DL_HIP_CHECK(hipEventRecord(W->ev_join, W->aux_stream));
+  DL_HIP_CHECK(run(W, W->selinv_p, s));
+  int64_t off = 0;
+  for (auto& I : W->inst) {
+    DL_HIP_CHECK(launch_pack(I.m, I.selout, diag_out_dev + off, s));
+    off += I.m.N;
+  }
+  DL_HIP_CHECK(hipStreamWaitEvent(s, W->ev_join, 0));
+  if (fobj_dev)
+    DL_HIP_CHECK(hipMemcpyAsync(fobj_dev, W->f_all, sizeof(double) * ntheta,
+                                hipMemcpyDeviceToDevice, s));
+  if (parts_dev)
+    DL_HIP_CHECK(hipMemcpyAsync(parts_dev, W->parts_all, sizeof(dl_fobj_parts) * ntheta,
+                                hipMemcpyDeviceToDevice, s));
+  if (info_dev)
+    DL_HIP_CHECK(hipMemcpyAsync(info_dev, W->info_all, sizeof(int64_t) * 2 * ntheta,
+                                hipMemcpyDeviceToDevice, s));
   W->assembled[0] = W->assembled[1] = false;
   W->factored[0] = W->factored[1] = true;
   W->solved = true;

@@ -85,6 +85,7 @@ def lib():
             "dl_autotune": (i32, [vp, C.c_char_p, vp]),
             "dl_ws_tile_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
             "dl_ws_force_tile": (i32, [vp, i32]),
+            "fobj_selinv_eval": (i32, [vp, vp, i32, vp, vp, vp, vp, vp]),
             "dl_ws_force_split": (i32, [vp, i32]),
             "dl_mlp_create": (i32, [vp, i32, i32, C.POINTER(vp)]),
             "dl_mlp_destroy": (None, [vp]),
@@ -259,6 +260,32 @@ class Workspace:
         _check("fobj_eval", lib().fobj_eval(self.h, _ptr(th), n, _ptr(f),
                                             _ptr(parts), _ptr(info), _stream()))
         return f, parts, info
+
+    def fobj_selinv(self, thetas, out=None):
+        """f_obj of one pass of thetas and the marginal variances of every
+        instance, the solve overlapping the selected inversion; `out` =
+        (f, parts, info, var) device tensors."""
+        th = thetas if isinstance(thetas, torch.Tensor) and thetas.is_cuda \
+            else torch.as_tensor(thetas, dtype=torch.float64)
+        uniform = all(m is self.models[0] for m in self.models)
+        if not uniform:
+            th = th.reshape(-1).to(self.dev).contiguous()
+            n = self.B
+        else:
+            if th.dim() == 1:
+                th = th[None]
+            th = th.to(self.dev).contiguous()
+            n = th.shape[0]
+        if out is None:
+            f = torch.empty(n, dtype=torch.float64, device=self.dev)
+            parts = torch.empty((n, 8), dtype=torch.float64, device=self.dev)
+            info = torch.empty((n, 2), dtype=torch.int64, device=self.dev)
+            var = torch.empty(self.N_total, dtype=torch.float64, device=self.dev)
+        else:
+            f, parts, info, var = out
+        _check("fobj_selinv_eval", lib().fobj_selinv_eval(
+            self.h, _ptr(th), n, _ptr(f), _ptr(parts), _ptr(info), _ptr(var), _stream()))
+        return f, parts, info, var
 
     def autotune(self, cache_path: Optional[str] = None):
         """Measure and fix the GEMM tile of every launch (see dl_autotune)."""
