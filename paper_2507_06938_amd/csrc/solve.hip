@@ -6,8 +6,26 @@
 namespace dl {
 
 // Workgroup (i, s, j): rows 64i..64i+63 of job j, k-split s; lane = row, the
-// 4 waves interleave columns and are combined in a fixed order.  `tri`: A is
-// lower triangular, columns k > row are skipped.
+// 4 waves interleave columns (wave w takes columns k0 + w + 4m), each wave
+// keeps four independent partial sums (columns 16 apart) so four loads are in
+// flight, and the sums are combined in a fixed order.  `tri`: A is lower
+// triangular, columns k > row are skipped.
+template <typename TA>
+__device__ __forceinline__ double gemv_n_rows(const TA* __restrict__ A, int64_t lda,
+                                              const double* __restrict__ x, int row, int k,
+                                              int k1) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const TA* p = A + row;
+  for (; k + 12 < k1; k += 16) {
+    a0 += (double)p[(int64_t)k * lda] * x[k];
+    a1 += (double)p[(int64_t)(k + 4) * lda] * x[k + 4];
+    a2 += (double)p[(int64_t)(k + 8) * lda] * x[k + 8];
+    a3 += (double)p[(int64_t)(k + 12) * lda] * x[k + 12];
+  }
+  for (; k < k1; k += 4) a0 += (double)p[(int64_t)k * lda] * x[k];
+  return (a0 + a1) + (a2 + a3);
+}
+
 __global__ __launch_bounds__(256) void k_gemv_n_partial(
     const GemvN* __restrict__ jobs) {
   __shared__ double sh[4][64];
@@ -20,16 +38,9 @@ __global__ __launch_bounds__(256) void k_gemv_n_partial(
   int k1 = min(g.K, k0 + ks_len);
   if (g.tri) k1 = min(k1, (int)blockIdx.x * 64 + 64);
   double acc = 0.0;
-  if (row < g.M) {
-    if (g.a32) {
-      const float* A32 = (const float*)g.A;
-      for (int k = k0 + wave; k < k1; k += 4)
-        acc += (double)A32[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
-    } else {
-      for (int k = k0 + wave; k < k1; k += 4)
-        acc += g.A[(int64_t)row + (int64_t)k * g.lda] * g.x[k];
-    }
-  }
+  if (row < g.M)
+    acc = g.a32 ? gemv_n_rows((const float*)g.A, g.lda, g.x, row, k0 + wave, k1)
+                : gemv_n_rows(g.A, g.lda, g.x, row, k0 + wave, k1);
   sh[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && row < g.M)
@@ -62,23 +73,34 @@ hipError_t launch_gemv_n(const GemvN* jobs, int count, int max_M, hipStream_t s)
   return hipGetLastError();
 }
 
-// One wave per column j of job blockIdx.y, lanes stride the rows, then a
-// fixed butterfly.  `tri`: A lower triangular (rows i < j skipped).  y must
-// not alias x.
+// One wave per column j of job blockIdx.y, lanes stride the rows with four
+// independent partial sums (rows 64 apart, four loads in flight), combined in
+// a fixed order and then by a fixed butterfly.  `tri`: A lower triangular
+// (rows i < j skipped).  y must not alias x.
+template <typename TA>
+__device__ __forceinline__ double gemv_t_col(const TA* __restrict__ col, const GemvT& g,
+                                             int i, int split) {
+  auto xv = [&](int r) { return (r < split) ? g.x1[r] : g.x2[r - split]; };
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (; i + 192 < g.M; i += 256) {
+    a0 += (double)col[i] * xv(i);
+    a1 += (double)col[i + 64] * xv(i + 64);
+    a2 += (double)col[i + 128] * xv(i + 128);
+    a3 += (double)col[i + 192] * xv(i + 192);
+  }
+  for (; i < g.M; i += 64) a0 += (double)col[i] * xv(i);
+  return (a0 + a1) + (a2 + a3);
+}
+
 __global__ __launch_bounds__(256) void k_gemv_t(const GemvT* __restrict__ jobs) {
   const GemvT g = jobs[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = blockIdx.x * 4 + wave;
   if (j >= g.N) return;
-  const double* col = g.A + (int64_t)j * g.lda;
-  const float* col32 = (const float*)g.A + (int64_t)j * g.lda;
   const int split = g.split < 0 ? g.M : g.split;
   const int i0 = g.tri ? (j & ~63) : 0;
-  double acc = 0.0;
-  for (int i = i0 + lane; i < g.M; i += 64) {
-    const double xv = (i < split) ? g.x1[i] : g.x2[i - split];
-    acc += (g.a32 ? (double)col32[i] : col[i]) * xv;
-  }
+  double acc = g.a32 ? gemv_t_col((const float*)g.A + (int64_t)j * g.lda, g, i0 + lane, split)
+                     : gemv_t_col(g.A + (int64_t)j * g.lda, g, i0 + lane, split);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) g.y[j] = (g.base ? g.beta * g.base[j] : 0.0) + g.alpha * acc;
 }

@@ -3,7 +3,7 @@
 
 namespace dl {
 
-constexpr int GEMV_KS = 8;  // k-splits of a column-major matrix-vector product
+constexpr int GEMV_KS = 16;  // k-splits of a column-major matrix-vector product
 
 // out = beta*base + alpha*A*x, rows [0, split) -> out1/base1 and rows
 // [split, M) -> out2/base2 (split < 0: all rows to out1).  `partial` holds
