@@ -233,7 +233,8 @@ dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
  * by timing the candidates on the device once per distinct launch shape;
  * choices are appended to / read from the text file cache_path (may be
  * NULL; one line per shape ending in the tile, suffixed "s" when split).
- * May grow the workspace's device memory by the split partial tiles.
+ * May grow the workspace's device memory by the split partial tiles (split
+ * choices needing more than 4 GiB of them are not tried).
  * Synchronises the stream; the
  * workspace's matrices must be re-assembled afterwards (fobj_eval always
  * does).  Call before the first evaluation of a DL_WS_GRAPH workspace. */

@@ -1569,6 +1569,10 @@ static int launch_ksplit(const dl_ws* W, const Launch& L) {
              : GEMM_KSPLIT;
 }
 
+// Device memory the autotuner may add for split-k partial tiles (doubles):
+// choices needing more are not tried.
+constexpr int64_t kSplitBudgetDoubles = (int64_t)4 << 27;  // 4 GiB
+
 // One tuned choice of a matrix-product launch.
 struct TileChoice {
   int tile = 64;
@@ -1619,8 +1623,20 @@ extern "C" dl_status dl_autotune(dl_ws* W, const char* cache_path, void* stream)
       std::vector<TileChoice> cand;
       for (int tile : {64, 128}) {
         cand.push_back({tile, false, GEMM_KSPLIT});
-        for (int ks : {512, 256})
-          if (kmax > ks) cand.push_back({tile, true, ks});
+        for (int ks : {512, 256}) {
+          if (kmax <= ks) continue;
+          // partial tiles of this choice: skipped above the budget
+          std::vector<GemmTask> tmp(W->H.gemm.begin() + L.off,
+                                    W->H.gemm.begin() + L.off + L.count);
+          for (auto& t : tmp) {
+            t.flags |= F_SPLIT;
+            t.ksplit = ks;
+          }
+          int64_t slots = 0;
+          (void)finalize_tasks(tmp.data(), L.count, tile, nullptr, &slots);
+          if (slots * tile * tile <= kSplitBudgetDoubles || slots * tile * tile <= W->partials_cap)
+            cand.push_back({tile, true, ks});
+        }
       }
       float tbest = 1e30f;
       TileChoice choice;
