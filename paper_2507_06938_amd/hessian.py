@@ -1,0 +1,128 @@
+"""Hessian of f at the mode and the Gaussian approximation of the
+hyperparameter marginals (Sec. II-C), on the batched GPU evaluator.
+
+The second-order central differences with step h on the internal theta --
+    H_ii = (f(x + h e_i) - 2 f(x) + f(x - h e_i)) / h^2,
+    H_ij = (f(x + h e_i + h e_j) - f(x + h e_i - h e_j)
+            - f(x - h e_i + h e_j) + f(x - h e_i - h e_j)) / (4 h^2)
+-- need 2 d^2 + 1 independent f_obj values; they are evaluated as batched
+passes of the library (a workspace of `batch` instances, the last pass
+padded).  The Gaussian approximation of the marginals has covariance
+(-H)^{-1} at the mode.
+
+Host-side logic only; every f_obj value comes from the library's kernels.
+
+    python -m paper_2507_06938_amd.hessian [c1|c2] [--batch B]
+
+prints one JSON document: the Hessian at the workload's generator theta,
+its eigenvalues, the evaluations and their rate.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def stencil_points(theta: np.ndarray, h: float) -> np.ndarray:
+    """x, then x +- h e_i, then for each i < j the corners in the order
+    (+,+), (+,-), (-,+), (-,-)."""
+    x = np.asarray(theta, np.float64)
+    d = x.size
+    rows = [x]
+    for i in range(d):
+        e = np.zeros(d)
+        e[i] = h
+        rows += [x + e, x - e]
+    for i in range(d):
+        ei = np.zeros(d)
+        ei[i] = h
+        for j in range(i + 1, d):
+            ej = np.zeros(d)
+            ej[j] = h
+            rows += [x + ei + ej, x + ei - ej, x - ei + ej, x - ei - ej]
+    return np.array(rows)
+
+
+def second_differences(f: np.ndarray, d: int, h: float) -> np.ndarray:
+    """H from the values at stencil_points (same order)."""
+    H = np.zeros((d, d))
+    c = f[0]
+    for i in range(d):
+        H[i, i] = (f[1 + 2 * i] - 2.0 * c + f[2 + 2 * i]) / h ** 2
+    pos = 1 + 2 * d
+    for i in range(d):
+        for j in range(i + 1, d):
+            q = f[pos:pos + 4]
+            H[i, j] = ((q[0] - q[1]) - (q[2] - q[3])) / (4.0 * h ** 2)
+            H[j, i] = H[i, j]
+            pos += 4
+    return H
+
+
+def fobj_hessian(ws, theta: np.ndarray, h: float = 1e-3):
+    """(H, f(theta), values) of f_obj at theta from batched passes of the
+    workspace `ws` (all instances of one model); values: f_obj at the
+    stencil points."""
+    import torch
+    pts = stencil_points(theta, h)
+    B = ws.B
+    vals = np.empty(pts.shape[0])
+    for k0 in range(0, pts.shape[0], B):
+        chunk = pts[k0:k0 + B]
+        n = chunk.shape[0]
+        if n < B:  # pad the last pass with copies of its first point
+            chunk = np.concatenate([chunk, np.repeat(chunk[:1], B - n, axis=0)])
+        f, _, info = ws.fobj(chunk)
+        vals[k0:k0 + n] = f.cpu().numpy()[:n]
+    torch.cuda.synchronize()
+    return second_differences(vals, pts.shape[1], h), vals[0], vals
+
+
+def marginal_sd(H: np.ndarray) -> np.ndarray:
+    """Marginal standard deviations of the Gaussian with covariance (-H)^{-1}."""
+    return np.sqrt(np.diag(np.linalg.inv(-H)))
+
+
+def main(argv=None):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import argparse
+    import torch
+    import workloads as W
+    from . import dalia as D
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("config", nargs="?", default="c1", choices=("c1", "c2"))
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instances per pass (0: 2 dim + 1 for c1, 31 for c2)")
+    ap.add_argument("--tiles", default=os.path.join(root, "paper_2507_06938_amd",
+                                                    "tiles_gfx950.txt"))
+    args = ap.parse_args(argv)
+    wl = W.config1() if args.config == "c1" else W.config2()
+    d = wl.dim_theta
+    B = args.batch or (2 * d + 1 if args.config == "c1" else 31)
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace([model] * B, graph=True)
+    ws.autotune(args.tiles)
+    fobj_hessian(ws, wl.theta)  # warm-up (graph capture)
+    t0 = time.perf_counter()
+    H, f0, vals = fobj_hessian(ws, wl.theta)
+    t = time.perf_counter() - t0
+    ev = np.linalg.eigvalsh(H)
+    out = {"workload": wl.name, "dim_theta": d, "points": int(vals.size), "batch": B,
+           "passes": int(-(-vals.size // B)), "s_per_hessian": t,
+           "evals_per_s": vals.size / t, "f": float(f0),
+           "hessian": H.tolist(), "eigenvalues": ev.tolist(),
+           "negative_definite": bool(ev.max() < 0)}
+    if out["negative_definite"]:
+        out["gaussian_marginal_sd"] = marginal_sd(H).tolist()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

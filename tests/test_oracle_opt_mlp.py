@@ -10,6 +10,7 @@ import scipy.sparse as sp
 import workloads as W
 from oracle import bfgs as OB
 from oracle import fobj as OF
+from oracle import hessian as OH
 from oracle import mlp as OL
 from oracle import model as OM
 
@@ -91,6 +92,64 @@ def test_fd_gradient_of_fobj_matches_analytic():
     g_fd = OB.central_gradient(lambda t: OF.fobj(wl, t), theta, 1e-3)
     g_an = _analytic_grad_univariate(wl, theta)
     np.testing.assert_allclose(g_fd, g_an, rtol=1e-4, atol=1e-4)
+
+
+# ---- Hessian at the mode (second-order central differences) ---------------------
+
+def test_hessian_stencil_exact_on_quadratics():
+    """Second differences are exact for quadratics: H = A; 2 d^2 + 1 points."""
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((5, 5))
+    A = B + B.T
+    b = rng.standard_normal(5)
+    f = lambda x: 0.5 * x @ A @ x + b @ x + 3.0
+    x0 = rng.standard_normal(5)
+    H = OH.hessian(f, x0, 1e-3)
+    np.testing.assert_allclose(H, A, atol=1e-7)
+    assert OH.hessian_stencil(x0, 1e-3).shape == (2 * 25 + 1, 5)
+
+
+def test_hessian_stencil_closed_form_separable():
+    """f = sum_i exp(c_i x_i) + x_0 x_1^3: the diagonal second difference of
+    exp(c x) is exp(c x) (2 cosh(c h) - 2) / h^2 exactly, the mixed one of
+    x_0 x_1^3 is 3 x_1^2 + h^2 exactly."""
+    c = np.array([0.5, -1.0, 2.0])
+    x = np.array([0.3, -0.4, 0.1])
+    h = 1e-2
+    f = lambda v: float(np.sum(np.exp(c * v)) + v[0] * v[1] ** 3)
+    H = OH.hessian(f, x, h)
+    diag = np.exp(c * x) * (2.0 * np.cosh(c * h) - 2.0) / h ** 2
+    diag[1] += 6.0 * x[0] * x[1]
+    np.testing.assert_allclose(np.diag(H), diag, rtol=1e-8)
+    np.testing.assert_allclose(H[0, 1], 3 * x[1] ** 2 + h ** 2, rtol=1e-8)
+    assert abs(H[0, 2]) < 1e-8 and abs(H[1, 2]) < 1e-8
+
+
+def test_gaussian_marginal_sd_of_a_gaussian():
+    """For a Gaussian log density the approximation is exact."""
+    S = np.array([[2.0, 0.3], [0.3, 0.5]])
+    P = np.linalg.inv(S)
+    logp = lambda x: -0.5 * x @ P @ x
+    H = OH.hessian(logp, np.zeros(2), 1e-3)
+    np.testing.assert_allclose(OH.gaussian_marginal_sd(H), np.sqrt(np.diag(S)), rtol=1e-6)
+
+
+def test_fd_hessian_of_fobj_matches_difference_of_analytic_gradient():
+    """The second differences of the oracle's f_obj against central
+    differences of the analytic gradient of the dense marginal likelihood (a
+    different route to the same matrix; both O(h^2))."""
+    wl = W.scaled("hess", 4, 3, 1, 2, 30, seed=3)
+    theta = wl.theta + np.array([0.1, -0.2, 0.15, -0.05])
+    h = 1e-3
+    H_fd = OH.hessian(lambda t: OF.fobj(wl, t), theta, h)
+    J = np.empty((4, 4))
+    for j in range(4):
+        e = np.zeros(4)
+        e[j] = h
+        J[:, j] = (_analytic_grad_univariate(wl, theta + e)
+                   - _analytic_grad_univariate(wl, theta - e)) / (2 * h)
+    scale = np.max(np.abs(J))
+    np.testing.assert_allclose(H_fd, 0.5 * (J + J.T), atol=1e-6 * scale)
 
 
 # ---- surrogate network -----------------------------------------------------------
