@@ -15,7 +15,14 @@ coregional) latent Gaussian model, as general scipy sparse matrices in
 Readings of points the paper leaves open (grid spacing h = 1; Neumann
 5-point stiffness; lumped mass; AR1 with unit marginal variance; Kronecker
 order time-outer; fixed effects not mixed by Lambda; Gaussian prior on
-theta) are stated on each function.
+theta; the form of the non-separable diffusion-based model) are stated on
+each function.
+
+Two model families: ``wl.model == "separable"`` (AR1 in time times the
+Matern SPDE precision in space) and ``"diffusion"``, the non-separable
+space-time model written as a sum of Kronecker products of temporal and
+spatial FEM matrices (Section III-B, multivariate models, which builds every
+univariate precision that way).
 """
 from __future__ import annotations
 
@@ -35,7 +42,7 @@ def theta_dim(nv: int) -> int:
     return 4 if nv == 1 else 4 * nv + n_lambda(nv)
 
 
-def theta_to_params(theta, nv: int) -> dict:
+def theta_to_params(theta, nv: int, model: str = "separable") -> dict:
     """Internal theta -> model parameters.
 
     Univariate: [log kappa, phi, log tau_u, log tau_y].
@@ -43,22 +50,33 @@ def theta_to_params(theta, nv: int) -> dict:
     rho = tanh(phi/2) inverts phi = log((1+rho)/(1-rho)), which keeps the AR1
     coefficient inside (-1, 1) for every real phi.  Optimisation is
     unconstrained over theta (Eq. 9).
+
+    The diffusion-based model reads the first two slots of each process as
+    log gamma_s and log gamma_t (spatial and temporal rate of the diffusion
+    operator, see ``diffusion_precision``); the remaining slots keep their
+    meaning, so the dimension of theta does not change.
     """
     th = np.asarray(theta, dtype=np.float64)
     assert th.shape == (theta_dim(nv),)
+    if model not in ("separable", "diffusion"):
+        raise ValueError(f"unknown model family {model!r}")
     if nv == 1:
-        return dict(kappa=np.exp(th[0:1]), rho=np.tanh(th[1:2] / 2),
-                    sigma=np.array([1.0 / math.sqrt(math.exp(th[2]))]),
-                    lam=np.zeros(0), tau_y=np.exp(th[3:4]),
-                    tau_u=math.exp(th[2]))
-    k = 0
-    kappa = np.exp(th[k:k + nv]); k += nv
-    rho = np.tanh(th[k:k + nv] / 2); k += nv
-    sigma = np.exp(th[k:k + nv]); k += nv
-    lam = th[k:k + n_lambda(nv)].copy(); k += n_lambda(nv)
-    tau_y = np.exp(th[k:k + nv])
-    return dict(kappa=kappa, rho=rho, sigma=sigma, lam=lam, tau_y=tau_y,
-                tau_u=None)
+        out = dict(sigma=np.array([1.0 / math.sqrt(math.exp(th[2]))]),
+                   lam=np.zeros(0), tau_y=np.exp(th[3:4]),
+                   tau_u=math.exp(th[2]))
+        head = (th[0:1], th[1:2])
+    else:
+        k = 2 * nv
+        sigma = np.exp(th[k:k + nv]); k += nv
+        lam = th[k:k + n_lambda(nv)].copy(); k += n_lambda(nv)
+        tau_y = np.exp(th[k:k + nv])
+        out = dict(sigma=sigma, lam=lam, tau_y=tau_y, tau_u=None)
+        head = (th[0:nv], th[nv:2 * nv])
+    if model == "diffusion":
+        out.update(gamma_s=np.exp(head[0]), gamma_t=np.exp(head[1]))
+    else:
+        out.update(kappa=np.exp(head[0]), rho=np.tanh(head[1] / 2))
+    return out
 
 
 def log_prior_theta(theta, mean, sd: float) -> float:
@@ -134,6 +152,73 @@ def spacetime_precision(nx: int, nt: int, kappa: float, rho: float):
                    format="csr")
 
 
+# --- non-separable diffusion-based space-time precision ----------------------------
+
+def temporal_fem(nt: int):
+    """Temporal FEM matrices of piecewise-linear elements on the time nodes
+    0, 1, ..., nt-1 (unit spacing):
+
+      M0  lumped mass: the integral of each hat function, 1/2 at the two end
+          nodes and 1 inside;
+      M1  boundary matrix: 1/2 at the two end nodes, 0 elsewhere;
+      M2  stiffness: the integrals of products of hat-function derivatives,
+          tridiag(-1; [1, 2, ..., 2, 1]; -1).
+
+    Needs nt >= 2 (one node spans no interval)."""
+    if nt < 2:
+        raise ValueError("the diffusion-based model needs nt >= 2")
+    m0 = np.ones(nt)
+    m0[0] = m0[-1] = 0.5
+    m1 = np.zeros(nt)
+    m1[0] = m1[-1] = 0.5
+    d2 = np.full(nt, 2.0)
+    d2[0] = d2[-1] = 1.0
+    off = -np.ones(nt - 1)
+    return (sp.diags(m0).tocsr(), sp.diags(m1).tocsr(),
+            sp.diags([off, d2, off], [-1, 0, 1]).tocsr())
+
+
+def spatial_operator_powers(nx: int, gamma_s: float):
+    """K_k, k = 1, 2, 3: the FEM matrices of L^k for L = gamma_s^2 - Laplace,
+    K_1 = gamma_s^2 C + G and K_{k+1} = K_1 C^{-1} K_k."""
+    C = mass_C(nx)
+    G = stiffness_G(nx)
+    Cinv = sp.diags(1.0 / C.diagonal())
+    K1 = (gamma_s ** 2 * C + G).tocsr()
+    K2 = (K1 @ Cinv @ K1).tocsr()
+    K3 = (K1 @ Cinv @ K2).tocsr()
+    return K1, K2, K3
+
+
+def diffusion_precision(nx: int, nt: int, gamma_s: float, gamma_t: float):
+    """Non-separable space-time precision as a sum of Kronecker products of
+    temporal and spatial FEM matrices, time outermost (Section III-B,
+    multivariate models, citing the diffusion-based family of Lindgren et
+    al.).  The paper gives no formula; read as the critical diffusion model
+    with one time derivative, a second-order spatial operator and a
+    first-order smoothing of the driving noise:
+
+        Q = M0 (x) K_3 + 2 gamma_t M1 (x) K_2 + gamma_t^2 M2 (x) K_1,
+
+    the discretised quadratic form of (gamma_t d/dt + L) x with noise
+    precision L, the boundary term of the time integral taken with a plus
+    sign at both ends (stationary start).  The overall scale is the process
+    scale of the surrounding model (tau_u, or sigma_i through Lambda)."""
+    M0, M1, M2 = temporal_fem(nt)
+    K1, K2, K3 = spatial_operator_powers(nx, gamma_s)
+    Q = (sp.kron(M0, K3) + 2.0 * gamma_t * sp.kron(M1, K2)
+         + gamma_t ** 2 * sp.kron(M2, K1))
+    return Q.tocsr()
+
+
+def process_precision(wl, p: dict, i: int):
+    """Precision of univariate process i (unit process scale)."""
+    if getattr(wl, "model", "separable") == "diffusion":
+        return diffusion_precision(wl.nx, wl.nt, p["gamma_s"][i],
+                                   p["gamma_t"][i])
+    return spacetime_precision(wl.nx, wl.nt, p["kappa"][i], p["rho"][i])
+
+
 # --- coregionalisation (Eq. 5, 6, 11) ------------------------------------------------
 
 def coregionalisation_matrix(sigma, lam) -> np.ndarray:
@@ -167,6 +252,10 @@ def mixing_weights(sigma, lam) -> np.ndarray:
 
 # --- the latent model ------------------------------------------------------------------
 
+def model_family(wl) -> str:
+    return getattr(wl, "model", "separable")
+
+
 def prior_precision(wl, theta) -> sp.csr_matrix:
     """Q_p(theta) in model order.
 
@@ -174,17 +263,16 @@ def prior_precision(wl, theta) -> sp.csr_matrix:
     effects (Eq. 1 with x extended by the fixed effects, Section II-A).
     nv > 1: the joint precision of Eq. 11 built from the univariate
     T^i (x) Q_s^i (each with its own kappa_i, rho_i), bordered likewise.
-    The fixed effects are not mixed by Lambda.
+    The fixed effects are not mixed by Lambda.  The diffusion-based family
+    puts ``diffusion_precision`` in place of T (x) Q_s.
     """
     nv, nx, nt = wl.nv, wl.nx, wl.nt
-    p = theta_to_params(theta, nv)
+    p = theta_to_params(theta, nv, model_family(wl))
     nst = nx * nx * nt
     if nv == 1:
-        Qz = p["tau_u"] * spacetime_precision(nx, nt, p["kappa"][0],
-                                              p["rho"][0])
+        Qz = p["tau_u"] * process_precision(wl, p, 0)
     else:
-        Qi = [spacetime_precision(nx, nt, p["kappa"][i], p["rho"][i])
-              for i in range(nv)]
+        Qi = [process_precision(wl, p, i) for i in range(nv)]
         M = mixing_weights(p["sigma"], p["lam"])
         blocks = [[None] * nv for _ in range(nv)]
         for j in range(nv):
@@ -231,7 +319,7 @@ def design_matrix(wl) -> sp.csr_matrix:
 def noise_precision(wl, theta) -> np.ndarray:
     """Diagonal of D(theta): the Gaussian likelihood's negative Hessian, i.e.
     tau_y_j for every row of response j (Eq. 4)."""
-    p = theta_to_params(theta, wl.nv)
+    p = theta_to_params(theta, wl.nv, model_family(wl))
     return np.concatenate([np.full(r.y.shape[0], p["tau_y"][j])
                            for j, r in enumerate(wl.responses)])
 

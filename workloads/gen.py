@@ -25,7 +25,10 @@ library and the oracle both accept:
   univariate  [log kappa, phi, log tau_u, log tau_y]
   trivariate  [log kappa_1..3, phi_1..3, log sigma_1..3, lambda_1..3,
                log tau_y_1..3]
-with phi = log((1+rho)/(1-rho)).
+with phi = log((1+rho)/(1-rho)).  A workload of the diffusion-based
+(non-separable) space-time model (``model="diffusion"``) puts log gamma_s and
+log gamma_t of each process in the slots of log kappa and phi; the other
+slots keep their meaning.
 """
 from __future__ import annotations
 
@@ -59,6 +62,7 @@ class Workload:
     theta_prior_sd: float = 1.0
     prior_fixed: float = 1e-3     # precision of each fixed effect
     seed: int = 0
+    model: str = "separable"      # or "diffusion" (non-separable)
 
     @property
     def ns(self) -> int:
@@ -123,24 +127,39 @@ def _smooth_signal(rng: np.random.Generator, nx: int, nt: int, cells, t,
     return out
 
 
+def _check_model(model: str) -> None:
+    if model not in ("separable", "diffusion"):
+        raise ValueError(f"unknown model family {model!r}")
+
+
 def make_univariate(name: str, nx: int, nt: int, nr: int, m: int, *,
                     kappa: float = 1.0, rho: float = 0.7, tau_u: float = 1.0,
-                    tau_y: float = 4.0, seed: int = 0) -> Workload:
-    """Univariate workload: responses y ~ N(0,1), one observation set."""
+                    tau_y: float = 4.0, seed: int = 0,
+                    model: str = "separable", gamma_s: float = 1.0,
+                    gamma_t: float = 2.0) -> Workload:
+    """Univariate workload: responses y ~ N(0,1), one observation set.
+    ``model="diffusion"`` takes gamma_s, gamma_t in place of kappa, rho."""
+    _check_model(model)
     rng = np.random.default_rng(seed)
     t, nodes, w, X, _ = _draw_rows(rng, nx, nt, m, nr)
     y = rng.standard_normal(m)
-    theta = np.array([math.log(kappa), _phi(rho), math.log(tau_u),
-                      math.log(tau_y)])
+    if model == "diffusion":
+        head = [math.log(gamma_s), math.log(gamma_t)]
+    else:
+        head = [math.log(kappa), _phi(rho)]
+    theta = np.array(head + [math.log(tau_u), math.log(tau_y)])
     return Workload(name=name, nx=nx, nt=nt, nv=1, nr=nr,
                     responses=[Response(t, nodes, w, X, y)],
-                    theta=theta, theta_prior_mean=theta.copy(), seed=seed)
+                    theta=theta, theta_prior_mean=theta.copy(), seed=seed,
+                    model=model)
 
 
 def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
                     kappa=(0.5, 1.0, 2.0), rho=(0.6, 0.8, 0.9),
                     tau_y=(4.0, 4.0, 4.0), seed: int = 0,
-                    nv: int = 3) -> Workload:
+                    nv: int = 3, model: str = "separable",
+                    gamma_s=(0.5, 1.0, 2.0),
+                    gamma_t=(1.0, 2.0, 4.0)) -> Workload:
     """Coregional workload with nv responses.
 
     sigma_i = max(|z|, 0.5) and lambda_i ~ N(0,1) play the role of the
@@ -148,7 +167,9 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
     positive diagonal.  Responses are a smooth random signal at the cell of
     each row, plus covariate effects, plus N(0, 1/tau_y) noise, so that the
     optimum of the objective lies inside the parameter space.
+    ``model="diffusion"`` takes gamma_s, gamma_t in place of kappa, rho.
     """
+    _check_model(model)
     rng = np.random.default_rng(seed)
     z = rng.standard_normal(nv)
     sigma = np.maximum(np.abs(z), 0.5)
@@ -164,13 +185,17 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
         noise = rng.standard_normal(m_per) / math.sqrt(tau_y[j])
         y = sig + X @ beta + noise
         responses[j] = Response(t, nodes, w, X, y)
-    theta = np.concatenate([np.log(np.asarray(kappa[:nv])),
-                            [_phi(r) for r in rho[:nv]],
-                            np.log(sigma), lam,
-                            np.log(np.asarray(tau_y[:nv]))])
+    if model == "diffusion":
+        head = [np.log(np.asarray(gamma_s[:nv], np.float64)),
+                np.log(np.asarray(gamma_t[:nv], np.float64))]
+    else:
+        head = [np.log(np.asarray(kappa[:nv])),
+                np.array([_phi(r) for r in rho[:nv]])]
+    theta = np.concatenate(head + [np.log(sigma), lam,
+                                   np.log(np.asarray(tau_y[:nv]))])
     return Workload(name=name, nx=nx, nt=nt, nv=nv, nr=nr,
                     responses=responses, theta=theta,
-                    theta_prior_mean=theta.copy(), seed=seed)
+                    theta_prior_mean=theta.copy(), seed=seed, model=model)
 
 
 # --- the named configurations ------------------------------------------------
@@ -181,25 +206,30 @@ def config0(seed: int = 0) -> Workload:
                            seed=seed)
 
 
-def config1(seed: int = 0) -> Workload:
+def _suffix(model: str) -> str:
+    return "" if model == "separable" else "_" + model
+
+
+def config1(seed: int = 0, model: str = "separable") -> Workload:
     """Production univariate: 45x45 grid (b=2025), nt=100, nr=4, m=200000."""
-    return make_univariate("c1_univariate_45x45_nt100", 45, 100, 4, 200_000,
-                           seed=seed)
+    return make_univariate("c1_univariate_45x45_nt100" + _suffix(model), 45,
+                           100, 4, 200_000, seed=seed, model=model)
 
 
-def config2(seed: int = 0) -> Workload:
+def config2(seed: int = 0, model: str = "separable") -> Workload:
     """Trivariate coregional: 30x30 grid (b=2700), nt=48, nr=2 (a=6),
     m = 3 x 48 x 900."""
-    return make_trivariate("c2_trivariate_30x30_nt48", 30, 48, 2, 48 * 900,
-                           seed=seed)
+    return make_trivariate("c2_trivariate_30x30_nt48" + _suffix(model), 30,
+                           48, 2, 48 * 900, seed=seed, model=model)
 
 
 def scaled(name: str, nx: int, nt: int, nv: int, nr: int, m_per: int,
-           seed: int = 0) -> Workload:
+           seed: int = 0, model: str = "separable") -> Workload:
     """Same generator at other sizes (parity cases, edge cases)."""
     if nv == 1:
-        return make_univariate(name, nx, nt, nr, m_per, seed=seed)
-    return make_trivariate(name, nx, nt, nr, m_per, seed=seed, nv=nv)
+        return make_univariate(name, nx, nt, nr, m_per, seed=seed, model=model)
+    return make_trivariate(name, nx, nt, nr, m_per, seed=seed, nv=nv,
+                           model=model)
 
 
 def uneven_instance(k: int) -> Workload:
