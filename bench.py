@@ -46,7 +46,8 @@ def fac_flops(n, b, a):
             + (n - 1) * (2 * b ** 3 + 2 * a * b * b) + a ** 3 / 3)
 
 
-def cpu_baseline(nt_sample: int = 20, var_samples: int = 8):
+def cpu_baseline(nt_sample: int = 20, var_samples: int = 8,
+                 model: str = "separable"):
     """The CPU oracle on a bounded sample of the same workload: the same
     generator and mesh with nt_sample time steps (2,000 observations per
     step), scaled linearly in nt (banded Cholesky cost is linear in N for a
@@ -57,7 +58,7 @@ def cpu_baseline(nt_sample: int = 20, var_samples: int = 8):
     import workloads as W
     from oracle import fobj as OF
     wl = W.make_univariate("c1_sample", 45, nt_sample, 4, 2000 * nt_sample,
-                           seed=0)
+                           seed=0, model=model)
     t0 = time.perf_counter()
     p = OF.fobj_parts(wl, wl.theta, method="banded", return_factors=True)
     t1 = time.perf_counter()
@@ -175,6 +176,11 @@ def main():
                     help="run only the warmup and timed steps and print their "
                          "line (the launch mix a kernel profiler then sees is "
                          "the timed region's)")
+    ap.add_argument("--model", choices=("separable", "diffusion"),
+                    default="separable",
+                    help="model family of the workload (the headline is the "
+                         "separable one; 'diffusion' times the non-separable "
+                         "space-time model on the same mesh and data)")
     ap.add_argument("--tiles", default=os.path.join(
         ROOT, "paper_2507_06938_amd", "tiles_gfx950.txt"),
         help="autotuner cache ('' disables tuning: default tiles)")
@@ -192,7 +198,7 @@ def main():
         B.build(verbose=False)
     import workloads as W
 
-    wl = W.config1()
+    wl = W.config1(model=args.model)
     model = D.Model.from_workload(wl)
     ws = D.Workspace(model, selinv=True)
     tiles = ws.autotune(args.tiles) if args.tiles else None
@@ -259,7 +265,9 @@ def main():
     torch.cuda.synchronize()
     pr = parts.cpu().numpy()[0]
 
-    golden_path = os.path.join(ROOT, "tests", "golden", "c1_golden.json")
+    golden_path = os.path.join(
+        ROOT, "tests", "golden",
+        "c1_golden.json" if args.model == "separable" else f"c1_{args.model}_golden.json")
     g = json.load(open(golden_path)) if os.path.exists(golden_path) else None
 
     def errors(p):
@@ -293,7 +301,7 @@ def main():
         out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles)
         out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt, model=args.model)
     print(json.dumps(out), flush=True)
 
 

@@ -73,7 +73,25 @@ typedef struct dl_model_desc {
   const double* theta_prior_mean; /* dim_theta values                     */
   double theta_prior_sd;          /* sd of the Gaussian prior on theta    */
   double prior_fixed;             /* precision of each fixed effect       */
+  int32_t family;                 /* DL_MODEL_SEPARABLE (0, what a zeroed
+                                     descriptor selects) or
+                                     DL_MODEL_DIFFUSION                    */
 } dl_model_desc;
+
+/* Model families of each univariate process (Section II-A; Section III-B,
+ * multivariate models, which builds each univariate precision as a sum of
+ * Kronecker products of temporal and spatial FEM matrices).
+ *   DL_MODEL_SEPARABLE  T (x) Q_s: unit-variance AR1 in time times the SPDE
+ *                       precision Q_s = kappa^4 C + 2 kappa^2 G + G C^-1 G.
+ *   DL_MODEL_DIFFUSION  non-separable diffusion-based model
+ *                         M0 (x) K3 + 2 gamma_t M1 (x) K2 + gamma_t^2 M2 (x) K1
+ *                       with K1 = gamma_s^2 C + G, K_{k+1} = K1 C^-1 K_k and the
+ *                       temporal FEM matrices of unit-spaced time nodes: M0
+ *                       lumped mass (1/2 at both ends, 1 inside), M1 = 1/2 at
+ *                       both ends, M2 stiffness tridiag(-1; 1,2,...,2,1; -1).
+ *                       Needs nt >= 2.  Its spatial stencil reaches grid
+ *                       distance 3 (25 points) instead of 2 (13 points). */
+enum { DL_MODEL_SEPARABLE = 0, DL_MODEL_DIFFUSION = 1 };
 
 /* Parts of f_obj (Eq. 8) written by fobj_eval, one record per theta. */
 typedef struct dl_fobj_parts {
@@ -90,13 +108,16 @@ typedef struct dl_fobj_parts {
 /* Number of hyperparameters: 4 for nv = 1, 4*nv + nv(nv-1)/2 otherwise.
  * theta layout, univariate: [log kappa, phi, log tau_u, log tau_y];
  * coregional: [log kappa_i (nv), phi_i (nv), log sigma_i (nv),
- * lambda_k (nv(nv-1)/2), log tau_y_j (nv)], rho = tanh(phi/2). */
+ * lambda_k (nv(nv-1)/2), log tau_y_j (nv)], rho = tanh(phi/2).
+ * DL_MODEL_DIFFUSION reads log gamma_s in the slots of log kappa and
+ * log gamma_t in the slots of phi; the other slots keep their meaning. */
 int32_t dl_theta_dim(int32_t nv);
 
 /* Upload a model.  Builds the spatial pattern (Section II-A, SPDE FEM) and
  * per-(response, time, node) observation index lists on the host (integer
  * work only) and copies all arrays to the device.  nv in {1,2,3}; nx >= 2;
- * nt >= 1; nr >= 0; every obs_t < nt and every node < nx*nx. */
+ * nt >= 1 (>= 2 for DL_MODEL_DIFFUSION); nr >= 0; every obs_t < nt and every
+ * node < nx*nx; family one of the DL_MODEL_* values.  DL_EINVAL otherwise. */
 dl_status dl_model_create(const dl_model_desc* desc_host, dl_model** out);
 void dl_model_destroy(dl_model* model);
 

@@ -12,8 +12,16 @@ namespace dl {
 // log tau_y]; coregional [log kappa_i, phi_i, log sigma_i, lambda_k,
 // log tau_y_j], rho = tanh(phi/2).  Lambda is the lower-triangular matrix of
 // Eq. 5; the joint precision has blocks (k, j) = sum_i (Lambda^-1)_{ik}
-// (Lambda^-1)_{ij} Q^i (Eq. 11).  Q^i = T^i (x) Q_s^i, Q_s = kappa^4 C +
-// 2 kappa^2 G + G C^-1 G, T the unit-variance AR1 precision.
+// (Lambda^-1)_{ij} Q^i (Eq. 11).  Separable family: Q^i = T^i (x) Q_s^i,
+// Q_s = kappa^4 C + 2 kappa^2 G + G C^-1 G, T the unit-variance AR1
+// precision.  Diffusion family (log gamma_s, log gamma_t in the slots of
+// log kappa, phi): Q^i = M0 (x) K3 + 2 gamma_t M1 (x) K2 + gamma_t^2 M2 (x) K1
+// with K1 = g C + G, K2 = g^2 C + 2g G + G C^-1 G, K3 = g^3 C + 3g^2 G +
+// 3g G C^-1 G + G C^-1 G C^-1 G (g = gamma_s^2, the binomial expansion of
+// K_{k+1} = K1 C^-1 K_k), M0 = 1/2 | 1 | 1/2, M1 = 1/2 | 0 | 1/2 and
+// M2 = 1 | 2 | 1 on the diagonal (end | inside | end), -1 off it.  Either
+// way Q^i's diagonal and sub-diagonal blocks are weighted sums of the four
+// FEM pieces; wd/wb below hold those weights per process.
 __global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
   if (threadIdx.x != 0) return;
   const ThetaJob J = jobs[blockIdx.x];
@@ -68,38 +76,61 @@ __global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
       for (int j = 0; j < nv; ++j)
         for (int k = 0; k < nv; ++k) Mw[i][j][k] = Li[i][j] * Li[i][k];
   }
-  double q[3][3], Tend[3], Tmid[3], Toff[3];
+  // wd[i][tt][c]: weight of FEM piece c in a diagonal block of Q^i (tt = 0
+  // end step, 1 inside, 2 single step); wb[i][c]: sub-diagonal block
+  double wd[3][3][NPIECE], wb[3][NPIECE];
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < NPIECE; ++c) {
+      wb[i][c] = 0.0;
+      for (int tt = 0; tt < 3; ++tt) wd[i][tt][c] = 0.0;
+    }
+  const bool diffusion = m.family == DL_MODEL_DIFFUSION;
   for (int i = 0; i < nv; ++i) {
-    const double k2 = kap[i] * kap[i];
-    q[i][0] = k2 * k2;
-    q[i][1] = 2.0 * k2;
-    q[i][2] = 1.0;
-    const double r = rho[i];
-    const double den = 1.0 - r * r;
-    if (!(den > 0.0) || !isfinite(kap[i]) || !isfinite(tau[i])) bad = 1;
-    Tend[i] = 1.0 / den;
-    Tmid[i] = (1.0 + r * r) / den;
-    Toff[i] = -r / den;
+    if (!isfinite(kap[i]) || !isfinite(tau[i])) bad = 1;
+    if (diffusion) {
+      const double g = kap[i] * kap[i];
+      const double gt = exp(theta[nv + i]);
+      if (!isfinite(gt)) bad = 1;
+      const double K1[NPIECE] = {g, 1.0, 0.0, 0.0};
+      const double K2[NPIECE] = {g * g, 2.0 * g, 1.0, 0.0};
+      const double K3[NPIECE] = {g * g * g, 3.0 * g * g, 3.0 * g, 1.0};
+      for (int c = 0; c < NPIECE; ++c) {
+        wd[i][0][c] = 0.5 * K3[c] + gt * K2[c] + gt * gt * K1[c];
+        wd[i][1][c] = K3[c] + 2.0 * gt * gt * K1[c];
+        wd[i][2][c] = wd[i][0][c];  // nt = 1 is rejected at model creation
+        wb[i][c] = -gt * gt * K1[c];
+      }
+    } else {
+      const double k2 = kap[i] * kap[i];
+      const double q[NPIECE] = {k2 * k2, 2.0 * k2, 1.0, 0.0};
+      const double r = rho[i];
+      const double den = 1.0 - r * r;
+      if (!(den > 0.0)) bad = 1;
+      const double Tend = 1.0 / den, Tmid = (1.0 + r * r) / den, Toff = -r / den;
+      for (int c = 0; c < NPIECE; ++c) {
+        wd[i][0][c] = Tend * q[c];
+        wd[i][1][c] = Tmid * q[c];
+        wd[i][2][c] = q[c];
+        wb[i][c] = Toff * q[c];
+      }
+    }
   }
   for (int tt = 0; tt < 3; ++tt)
     for (int k = 0; k < 3; ++k)
       for (int j = 0; j < 3; ++j)
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NPIECE; ++c) {
           double v = 0.0;
           if (k < nv && j < nv)
-            for (int i = 0; i < nv; ++i) {
-              const double tv = tt == 0 ? Tend[i] : (tt == 1 ? Tmid[i] : 1.0);
-              v += Mw[i][k][j] * tv * q[i][c];
-            }
-          coef[C_D + ((tt * 3 + k) * 3 + j) * 3 + c] = v;
+            for (int i = 0; i < nv; ++i) v += Mw[i][k][j] * wd[i][tt][c];
+          coef[C_D + ((tt * 3 + k) * 3 + j) * NPIECE + c] = v;
         }
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < 3; ++j)
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < NPIECE; ++c) {
         double v = 0.0;
         if (k < nv && j < nv)
-          for (int i = 0; i < nv; ++i) v += Mw[i][k][j] * Toff[i] * q[i][c];
-        coef[C_B + (k * 3 + j) * 3 + c] = v;
+          for (int i = 0; i < nv; ++i) v += Mw[i][k][j] * wb[i][c];
+        coef[C_B + (k * 3 + j) * NPIECE + c] = v;
       }
   const double two_pi = 6.283185307179586476925286766559;
   double lp = 0.0;
@@ -187,12 +218,12 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
     const int e = e0 + idx / nv;
     const int k = idx % nv;
     const int r = k * ns + m.sp_col[e];
-    const double pc = m.sp_C[e], pg = m.sp_G[e], pg2 = m.sp_G2[e];
-    const double* cd = J.coef + C_D + ((tt * 3 + k) * 3 + j) * 3;
-    colD[r] = cd[0] * pc + cd[1] * pg + cd[2] * pg2;
+    const double pc = m.sp_C[e], pg = m.sp_G[e], pg2 = m.sp_G2[e], pg3 = m.sp_G3[e];
+    const double* cd = J.coef + C_D + ((tt * 3 + k) * 3 + j) * NPIECE;
+    colD[r] = cd[0] * pc + cd[1] * pg + cd[2] * pg2 + cd[3] * pg3;
     if (hasB) {
-      const double* cb = J.coef + C_B + (k * 3 + j) * 3;
-      colB[r] = cb[0] * pc + cb[1] * pg + cb[2] * pg2;
+      const double* cb = J.coef + C_B + (k * 3 + j) * NPIECE;
+      colB[r] = cb[0] * pc + cb[1] * pg + cb[2] * pg2 + cb[3] * pg3;
     }
   }
   __syncthreads();
@@ -334,8 +365,9 @@ hipError_t launch_assemble_tips(const AsmJob* jobs, int count, int max_blocks,
 //
 // mu^T Q_p mu with Q_p applied from its stencil (no dense blocks): row
 // (t, k, s') of Q_p mu = sum over time neighbours t' in {t-1, t, t+1},
-// responses j and spatial neighbours s of coef(t,t')_{kj} . (C, G, GC^-1G)
-// at (s', s) times mu(t', j, s); fixed effects add prior_fixed * |mu_f|^2.
+// responses j and spatial neighbours s of coef(t,t')_{kj} . (C, G, GC^-1G,
+// GC^-1GC^-1G) at (s', s) times mu(t', j, s); fixed effects add
+// prior_fixed * |mu_f|^2.
 // (y - A mu)^T D (y - A mu) row by row.  Both are reduced with a fixed tree
 // per block, then over blocks in order.
 __device__ __forceinline__ double blk_sum(double v, double* sh) {
@@ -372,11 +404,12 @@ __global__ __launch_bounds__(256) void k_quad_prior(const QuadJob* __restrict__ 
       const int t2 = t + dt;
       if (t2 < 0 || t2 >= m.nt) continue;
       for (int j = 0; j < nv; ++j) {
-        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * 3
-                                     : coef + C_B + (k * 3 + j) * 3;
+        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * NPIECE
+                                     : coef + C_B + (k * 3 + j) * NPIECE;
         const double* x = mu + (int64_t)t2 * bp + j * ns;
         for (int e = m.sp_ptr[sp]; e < m.sp_ptr[sp + 1]; ++e) {
-          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e];
+          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e] +
+                            cf[3] * m.sp_G3[e];
           qmu += qv * x[m.sp_col[e]];
         }
       }
@@ -566,11 +599,12 @@ __global__ __launch_bounds__(256) void k_res_rows(const ResJob* __restrict__ job
       const int t2 = t + dt;
       if (t2 < 0 || t2 >= m.nt) continue;
       for (int j = 0; j < nv; ++j) {
-        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * 3
-                                     : coef + C_B + (k * 3 + j) * 3;
+        const double* cf = (dt == 0) ? coef + C_D + ((tt * 3 + k) * 3 + j) * NPIECE
+                                     : coef + C_B + (k * 3 + j) * NPIECE;
         const double* x = R.v + (int64_t)t2 * bp + j * ns;
         for (int e = m.sp_ptr[sp]; e < m.sp_ptr[sp + 1]; ++e) {
-          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e];
+          const double qv = cf[0] * m.sp_C[e] + cf[1] * m.sp_G[e] + cf[2] * m.sp_G2[e] +
+                            cf[3] * m.sp_G3[e];
           q += qv * x[m.sp_col[e]];
         }
       }

@@ -37,6 +37,9 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
       (2 * ((nv * nx * nx + 63) / 64) * 64 + 64) * 8 > 160 * 1024)
     return DL_EINVAL;
   if (!desc->theta_prior_mean || !(desc->theta_prior_sd > 0.0)) return DL_EINVAL;
+  const int family = desc->family;
+  if (family != DL_MODEL_SEPARABLE && family != DL_MODEL_DIFFUSION) return DL_EINVAL;
+  if (family == DL_MODEL_DIFFUSION && nt < 2) return DL_EINVAL;
   const int ns = nx * nx;
   for (int j = 0; j < nv; ++j) {
     if (desc->m[j] < 0) return DL_EINVAL;
@@ -56,6 +59,7 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
   if (!M) return DL_ENOMEM;
   ModelDev& d = M->d;
   d.nx = nx; d.nt = nt; d.nv = nv; d.nr = nr; d.ns = ns;
+  d.family = family;
   d.b = nv * ns; d.a = nv * nr;
   d.bp = ((d.b + 63) / 64) * 64;
   d.ap = d.a > 0 ? 64 : 0;
@@ -66,9 +70,12 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
   d.prior_fixed = desc->prior_fixed;
 
   // FEM pieces on the grid: C = I (lumped mass, unit spacing), G = 5-point
-  // Neumann graph Laplacian, G C^-1 G = G*G.  Pattern: 13-point stencil.
+  // Neumann graph Laplacian, G C^-1 G = G*G and G C^-1 G C^-1 G = G*G*G.
+  // Pattern: all nodes within grid distance 2 (13-point stencil), or 3 for
+  // the diffusion model, whose K3 holds the third power of G.
   std::vector<int> ptr(ns + 1, 0), col;
-  std::vector<double> vC, vG, vG2;
+  std::vector<double> vC, vG, vG2, vG3;
+  auto inside = [&](int x, int y) { return x >= 0 && y >= 0 && x < nx && y < nx; };
   auto deg = [&](int ix, int iy) {
     return (ix > 0) + (ix < nx - 1) + (iy > 0) + (iy < nx - 1);
   };
@@ -77,29 +84,43 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
     if (abs(ax - bx) + abs(ay - by) == 1) return -1.0;
     return 0.0;
   };
+  // row a of G has its nonzeros at a and its grid neighbours
+  static const int nb5[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+  auto g2val = [&](int ax, int ay, int bx, int by) -> double {
+    double acc = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      const int kx = ax + nb5[q][0], ky = ay + nb5[q][1];
+      if (inside(kx, ky)) acc += gval(ax, ay, kx, ky) * gval(kx, ky, bx, by);
+    }
+    return acc;
+  };
+  auto g3val = [&](int ax, int ay, int bx, int by) -> double {
+    double acc = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      const int kx = ax + nb5[q][0], ky = ay + nb5[q][1];
+      if (inside(kx, ky)) acc += gval(ax, ay, kx, ky) * g2val(kx, ky, bx, by);
+    }
+    return acc;
+  };
+  const int reach = family == DL_MODEL_DIFFUSION ? 3 : 2;
   for (int iy = 0; iy < nx; ++iy)
     for (int ix = 0; ix < nx; ++ix) {
       const int s = iy * nx + ix;
-      for (int dy = -2; dy <= 2; ++dy)
-        for (int dx = -2; dx <= 2; ++dx) {
-          if (abs(dx) + abs(dy) > 2) continue;
+      for (int dy = -reach; dy <= reach; ++dy)
+        for (int dx = -reach; dx <= reach; ++dx) {
+          if (abs(dx) + abs(dy) > reach) continue;
           const int jx = ix + dx, jy = iy + dy;
-          if (jx < 0 || jy < 0 || jx >= nx || jy >= nx) continue;
-          // (G G)(s, s') = sum over k of G(s,k) G(k,s'), k within 1 of both
-          double g2 = 0.0;
-          for (int ky = iy - 1; ky <= iy + 1; ++ky)
-            for (int kx = ix - 1; kx <= ix + 1; ++kx) {
-              if (kx < 0 || ky < 0 || kx >= nx || ky >= nx) continue;
-              if (abs(kx - ix) + abs(ky - iy) > 1) continue;
-              g2 += gval(ix, iy, kx, ky) * gval(kx, ky, jx, jy);
-            }
+          if (!inside(jx, jy)) continue;
           const double c = (dx == 0 && dy == 0) ? 1.0 : 0.0;
           const double g = gval(ix, iy, jx, jy);
-          if (c == 0.0 && g == 0.0 && g2 == 0.0) continue;
+          const double g2 = g2val(ix, iy, jx, jy);
+          const double g3 = reach == 3 ? g3val(ix, iy, jx, jy) : 0.0;
+          if (c == 0.0 && g == 0.0 && g2 == 0.0 && g3 == 0.0) continue;
           col.push_back(jy * nx + jx);
           vC.push_back(c);
           vG.push_back(g);
           vG2.push_back(g2);
+          vG3.push_back(g3);
         }
       ptr[s + 1] = (int)col.size();
     }
@@ -155,6 +176,7 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
       (st = upload(M->allocs, vC, &d.sp_C)) != DL_OK ||
       (st = upload(M->allocs, vG, &d.sp_G)) != DL_OK ||
       (st = upload(M->allocs, vG2, &d.sp_G2)) != DL_OK ||
+      (st = upload(M->allocs, vG3, &d.sp_G3)) != DL_OK ||
       (st = upload(M->allocs, ot, &d.obs_t)) != DL_OK ||
       (st = upload(M->allocs, on, &d.obs_nodes)) != DL_OK ||
       (st = upload(M->allocs, ow, &d.obs_w)) != DL_OK ||

@@ -9,30 +9,36 @@ namespace dl {
 //   [C_LLCONST]         sum_j m_j/2 log tau_j - m/2 log 2pi
 //   [C_BAD]             1 if theta maps outside the model (NaN, |rho| = 1)
 //   [C_TAU + j]         tau_y of response j
-//   [C_D + ((tt*3 + k)*3 + j)*3 + c]
-//                       weight of FEM piece c (0: C, 1: G, 2: G C^-1 G) in
-//                       block (k, j) of a diagonal block; tt = 0 first/last
-//                       time step, 1 interior step, 2 single step (nt = 1)
-//   [C_B + (k*3 + j)*3 + c]  the same for a sub-diagonal block
+//   [C_D + ((tt*3 + k)*3 + j)*NPIECE + c]
+//                       weight of FEM piece c (0: C, 1: G, 2: G C^-1 G,
+//                       3: G C^-1 G C^-1 G) in block (k, j) of a diagonal
+//                       block; tt = 0 first/last time step, 1 interior
+//                       step, 2 single step (nt = 1)
+//   [C_B + (k*3 + j)*NPIECE + c]  the same for a sub-diagonal block
 enum : int {
+  NPIECE = 4,
   C_LOGPRIOR = 0,
   C_LLCONST = 1,
   C_BAD = 2,
   C_TAU = 4,
   C_D = 8,
-  C_B = 8 + 81,
-  C_SIZE = 8 + 81 + 27 + 4
+  C_B = 8 + 27 * NPIECE,
+  C_SIZE = 8 + 36 * NPIECE + 4
 };
 
 struct ModelDev {
   int nx, nt, nv, nr, ns, b, a, bp, ap, dim_theta;
+  int family;             // DL_MODEL_SEPARABLE or DL_MODEL_DIFFUSION
   int64_t N, Np;          // unpadded and padded vector lengths
-  // 13-point spatial pattern of Q_s, CSR over nodes, with FEM pieces
+  // spatial pattern (13 points, or 25 for the diffusion model), CSR over
+  // nodes, with the values of the four FEM pieces (G3 is zero for the
+  // separable model)
   const int* sp_ptr;
   const int* sp_col;
   const double* sp_C;
   const double* sp_G;
   const double* sp_G2;
+  const double* sp_G3;
   // observations of all responses, concatenated
   int64_t m_total;
   int64_t m_off[4];

@@ -44,7 +44,11 @@ class _Desc(C.Structure):
                 ("obs_t", C.c_void_p * 3), ("obs_nodes", C.c_void_p * 3),
                 ("obs_w", C.c_void_p * 3), ("obs_x", C.c_void_p * 3),
                 ("y", C.c_void_p * 3), ("theta_prior_mean", C.c_void_p),
-                ("theta_prior_sd", C.c_double), ("prior_fixed", C.c_double)]
+                ("theta_prior_sd", C.c_double), ("prior_fixed", C.c_double),
+                ("family", C.c_int32)]
+
+
+MODEL_FAMILIES = {"separable": 0, "diffusion": 1}
 
 
 _lib = None
@@ -129,11 +133,15 @@ class Model:
 
     def __init__(self, nx: int, nt: int, nv: int, nr: int,
                  responses: Sequence, theta_prior_mean, theta_prior_sd=1.0,
-                 prior_fixed=1e-3):
+                 prior_fixed=1e-3, family: str = "separable"):
         L = lib()
+        if family not in MODEL_FAMILIES:
+            raise ValueError(f"unknown model family {family!r}")
         self.nx, self.nt, self.nv, self.nr = nx, nt, nv, nr
+        self.family = family
         d = _Desc()
         d.nx, d.nt, d.nv, d.nr = nx, nt, nv, nr
+        d.family = MODEL_FAMILIES[family]
         keep = []
         for j, r in enumerate(responses):
             t, nodes, w, X, y = r
@@ -166,7 +174,8 @@ class Model:
     def from_workload(cls, wl) -> "Model":
         resp = [(r.t, r.nodes, r.w, r.X, r.y) for r in wl.responses]
         return cls(wl.nx, wl.nt, wl.nv, wl.nr, resp, wl.theta_prior_mean,
-                   wl.theta_prior_sd, wl.prior_fixed)
+                   wl.theta_prior_sd, wl.prior_fixed,
+                   getattr(wl, "model", "separable"))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

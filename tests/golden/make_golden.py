@@ -1,6 +1,6 @@
 """Write the stored expected values of the full-size parity tests.
 
-    python tests/golden/make_golden.py c1 [c2]
+    python tests/golden/make_golden.py c1 [c2] [c1_diffusion]
 
 Calls only the CPU oracle (``oracle/``) on the seeded workloads of
 ``workloads/``; nothing here touches the GPU path.  For each configuration it
@@ -22,7 +22,8 @@ import workloads as W  # noqa: E402
 from oracle import fobj as OF  # noqa: E402
 from oracle import model as OM  # noqa: E402
 
-CONFIGS = {"c1": W.config1, "c2": W.config2}
+CONFIGS = {"c1": W.config1, "c2": W.config2,
+           "c1_diffusion": lambda: W.config1(model="diffusion")}
 
 
 def sample_positions(N, a, k, seed):

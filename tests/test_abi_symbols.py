@@ -32,3 +32,29 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     assert lib.dl_theta_dim(1) == 4 and lib.dl_theta_dim(3) == 15
+
+
+def test_model_create_rejects_bad_family_before_any_device_call():
+    """Argument checks of dl_model_create run on the host before any HIP
+    call: an unknown model family, and the diffusion-based family with a
+    single time step (its temporal FEM needs two nodes), give DL_EINVAL."""
+    import numpy as np
+    from paper_2507_06938_amd import build as B
+    from paper_2507_06938_amd import dalia as D
+    if not os.path.exists(B.LIB):
+        B.build(verbose=False)
+    L = D.lib()
+    pm = np.zeros(4)
+    for family, nt in ((7, 3), (-1, 3), (D.MODEL_FAMILIES["diffusion"], 1)):
+        d = D._Desc()
+        d.nx, d.nt, d.nv, d.nr = 4, nt, 1, 1
+        d.theta_prior_mean = pm.ctypes.data
+        d.theta_prior_sd = 1.0
+        d.prior_fixed = 1e-3
+        d.family = family
+        h = ctypes.c_void_p()
+        assert L.dl_model_create(ctypes.byref(d), ctypes.byref(h)) == 1  # DL_EINVAL
+        assert not h.value
+    # dl_model_desc: 4 int32, 3 int64, 16 pointers, 2 doubles, int32 family,
+    # padded to a multiple of 8
+    assert ctypes.sizeof(D._Desc) == 16 + 24 + 128 + 16 + 8

@@ -26,7 +26,9 @@ def D():
 
 
 @pytest.mark.parametrize("splitk", [False, True])
-@pytest.mark.parametrize("name,make", [("c1", W.config1), ("c2", W.config2)])
+@pytest.mark.parametrize("name,make", [
+    ("c1", W.config1), ("c2", W.config2),
+    ("c1_diffusion", lambda: W.config1(model="diffusion"))])
 def test_fullsize_against_banded_oracle(D, name, make, splitk):
     path = os.path.join(GOLD, f"{name}_golden.json")
     if not os.path.exists(path):

@@ -33,6 +33,9 @@ CASES = {
     "tri_small": lambda: W.scaled("tri", 6, 5, 3, 2, 60, seed=4),
     "c1_univariate_45x45_nt100": W.config1,
     "c2_trivariate_30x30_nt48": W.config2,
+    "diffusion_tri_small": lambda: W.scaled("dtri", 6, 5, 3, 2, 60, seed=4,
+                                            model="diffusion"),
+    "c1_univariate_45x45_nt100_diffusion": lambda: W.config1(model="diffusion"),
 }
 
 

@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle, element by
 element, on seeded workloads small enough for the dense oracle but spanning
 several 64x64 tiles, ragged block sizes and the degenerate cases (one time
-step, no fixed effects).
+step, no fixed effects), for the separable and the non-separable
+(diffusion-based) model families.
 
 Tolerances (FP64 throughout, condition numbers <= ~1e5 at these sizes):
   log-determinants   relative 1e-10
@@ -54,6 +55,14 @@ CASES = {
     "no_fixed": lambda: W.scaled("nof", 6, 4, 1, 0, 60, seed=10),
     "bivariate": lambda: W.scaled("bi", 6, 3, 2, 1, 40, seed=11),
     "multi_tile": lambda: W.scaled("mt", 12, 3, 1, 2, 300, seed=12),
+    # non-separable diffusion-based model: 25-point spatial stencil, the
+    # fourth FEM piece, nt = 2 (both steps are end steps) and ragged tiles
+    "diff_uni": lambda: W.scaled("du", 7, 5, 1, 2, 80, seed=13, model="diffusion"),
+    "diff_two_steps": lambda: W.scaled("d2", 6, 2, 1, 1, 40, seed=14,
+                                       model="diffusion"),
+    "diff_tri": lambda: W.scaled("dt", 5, 4, 3, 2, 40, seed=15, model="diffusion"),
+    "diff_multi_tile": lambda: W.scaled("dm", 11, 3, 1, 2, 250, seed=16,
+                                        model="diffusion"),
 }
 
 
