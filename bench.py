@@ -7,8 +7,11 @@ nt = 100, 4 fixed effects, 200,000 observations): theta -> coefficients,
 assembly of Q_p and Q_c into dense BTA blocks, BTA Cholesky of both,
 log-determinants, forward/backward solve for the conditional mean, the
 quadratic forms and f_obj, then the selected inversion of Q_c for all
-marginal variances.  Inputs are seeded and synthetic and already resident on
-the device when the timed region starts.
+marginal variances.  By default the time domain is split into two
+partitions eliminated concurrently toward a middle block (``--order
+two-sided``; ``one-sided`` sweeps the time steps forward only).  Inputs are
+seeded and synthetic and already resident on the device when the timed
+region starts.
 
 Prints one JSON line.  Besides the metric it reports the BTA Cholesky
 TFLOP/s of Q_c alone, the log-determinant error against the FP64 CPU oracle
@@ -96,7 +99,7 @@ def _events_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def fd_batch(D, W, wl, model, single_ms, tiles):
+def fd_batch(D, W, wl, model, single_ms, tiles, two_sided=False):
     """The 2 dim(theta) + 1 = 9 central-difference points of one gradient
     (Eq. 10, h = 1e-3) as one batched, graph-replayed evaluation."""
     import numpy as np
@@ -108,7 +111,7 @@ def fd_batch(D, W, wl, model, single_ms, tiles):
         pts[1 + 2 * i, i] += h
         pts[2 + 2 * i, i] -= h
     th = torch.tensor(pts, dtype=torch.float64, device="cuda")
-    ws = D.Workspace([model] * (2 * d + 1), graph=True)
+    ws = D.Workspace([model] * (2 * d + 1), graph=True, two_sided=two_sided)
     if tiles:
         ws.autotune(tiles)
     ms = _events_ms(torch, lambda: ws.fobj(th), 3)
@@ -124,11 +127,11 @@ def fd_batch(D, W, wl, model, single_ms, tiles):
             "gradient": grad, "all_spd": ok}
 
 
-def mixed(D, wl, model, errors, tiles):
+def mixed(D, wl, model, errors, tiles, two_sided=False):
     """f_obj with FP32 off-diagonal blocks (FP64 diagonal blocks, tip and
     refinement of the mean) at the same theta."""
     import torch
-    ws = D.Workspace(model, mixed=True)
+    ws = D.Workspace(model, mixed=True, two_sided=two_sided)
     if tiles:
         ws.autotune(tiles)
     th = torch.tensor(wl.theta, dtype=torch.float64, device="cuda")
@@ -181,6 +184,11 @@ def main():
                     help="model family of the workload (the headline is the "
                          "separable one; 'diffusion' times the non-separable "
                          "space-time model on the same mesh and data)")
+    ap.add_argument("--order", choices=("one-sided", "two-sided"),
+                    default="two-sided",
+                    help="elimination order: time steps forward only, or the "
+                         "two halves of the time domain concurrently toward "
+                         "a middle block (two time-domain partitions)")
     ap.add_argument("--tiles", default=os.path.join(
         ROOT, "paper_2507_06938_amd", "tiles_gfx950.txt"),
         help="autotuner cache ('' disables tuning: default tiles)")
@@ -200,7 +208,8 @@ def main():
 
     wl = W.config1(model=args.model)
     model = D.Model.from_workload(wl)
-    ws = D.Workspace(model, selinv=True)
+    two_sided = args.order == "two-sided"
+    ws = D.Workspace(model, selinv=True, two_sided=two_sided)
     tiles = ws.autotune(args.tiles) if args.tiles else None
     dev = torch.device("cuda")
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev)
@@ -287,6 +296,7 @@ def main():
         "config": {"workload": wl.name, "ns": wl.ns, "nt": wl.nt,
                    "nb": wl.a, "m": wl.m, "b": wl.b, "N": wl.N,
                    "step": "fobj_eval + bta_selinv (all marginal variances)",
+                   "order": args.order,
                    "gemm_tiles": tiles},
         "fobj_only_evals_per_s": 1000.0 / fobj_ms,
         "bta_cholesky_tflops": F / (fac_ms * 1e-3) / 1e12,
@@ -298,8 +308,9 @@ def main():
     del ws
     torch.cuda.empty_cache()
     if not args.no_extras:
-        out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles)
-        out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles)
+        out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles,
+                                            two_sided)
+        out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles, two_sided)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt, model=args.model)
     print(json.dumps(out), flush=True)

@@ -146,7 +146,20 @@ enum {
                          pieces of 512 summed in a fixed order: more
                          parallelism for single evaluations; the results
                          differ from an unsplit workspace by rounding only
-                         and do not depend on the tile sizes chosen         */
+                         and do not depend on the tile sizes chosen         */,
+  DL_WS_TWOSIDED = 32 /* time-domain partitioning into two partitions on one
+                         GPU (Sec. III-C, time-domain partitioning, with
+                         S3's nested dissection for two partitions, which
+                         have no middle partition and so add no work): the
+                         first half of the time steps is eliminated forward
+                         and the second half backward, concurrently (their
+                         steps share launches), into the middle block
+                         mid = floor((nt+1)/2), which is factored last;
+                         solve and selected inversion follow the same order.
+                         Needs nt >= 4 (otherwise one-sided).  Results
+                         differ from the one-sided order by rounding only.
+                         Relies on symmetric sub-diagonal blocks, which
+                         every model of this library has                    */
 };
 #define DL_REFINE_STEPS 3
 
@@ -228,7 +241,9 @@ dl_status dl_ws_mean(dl_ws* ws, double* out_dev, void* stream);
 /* Copy one assembled (or factored) block to out_dev, column-major, for
  * inspection: kind 0 = diagonal block D_t (b x b, lower triangle), 1 =
  * sub-diagonal block B_t (b x b, rows t+1, cols t), 2 = arrow block R_t
- * (a x b), 3 = tip (a x a, lower triangle), 4 = right-hand side (N). */
+ * (a x b), 3 = tip (a x a, lower triangle), 4 = right-hand side (N).  After
+ * a DL_WS_TWOSIDED factorisation kind 1 at t >= mid holds the factor's
+ * coupling of block t to block t-1 (its successor in that order). */
 dl_status dl_ws_get_block(dl_ws* ws, dl_which which, int32_t kind, int32_t t,
                           double* out_dev, void* stream);
 

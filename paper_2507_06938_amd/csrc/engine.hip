@@ -362,10 +362,22 @@ struct Inst {
   // blocks assembled just in time (only log|Q_p| is needed)
   double *Dp = nullptr, *Bp = nullptr, *Pp = nullptr;
   bool qp_ring = true;
-  // Q_c: full storage, [B_t; R_t] in nt+1 slots of (bp+ap) x bp
+  // Q_c: full storage, [B_t; R_t] in nt+1 slots of (bp+ap) x bp (nt+2 when
+  // two-sided: one spare slot per elimination chain)
   double *Dc = nullptr, *BRc = nullptr, *Pc = nullptr, *GPc = nullptr;
   int64_t ldbr = 0;
   std::vector<int> slot_final;
+  // Elimination order.  One-sided: blocks 0..nt-2 forward, then the root
+  // block nt-1.  Two-sided: chain A = 0..mid-1 forward and chain B =
+  // nt-1..mid+1 backward run concurrently (their steps share launches),
+  // each block eliminated into its neighbour toward the root block mid,
+  // which is factored last.  Chain B accumulates its tip updates (and the
+  // tip part of the forward solve) in buffers of its own.
+  bool two = false;
+  int mid = 0;
+  double *PcB = nullptr, *ttempB[2] = {nullptr, nullptr};
+  double *uB = nullptr, *gpartB = nullptr, *xPB = nullptr;
+  double *YB = nullptr, *XCB[2] = {nullptr, nullptr};
   double *theta = nullptr, *coef = nullptr, *logdiag[2] = {nullptr, nullptr};
   double *logdet2 = nullptr, *quad2 = nullptr, *sumpart = nullptr, *qpart = nullptr;
   int64_t* info2 = nullptr;
@@ -575,11 +587,22 @@ static void seq_assemble(dl_ws* W, Inst& I, bool p, bool c, std::vector<Step>& q
   }
 }
 
-// BTA Cholesky of Q_p (w = 0) or Q_c (w = 1) of instance I.  Keys: major =
-// t + 1 (0 is the prologue), then 1 + nt_max for the tip.
+// BTA Cholesky of Q_p (w = 0) or Q_c (w = 1) of instance I in its
+// elimination order.  Every block t other than the root is eliminated into
+// its successor (t+1 in chain A, t-1 in chain B): factor D_t, scale its
+// coupling block and arrow block by L_tt^-T, and subtract the Schur
+// complement from D_succ, R_succ and the tip.  The coupling of a chain-B
+// block t is Q(t-1, t) = B_{t-1}^T = B_{t-1}: the sub-diagonal blocks of
+// these models are symmetric (each is a weighted sum of symmetric FEM
+// matrices, the weights symmetric in the response pair), so chain B reads
+// the assembled B_{t-1} as it is.  Keys: major = position of the block in
+// its chain + 1 (0 is the prologue), the root one major after the longer
+// chain, 1 + nt_max for the tip.  The two chains' updates of the root block
+// fall in different launches because the chains differ in length.
 static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& q) {
   const ModelDev& m = I.m;
   const int bp = m.bp;
+  const int n = m.nt;
   const int64_t bb = (int64_t)bp * bp;
   const bool ring = (w == 0) && I.qp_ring;
   const int64_t ldbr = (w == 0) ? bp : I.ldbr;
@@ -587,18 +610,34 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
   double* P = (w == 0) ? I.Pp : I.Pc;
   double* logdiag = I.logdiag[w];
   int64_t* info = I.info2 + w;
+  const bool two = I.two;
+  const int mid = I.mid;
+  const int lenA = mid, lenB = n - 1 - mid;
+  const uint64_t root_major = (uint64_t)std::max(lenA, lenB) + 1;
   q.push_back(misc_step(K(0, 0), DL_CAT_OTHER, MJ_ZERO_I64, (double*)info, nullptr, 1));
-  // storage maps
-  std::vector<int> slot(m.nt + 1);
-  for (int t = 0; t <= m.nt; ++t) slot[t] = t;
-  int spare = m.nt;
+  if (two && apr)
+    q.push_back(misc_step(K(0, 0), DL_CAT_OTHER, MJ_FILL, I.PcB, nullptr,
+                          (int64_t)m.ap * m.ap, 0.0));
+  const int eb = I.eb;
   double* Dbase = (w == 0) ? I.Dp : I.Dc;
   double* Bbase = (w == 0) ? I.Bp : I.BRc;
-  auto Dt = [&](int t) { return Dbase + (ring ? (int64_t)(t % 2) : (int64_t)t) * bb; };
-  const int eb = I.eb;
   auto BRs = [&](int sl) { return eoff(Bbase, (int64_t)sl * ldbr * bp, eb); };
   auto BRo = [&](int sl, int rows) { return eoff(Bbase, (int64_t)sl * ldbr * bp + rows, eb); };
-  auto asm_qp = [&](int t, uint64_t key) {
+  // full storage: slot of [B_t; R_t] per block, one spare slot per chain
+  std::vector<int> slot(n + 2);
+  for (int t = 0; t < n + 2; ++t) slot[t] = t;
+  int spare[2] = {n, n + 1};
+  // Q_p ring: diagonal slots 0,1 (chain A; the root too when one-sided),
+  // 2,3 (chain B), 4 (root, two-sided); coupling slots 0,1 assembled + 2
+  // scaled (chain A), 3,4 assembled + 5 scaled (chain B), 6 (the root's
+  // B_mid, read by chain B's last block)
+  auto Dt = [&](int t) -> double* {
+    if (!ring) return Dbase + (int64_t)t * bb;
+    if (!two || t < mid) return Dbase + (int64_t)(t % 2) * bb;
+    if (t == mid) return Dbase + 4 * bb;
+    return Dbase + (int64_t)(2 + t % 2) * bb;
+  };
+  auto asm_qp = [&](int t, double* D, double* B, uint64_t key) {
     Step s;
     s.key = key;
     s.kind = OP_ASM_COLS;
@@ -608,62 +647,100 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     s.asmj.coef = I.coef;
     s.asmj.t0 = t;
     s.asmj.nt = 1;
-    s.asmj.o.Dp = Dt(t);
-    s.asmj.o.Bp = BRs(t % 2);
+    s.asmj.o.Dp = D;
+    s.asmj.o.Bp = B;
     s.asmj.o.rhs = I.rhs;
     s.asmj.o.b32 = I.mixed ? 1 : 0;
     s.gx = bp;
     s.gy = 1;
     q.push_back(s);
   };
-  if (ring) asm_qp(0, K(0, 3));
+  if (ring) {
+    asm_qp(0, Dt(0), BRs(0), K(0, 3));
+    if (two) {
+      asm_qp(n - 1, Dt(n - 1), BRs(3 + (n - 1) % 2), K(0, 3));
+      asm_qp(mid, Dt(mid), BRs(6), K(0, 3));
+    }
+  }
   const bool count_inv = (w == 1) && W->sel;
   // split k of the FP64 products (FP32 launches drop the flag)
   const int xf = W->splitk ? F_SPLIT : 0;
-  for (int t = 0; t < m.nt; ++t) {
-    const uint64_t major = (uint64_t)t + 1;
-    const bool last = (t + 1 == m.nt);
-    if (ring && !last) asm_qp(t + 1, K(major, 0));
+  const int x64 = I.mixed ? F_B64 : 0;
+  const int c64 = I.mixed ? F_C64 : 0;
+  auto gs = [&](uint64_t key, int cat, double fl, std::vector<GemmTask> ts) {
+    return I.mixed ? gemm32_step(key, cat, fl, std::move(ts))
+                   : gemm_step(key, cat, fl, std::move(ts));
+  };
+  // chain 0: A, 1: B, 2: root
+  auto eliminate = [&](int t, uint64_t major, int chain) {
+    const bool root = chain == 2;
+    const int succ = chain == 0 ? t + 1 : t - 1;
+    if (ring) {
+      if (chain == 0 && t + 1 < (two ? mid : n))
+        asm_qp(t + 1, Dt(t + 1), BRs((t + 1) % 2), K(major, 0));
+      if (chain == 1 && t - 1 > mid)
+        asm_qp(t - 1, Dt(t - 1), BRs(3 + (t - 1) % 2), K(major, 0));
+    }
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
               (int64_t)t * m.b, m.b);
-    seq_trtri(q, major, Dt(t), bp, bp, I.ttemp[w], count_inv ? m.b : 0, xf);
-    const int rows_lo = last ? bp : 0;
-    const int M = (last ? 0 : bp) + apr;
-    if (M <= 0) continue;
-    int src = ring ? (t % 2) : slot[t];
-    int nw = ring ? 2 : spare;
+    seq_trtri(q, major, Dt(t), bp, bp, chain == 1 ? I.ttempB[w] : I.ttemp[w],
+              count_inv ? m.b : 0, xf);
+    const int M = (root ? 0 : bp) + apr;
+    if (M <= 0) return;
     const double b = m.b, ar = apr ? m.a : 0;
-    const double mreal = (last ? 0.0 : b) + ar;
-    // [B_t; R_t] <- [B_t; R_t] L_tt^{-T} = [B_t; R_t] G_t^T
-    const int x64 = I.mixed ? F_B64 : 0;
-    auto gs = [&](uint64_t key, int cat, double fl, std::vector<GemmTask> ts) {
-      return I.mixed ? gemm32_step(key, cat, fl, std::move(ts))
-                     : gemm_step(key, cat, fl, std::move(ts));
-    };
-    q.push_back(gs(K(major, 3), DL_CAT_TRSM, mreal * b * b,
-                   {mk(BRo(src, rows_lo), ldbr, Dt(t), bp, BRo(nw, rows_lo), ldbr, M, bp,
-                       bp, F_TB | F_KHI_COL | F_BETA0 | x64 | xf, 1.0, 0.0)}));
+    const double mreal = (root ? 0.0 : b) + ar;
+    const int ci = chain == 1 ? 1 : 0;
+    const int nw = ring ? (ci ? 5 : 2) : spare[ci];
+    // [C_t; R_t] <- [C_t; R_t] L_tt^{-T} = [C_t; R_t] G_t^T, C_t the coupling
+    const int fl = F_TB | F_KHI_COL | F_BETA0 | x64 | xf;
+    std::vector<GemmTask> tr;
+    if (chain == 1) {
+      const double* C = ring ? BRs(t - 1 == mid ? 6 : 3 + (t - 1) % 2) : BRs(slot[t - 1]);
+      tr.push_back(mk(C, ldbr, Dt(t), bp, BRs(nw), ldbr, bp, bp, bp, fl, 1.0, 0.0));
+      if (apr)
+        tr.push_back(mk(BRo(slot[t], bp), ldbr, Dt(t), bp, BRo(nw, bp), ldbr, apr, bp, bp,
+                        fl, 1.0, 0.0));
+    } else {
+      const int rows_lo = root ? bp : 0;
+      const int src = ring ? (t % 2) : slot[t];
+      tr.push_back(mk(BRo(src, rows_lo), ldbr, Dt(t), bp, BRo(nw, rows_lo), ldbr, M, bp,
+                      bp, fl, 1.0, 0.0));
+    }
+    q.push_back(gs(K(major, 3), DL_CAT_TRSM, mreal * b * b, std::move(tr)));
     if (!ring) {
-      spare = slot[t];
+      // the block's old slot is free: its coupling rows were read by this
+      // step (chain A, root) or by the previous step of chain B, its arrow
+      // rows by this step
+      const int old = slot[t];
       slot[t] = nw;
+      spare[ci] = old;
     }
     double* BRt = BRs(nw);
     double* RRt = BRo(nw, bp);
-    const int c64 = I.mixed ? F_C64 : 0;
+    double* Ptip = (chain == 1) ? I.PcB : P;
     std::vector<GemmTask> up;
-    if (!last) {
-      up.push_back(mk(BRt, ldbr, BRt, ldbr, Dt(t + 1), bp, bp, bp, bp,
+    if (!root) {
+      up.push_back(mk(BRt, ldbr, BRt, ldbr, Dt(succ), bp, bp, bp, bp,
                       F_TB | F_LOWER | c64 | xf, -1.0, 1.0));
       if (apr)
-        up.push_back(mk(RRt, ldbr, BRt, ldbr, BRo(slot[t + 1], bp), ldbr, apr, bp, bp,
+        up.push_back(mk(RRt, ldbr, BRt, ldbr, BRo(slot[succ], bp), ldbr, apr, bp, bp,
                         F_TB | xf, -1.0, 1.0));
     }
     if (apr)
-      up.push_back(mk(RRt, ldbr, RRt, ldbr, P, m.ap, apr, apr, bp,
+      up.push_back(mk(RRt, ldbr, RRt, ldbr, Ptip, m.ap, apr, apr, bp,
                       F_TB | F_LOWER | c64 | xf, -1.0, 1.0));
-    const double upd = (last ? 0.0 : b * b * b + 2.0 * ar * b * b) + ar * ar * b;
-    q.push_back(gs(K(major, 4), DL_CAT_UPDATE, upd, up));
+    const double upd = (root ? 0.0 : b * b * b + 2.0 * ar * b * b) + ar * ar * b;
+    q.push_back(gs(K(major, 4), DL_CAT_UPDATE, upd, std::move(up)));
+  };
+  for (int k = 0; k < std::max(lenA, lenB); ++k) {
+    const uint64_t major = (uint64_t)k + 1;
+    if (k < lenA) eliminate(k, major, 0);
+    if (k < lenB) eliminate(n - 1 - k, major, 1);
   }
+  eliminate(mid, root_major, 2);
+  if (two && apr)
+    q.push_back(misc_step(K(root_major, 5), DL_CAT_OTHER, MJ_AXPY, P, I.PcB,
+                          (int64_t)m.ap * m.ap));
   const uint64_t tail = (uint64_t)nt_max + 1;
   if (m.ap > 0) {
     Step s;
@@ -717,8 +794,14 @@ static Step gt_step(uint64_t key, GemvT g, double bytes) {
   return s;
 }
 
-// Forward and backward block substitution with the factor of Q_c:
-// L z = x (z overwrites x), then L^T mu = z.
+// Forward and backward block substitution with the factor of Q_c, in the
+// elimination order of the factor: L z = x (z overwrites x), then
+// L^T mu = z.  Forward, each block subtracts the coupling of the blocks
+// eliminated into it (its predecessor in the chain; both chains' last
+// blocks for the root) and applies G_t; the arrow rows accumulate into the
+// tip part (chain B into a tip accumulator of its own, added before the
+// tip solve).  Backward runs from the tip and the root outward:
+// mu_t = G_t^T (z_t - C_t^T mu_succ(t) - R_t^T mu_P).
 static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   const ModelDev& m = I.m;
   const int bp = m.bp, ap = m.ap;
@@ -735,56 +818,97 @@ static void seq_solve(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   double* xP = x + (int64_t)m.nt * bp;
   double* mu = I.mu;
   double* muP = mu + (int64_t)m.nt * bp;
-  double* part = I.gpart;
-  for (int t = 0; t < m.nt; ++t) {
-    double* xt = x + (int64_t)t * bp;
-    const uint64_t mj = (uint64_t)t + 1;
-    if (t > 0)
-      q.push_back(gn_step(K(mj, 0), {bp + ap, bp, BRs(t - 1), ldbr,
-                                     x + (int64_t)(t - 1) * bp, 0, -1.0, 1.0, bp, xt,
-                                     I.u, xP, xP, part, a32},
+  auto xt = [&](int t) { return x + (int64_t)t * bp; };
+  const int n = m.nt, mid = I.mid;
+  const int lenA = mid, lenB = n - 1 - mid;
+  const int steps = std::max(lenA, lenB);
+  const uint64_t root_major = (uint64_t)steps + 1;
+  // per chain (0: A and the root, 1: B): temporary, GEMV partial sums and
+  // tip accumulator
+  double* u[2] = {I.u, I.two ? I.uB : I.u};
+  double* part[2] = {I.gpart, I.two ? I.gpartB : I.gpart};
+  double* tipacc[2] = {xP, I.two ? I.xPB : xP};
+  if (I.two && ap > 0)
+    q.push_back(misc_step(K(0, 0), DL_CAT_SOLVE, MJ_FILL, I.xPB, nullptr, ap, 0.0));
+  auto fwd = [&](int t, uint64_t major, int chain) {
+    const int ci = chain == 1 ? 1 : 0;
+    int preds[2][2];
+    int np = 0;
+    if (chain == 0 && t > 0) { preds[np][0] = t - 1; preds[np][1] = 0; ++np; }
+    if (chain == 1 && t < n - 1) { preds[np][0] = t + 1; preds[np][1] = 1; ++np; }
+    if (chain == 2) {
+      if (lenA > 0) { preds[np][0] = mid - 1; preds[np][1] = 0; ++np; }
+      if (lenB > 0) { preds[np][0] = mid + 1; preds[np][1] = 1; ++np; }
+    }
+    const double* base = xt(t);
+    for (int k = 0; k < np; ++k) {
+      const int pb = preds[k][0], pc = preds[k][1];
+      q.push_back(gn_step(K(major, 0, 0, k), {bp + ap, bp, BRs(pb), ldbr, xt(pb), 0, -1.0,
+                                              1.0, bp, base, u[ci], tipacc[pc], tipacc[pc],
+                                              part[ci], a32},
                           8.0 * (b + a) * b));
-    q.push_back(gn_step(K(mj, 1), {bp, bp, G(t), bp, t > 0 ? I.u : xt, 1, 1.0, 0.0,
-                                   -1, nullptr, xt, nullptr, nullptr, part},
+      base = u[ci];
+    }
+    q.push_back(gn_step(K(major, 1), {bp, bp, G(t), bp, np > 0 ? u[ci] : xt(t), 1, 1.0,
+                                      0.0, -1, nullptr, xt(t), nullptr, nullptr, part[ci]},
                         4.0 * b * b));
+  };
+  for (int k = 0; k < steps; ++k) {
+    if (k < lenA) fwd(k, (uint64_t)k + 1, 0);
+    if (k < lenB) fwd(n - 1 - k, (uint64_t)k + 1, 1);
   }
-  const uint64_t mid = (uint64_t)nt_max + 1;
+  fwd(mid, root_major, 2);
+  const uint64_t tk = (uint64_t)nt_max + 1;
   if (ap > 0) {
-    q.push_back(gn_step(K(mid, 0), {ap, bp, BRo(m.nt - 1, bp), ldbr,
-                                    x + (int64_t)(m.nt - 1) * bp, 0, -1.0, 1.0, -1,
-                                    xP, xP, nullptr, nullptr, part, a32},
+    q.push_back(gn_step(K(tk, 0), {ap, bp, BRo(mid, bp), ldbr, xt(mid), 0, -1.0, 1.0, -1,
+                                   xP, xP, nullptr, nullptr, part[0], a32},
                         8.0 * a * b));
-    q.push_back(gn_step(K(mid, 1), {ap, ap, I.GPc, ap, xP, 1, 1.0, 0.0, -1, nullptr,
-                                    xP, nullptr, nullptr, part},
+    if (I.two)
+      q.push_back(misc_step(K(tk, 0, 0, 1), DL_CAT_SOLVE, MJ_AXPY, xP, I.xPB, ap));
+    q.push_back(gn_step(K(tk, 1), {ap, ap, I.GPc, ap, xP, 1, 1.0, 0.0, -1, nullptr,
+                                   xP, nullptr, nullptr, part[0]},
                         4.0 * a * a));
-    q.push_back(gt_step(K(mid, 2), {ap, ap, I.GPc, ap, xP, -1, nullptr, 1, 1.0, 0.0,
-                                    nullptr, muP},
+    q.push_back(gt_step(K(tk, 2), {ap, ap, I.GPc, ap, xP, -1, nullptr, 1, 1.0, 0.0,
+                                   nullptr, muP},
                         4.0 * a * a));
   }
-  for (int t = m.nt - 1; t >= 0; --t) {
-    double* xt = x + (int64_t)t * bp;
-    const uint64_t mj = mid + 1 + (uint64_t)(m.nt - 1 - t);
-    if (t == m.nt - 1) {
+  auto bwd = [&](int t, uint64_t major, int chain) {
+    const int ci = chain == 1 ? 1 : 0;
+    if (chain == 2) {
       if (ap > 0)
-        q.push_back(gt_step(K(mj, 0), {ap, bp, BRo(t, bp), ldbr, muP, -1, nullptr, 0,
-                                       -1.0, 1.0, xt, I.u, a32},
+        q.push_back(gt_step(K(major, 0), {ap, bp, BRo(t, bp), ldbr, muP, -1, nullptr, 0,
+                                          -1.0, 1.0, xt(t), u[0], a32},
                             8.0 * a * b));
       else
-        q.push_back(misc_step(K(mj, 0), DL_CAT_SOLVE, MJ_COPY, I.u, xt, bp));
+        q.push_back(misc_step(K(major, 0), DL_CAT_SOLVE, MJ_COPY, u[0], xt(t), bp));
     } else {
-      q.push_back(gt_step(K(mj, 0), {bp + ap, bp, BRs(t), ldbr,
-                                     mu + (int64_t)(t + 1) * bp, bp, muP, 0, -1.0, 1.0,
-                                     xt, I.u, a32},
+      const int succ = chain == 0 ? t + 1 : t - 1;
+      q.push_back(gt_step(K(major, 0), {bp + ap, bp, BRs(t), ldbr,
+                                        mu + (int64_t)succ * bp, bp, muP, 0, -1.0, 1.0,
+                                        xt(t), u[ci], a32},
                           8.0 * (b + a) * b));
     }
-    q.push_back(gt_step(K(mj, 1), {bp, bp, G(t), bp, I.u, -1, nullptr, 1, 1.0, 0.0,
-                                   nullptr, mu + (int64_t)t * bp},
+    q.push_back(gt_step(K(major, 1), {bp, bp, G(t), bp, u[ci], -1, nullptr, 1, 1.0, 0.0,
+                                      nullptr, mu + (int64_t)t * bp},
                         4.0 * b * b));
+  };
+  bwd(mid, tk + 1, 2);
+  for (int k = 0; k < steps; ++k) {
+    const uint64_t major = tk + 2 + (uint64_t)k;
+    if (k < lenA) bwd(mid - 1 - k, major, 0);
+    if (k < lenB) bwd(mid + 1 + k, major, 1);
   }
 }
 
-// Takahashi selected inversion of Q_c, backward in time, from the factor's
-// off-diagonal blocks and the diagonal-block inverses G_t.
+// Takahashi selected inversion of Q_c from the factor's off-diagonal blocks
+// and the diagonal-block inverses G_t, in the reverse of the elimination
+// order: the root block first, then each chain outward.  Block t needs the
+// inverse entries of its successor s (the block it was eliminated into):
+//   [X_{s,t}; X_{P,t}] = -[[X_{s,s}, X_{s,P}]; [X_{P,s}, X_P]] [W_t; V_t],
+//   X_tt = G_t^T G_t - [X_{s,t}; X_{P,t}]^T [W_t; V_t],
+// [W_t; V_t] = [C_t; R_t]_factor G_t (the root has no coupling rows).  Each
+// chain keeps the current [X_{s,s}, X_{s,P}; X_{P,s}, X_P] in a pair of
+// ping-pong buffers; chain B starts from the root's buffer of chain A.
 static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   const ModelDev& m = I.m;
   const int bp = m.bp, ap = m.ap;
@@ -803,17 +927,24 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
   };
   const int fB64 = mx ? F_B64 : 0, fA64 = mx ? F_A64 : 0, fC64 = mx ? F_C64 : 0;
   const int xf = W->splitk ? F_SPLIT : 0;  // dropped by FP32 launches
+  const int n = m.nt, mid = I.mid;
+  const int lenA = mid, lenB = n - 1 - mid;
+  const int nch = I.two ? 2 : 1;
+  double* XCc[2][2] = {{I.XC[0], I.XC[1]}, {I.XCB[0], I.XCB[1]}};
+  double* Yc[2] = {I.Y, I.YB};
   // [W_t; V_t] of every step, eb bytes per element, ld x bp each
   auto WVt = [&](int t) { return eoff(I.WV, (int64_t)t * ld * bp, eb); };
-  for (int k = 0; k < 2; ++k)
-    q.push_back(misc_step(K(0, 0, 0, k), DL_CAT_SELINV, MJ_FILL, I.XC[k], nullptr,
-                          ld * ld, 0.0));
-  if (ap > 0) {
-    // X_P = G_P^T G_P into the corner of both ping-pong buffers
-    std::vector<GemmTask> xp;
+  for (int c = 0; c < nch; ++c)
     for (int k = 0; k < 2; ++k)
-      xp.push_back(mk(I.GPc, ap, I.GPc, ap, I.XC[k] + bp + (int64_t)bp * ld, ld, ap,
-                      ap, ap, F_TA | F_BETA0, 1.0, 0.0));
+      q.push_back(misc_step(K(0, 0, 0, 2 * c + k), DL_CAT_SELINV, MJ_FILL, XCc[c][k],
+                            nullptr, ld * ld, 0.0));
+  if (ap > 0) {
+    // X_P = G_P^T G_P into the corner of every ping-pong buffer
+    std::vector<GemmTask> xp;
+    for (int c = 0; c < nch; ++c)
+      for (int k = 0; k < 2; ++k)
+        xp.push_back(mk(I.GPc, ap, I.GPc, ap, XCc[c][k] + bp + (int64_t)bp * ld, ld, ap,
+                        ap, ap, F_TA | F_BETA0, 1.0, 0.0));
     q.push_back(gemm_step(K(0, 1), DL_CAT_SELINV, 2.0 * a * a * a, xp));
     Step dg = misc_step(K(0, 2), DL_CAT_SELINV, MJ_DIAG,
                         I.selout + (int64_t)m.nt * bp, I.XC[0] + bp + (int64_t)bp * ld,
@@ -821,17 +952,16 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     dg.misc.lds = ld;
     q.push_back(dg);
   }
-  // [W_t; V_t] = [B_t; R_t]_factor G_t for all t: independent of the
-  // recursion, so one launch (the last step has only the arrow rows; its
-  // W block is zero)
+  // [W_t; V_t] = [C_t; R_t]_factor G_t for all t: independent of the
+  // recursion, so one launch (the root has only the arrow rows; its W block
+  // is zero)
   {
-    const int tl = m.nt - 1;
-    q.push_back(misc_step(K(0, 3), DL_CAT_SELINV, MJ_FILL, WVt(tl), nullptr,
+    q.push_back(misc_step(K(0, 3), DL_CAT_SELINV, MJ_FILL, WVt(mid), nullptr,
                           ld * bp * eb / 8));
     std::vector<GemmTask> wv;
     double fl = 0.0;
     for (int t = 0; t < m.nt; ++t) {
-      if (t == tl) {
+      if (t == mid) {
         if (ap > 0) {
           wv.push_back(mk(BRo(t, bp), ld, G(t), bp, eoff(WVt(t), bp, eb), ld, ap, bp, bp,
                           F_KLO_COL | F_BETA0 | fB64 | xf, 1.0, 0.0));
@@ -845,39 +975,48 @@ static void seq_selinv(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
     }
     if (!wv.empty()) q.push_back(gs(K(0, 4), DL_CAT_SELINV, fl, wv));
   }
-  int cur = 0;
-  for (int t = m.nt - 1; t >= 0; --t) {
-    const uint64_t mj = 1 + (uint64_t)(m.nt - 1 - t);
-    const int nxt = cur ^ 1;
-    const bool last = (t + 1 == m.nt);
+  auto step = [&](int t, uint64_t mj, double* Xin, double* Xout, double* Y, bool root) {
     const double ba = b + a;
-    // [X_{t+1,t}; X_{P,t}] = -[[X_{t+1,t+1}, X_{t+1,P}]; [X_{P,t+1}, X_P]] WV
-    // and, independent of it (same launch when both run in FP64),
-    // X_tt = G_t^T G_t (lower triangle)
-    q.push_back(gs(K(mj, 2), DL_CAT_SELINV, last ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
-                   {mk(I.XC[cur], ld, WVt(t), ld, I.Y, ld, bp + ap, bp, bp + ap,
+    // [X_{s,t}; X_{P,t}] = -X(s) WV and, independent of it (same launch
+    // when both run in FP64), X_tt = G_t^T G_t (lower triangle)
+    q.push_back(gs(K(mj, 2), DL_CAT_SELINV, root ? 2.0 * a * ba * b : 2.0 * ba * ba * b,
+                   {mk(Xin, ld, WVt(t), ld, Y, ld, bp + ap, bp, bp + ap,
                        F_BETA0 | fA64 | fC64 | xf, -1.0, 0.0)}));
     q.push_back(gemm_step(K(mj, 2), DL_CAT_SELINV, b * b * b / 3.0,
-                          {mk(G(t), bp, G(t), bp, I.XC[nxt], ld, bp, bp, bp,
+                          {mk(G(t), bp, G(t), bp, Xout, ld, bp, bp, bp,
                               F_TA | F_KLO_ROW | F_KLO_COL | F_LOWER | F_BETA0 | xf, 1.0,
                               0.0)}));
     // X_tt -= Y^T WV   (lower triangle)
-    q.push_back(gs(K(mj, 4), DL_CAT_SELINV, last ? b * b * a : b * b * ba,
-                   {mk(I.Y, ld, WVt(t), ld, I.XC[nxt], ld, bp, bp, bp + ap,
+    q.push_back(gs(K(mj, 4), DL_CAT_SELINV, root ? b * b * a : b * b * ba,
+                   {mk(Y, ld, WVt(t), ld, Xout, ld, bp, bp, bp + ap,
                        F_TA | F_LOWER | fA64 | fC64 | xf, -1.0, 1.0)}));
     Step fin;
     fin.key = K(mj, 5);
     fin.kind = OP_FINISH;
     fin.cat = DL_CAT_SELINV;
-    fin.fin.XC = I.XC[nxt];
+    fin.fin.XC = Xout;
     fin.fin.ld = ld;
     fin.fin.bp = bp;
     fin.fin.ap = ap;
-    fin.fin.Y = I.Y;
+    fin.fin.Y = Y;
     fin.fin.out = I.selout + (int64_t)t * bp;
     fin.gx = bp;
     q.push_back(fin);
-    cur = nxt;
+  };
+  step(mid, 1, XCc[0][0], XCc[0][1], Yc[0], true);
+  int cur[2] = {1, -1};  // chain B reads the root's buffer first
+  for (int k = 0; k < std::max(lenA, lenB); ++k) {
+    const uint64_t mj = 2 + (uint64_t)k;
+    if (k < lenA) {
+      step(mid - 1 - k, mj, XCc[0][cur[0]], XCc[0][cur[0] ^ 1], Yc[0], false);
+      cur[0] ^= 1;
+    }
+    if (k < lenB) {
+      double* in = (k == 0) ? XCc[0][1] : XCc[1][cur[1]];
+      const int out = (k == 0) ? 0 : (cur[1] ^ 1);
+      step(mid + 1 + k, mj, in, XCc[1][out], Yc[1], false);
+      cur[1] = out;
+    }
   }
 }
 
@@ -1087,6 +1226,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->mixed = (flags & DL_WS_MIXED) != 0;
   W->use_graph = (flags & DL_WS_GRAPH) != 0;
   W->splitk = (flags & DL_WS_SPLITK) != 0;
+  const bool two_sided = (flags & DL_WS_TWOSIDED) != 0;
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
   auto A = [&](size_t bytes, void** p) {
@@ -1107,16 +1247,20 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     I.ldbr = bp + ap;
     I.mixed = W->mixed;
     I.eb = I.mixed ? 4 : 8;
+    // two chains need at least one block each besides the root
+    I.two = two_sided && m.nt >= 4;
+    I.mid = I.two ? (m.nt + 1) / 2 : m.nt - 1;
+    const int xs = I.two ? 1 : 0;  // extra spare slot of chain B
     const size_t eb = I.eb;
     if (I.qp_ring) {
-      A(sizeof(double) * 2 * bb, (void**)&I.Dp);
-      A(eb * 3 * bb, (void**)&I.Bp);
+      A(sizeof(double) * (I.two ? 5 : 2) * bb, (void**)&I.Dp);
+      A(eb * (I.two ? 7 : 3) * bb, (void**)&I.Bp);
     } else {
       A(sizeof(double) * m.nt * bb, (void**)&I.Dp);
-      A(eb * (m.nt + 1) * bb, (void**)&I.Bp);
+      A(eb * (m.nt + 1 + xs) * bb, (void**)&I.Bp);
     }
     A(sizeof(double) * m.nt * bb, (void**)&I.Dc);
-    A(eb * (m.nt + 1) * I.ldbr * bp, (void**)&I.BRc);
+    A(eb * (m.nt + 1 + xs) * I.ldbr * bp, (void**)&I.BRc);
     A(sizeof(double) * m.Np, (void**)&I.mu_acc);
     A(sizeof(double) * (m.m_total + 1), (void**)&I.av);
     A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.rpart);
@@ -1142,6 +1286,14 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(sizeof(double) * m.Np, (void**)&I.mu);
     A(sizeof(double) * I.ldbr, (void**)&I.u);
     A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
+    if (I.two) {
+      A(tip, (void**)&I.PcB);
+      for (int w = 0; w < 2; ++w)
+        A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttempB[w]);
+      A(sizeof(double) * I.ldbr, (void**)&I.uB);
+      A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpartB);
+      A(sizeof(double) * (ap > 0 ? ap : 1), (void**)&I.xPB);
+    }
     if (W->sel) {
       // [W_t; V_t] = [B_t; R_t] G_t of every time step (formed up front)
       A((size_t)I.eb * m.nt * I.ldbr * bp, (void**)&I.WV);
@@ -1149,6 +1301,11 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
       A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[0]);
       A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[1]);
       A(sizeof(double) * m.Np, (void**)&I.selout);
+      if (I.two) {
+        A(sizeof(double) * I.ldbr * bp, (void**)&I.YB);
+        A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[0]);
+        A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[1]);
+      }
     }
   }
   W->dim_total = dim_total;

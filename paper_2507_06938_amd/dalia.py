@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libdalia_hip.so")
 DL_QP, DL_QC, DL_BOTH = 0, 1, 2
 DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH, DL_WS_MIXED = 1, 2, 4, 8
 DL_WS_SPLITK = 16
+DL_WS_TWOSIDED = 32
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
@@ -189,14 +190,16 @@ class Workspace:
     together.  Per-instance vectors are packed in instance order."""
 
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
-                 graph: bool = False, mixed: bool = False, splitk: bool = False):
+                 graph: bool = False, mixed: bool = False, splitk: bool = False,
+                 two_sided: bool = False):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
         self.model = self.models[0]
         flags = ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
                  | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
-                 | (DL_WS_SPLITK if splitk else 0))
+                 | (DL_WS_SPLITK if splitk else 0)
+                 | (DL_WS_TWOSIDED if two_sided else 0))
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
         _check("dl_ws_create_batch",
