@@ -140,8 +140,12 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
 //     A(I, J) -= L(I, j) L(J, j)^T,   L(., j) = P_j G_jj^T
 // (L formed in the workgroup, not stored), and in the same launch factors
 // the updated diagonal tile j+1 (mode 1, logdiag, info).  The panels are
-// solved afterwards, all at once (L(I, k) = P_k(I) G_kk^T).  One workgroup
-// per tile; the tiles that factor are numbered first.
+// solved afterwards, all at once (L(I, k) = P_k(I) G_kk^T).  With `solved`
+// set, panel j already holds L(., j) (solved in place by a launch before
+// this one) and the workgroups read it instead of forming it: one tile
+// product per tile instead of three, for the panels whose trailing grid is
+// large enough that the work, not the factor path, sets the launch time.
+// One workgroup per tile; the tiles that factor are numbered first.
 struct PanelTask {
   double* A;
   int64_t ld;
@@ -152,6 +156,8 @@ struct PanelTask {
   int32_t tile_begin;  // first non-factor workgroup of this task (after the
                        // count factor workgroups of the launch)
   int32_t ntiles;      // lower tiles of the trailing grid, factor tile included
+  int32_t solved;      // panel j holds L(., j)
+  int32_t pad_;
 };
 // Fill tile_begin/ntiles; return the grid size.
 int finalize_panels(PanelTask* t, int n);

@@ -235,6 +235,8 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   const int p0 = 16 * (wv >> 2), q0 = 16 * (wv & 3);  // this wave's 16 x 16 block
   double* C = T.A + ti0 + tj0 * T.ld;
   constexpr int PER = NB * NB / POTRF_NT;
+  // panel tiles (I, j) and (J, j): P or, when solved, L; S0[c][m] = X(m, c)
+  const bool solved = T.solved != 0;
   double vp[PER], vg[PER], vq[PER], cpre[4];
   {
     const double* Pi = T.A + ti0 + pc;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
       const int idx = threadIdx.x + e * POTRF_NT;
       const int64_t o = (idx & 63) + (int64_t)(idx >> 6) * T.ld;
       vp[e] = Pi[o];
-      vg[e] = Gj[o];
+      vg[e] = solved ? 0.0 : Gj[o];
       vq[e] = (I != J) ? Pj[o] : 0.0;
     }
 #pragma unroll
@@ -255,23 +257,25 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
       const int idx = threadIdx.x + e * POTRF_NT;
       const int o = (idx >> 6) * LDL + (idx & 63);
       S0[o] = vp[e];
-      S1[o] = vg[e];
+      if (!solved) S1[o] = vg[e];
       if (I != J) S2[o] = vq[e];
     }
   }
   __syncthreads();
-  // L^T = G P^T: D[c][m] = sum_k G(c, k) P(m, k), k <= c < p0 + 16
-  v4d a0 = {0.0, 0.0, 0.0, 0.0}, b0 = {0.0, 0.0, 0.0, 0.0};
-  mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L_I(m = q0 + lr, c = p0 + lk + 4r)
-  if (I != J) mfma1_k64(S1, p0, S2, q0, b0, p0 + 16);
-  __syncthreads();
+  if (!solved) {
+    // L^T = G P^T: D[c][m] = sum_k G(c, k) P(m, k), k <= c < p0 + 16
+    v4d a0 = {0.0, 0.0, 0.0, 0.0}, b0 = {0.0, 0.0, 0.0, 0.0};
+    mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L_I(m = q0 + lr, c = p0 + lk + 4r)
+    if (I != J) mfma1_k64(S1, p0, S2, q0, b0, p0 + 16);
+    __syncthreads();
 #pragma unroll
-  for (int rg = 0; rg < 4; ++rg) {
-    const int c = p0 + lk + 4 * rg;
-    S0[c * LDL + q0 + lr] = a0[rg];
-    if (I != J) S2[c * LDL + q0 + lr] = b0[rg];
+    for (int rg = 0; rg < 4; ++rg) {
+      const int c = p0 + lk + 4 * rg;
+      S0[c * LDL + q0 + lr] = a0[rg];
+      if (I != J) S2[c * LDL + q0 + lr] = b0[rg];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // (L_I L_J^T)^T = L_J L_I^T: D[n][m] = sum_c L_J(n, c) L_I(m, c)
   const double* LJ = (I != J) ? S2 : S0;
   v4d u0 = {0.0, 0.0, 0.0, 0.0};

@@ -240,18 +240,27 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
   return s;
 }
 
+// Panels whose trailing grid has at least this many tile rows are solved
+// in place by a GEMM launch before their trailing update (the update then
+// does one tile product per tile instead of forming L in every tile).
+constexpr int PANEL_SOLVE_MIN_ROWS = 16;
+
 // Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
 // panels of 64 columns.  Diagonal tiles are overwritten by their inverses
 // G_jj (they are used only through them).  Tile 0 is factored alone; step j
-// then updates the trailing tiles with L(., j) = P_j G_jj^T formed from the
-// unsolved panel j and factors tile j+1 in the same launch; finally all
-// panels are solved in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`: unpadded size (operation
-// count).  Keys (major, group 1, j, sub): (0, 0) tile 0, (j, 1) step j,
-// (255, 0) the panel solves.
+// then updates the trailing tiles with L(., j) = P_j G_jj^T and factors tile
+// j+1 in the same launch.  L(., j) is formed inside each tile from the
+// unsolved panel for small trailing grids, and solved in place by a GEMM
+// launch just before the step for large ones; the panels left unsolved are
+// solved at the end in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`:
+// unpadded size (operation count).  Keys (major, group 1, j, sub): (0, 0)
+// tile 0, (j, 1) the in-place solve of panel j, (j, 2) step j, (255, 0) the
+// remaining panel solves.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
                       int breal) {
   const int nbk = n / 64;
+  auto early = [&](int j) { return nbk - j - 1 >= PANEL_SOLVE_MIN_ROWS; };
   auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
   auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
   {
@@ -271,8 +280,15 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
   }
   for (int j = 0; j + 1 < nbk; ++j) {
     const double w = width(j), w1 = width(j + 1), bl = below(j);
+    if (early(j)) {
+      double* Ajj = A + (int64_t)j * 64 * (ld + 1);
+      double* panel = Ajj + 64;
+      q.push_back(gemm_step(K(major, 1, j, 1), DL_CAT_PANEL_TRSM, bl * w * w,
+                            {mk(panel, ld, Ajj, ld, panel, ld, n - (j + 1) * 64, 64, 64,
+                                F_TB | F_BETA0, 1.0, 0.0)}));
+    }
     Step s;
-    s.key = K(major, 1, j, 1);
+    s.key = K(major, 1, j, 2);
     s.kind = OP_PANEL;
     s.cat = DL_CAT_PANEL_SYRK;
     // the trailing update of a right-looking Cholesky plus the tile factor
@@ -285,12 +301,14 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     t.row0 = row0 + (int64_t)(j + 1) * 64;
     t.j = j;
     t.nbk = nbk;
+    t.solved = early(j) ? 1 : 0;
     q.push_back(s);
   }
   if (nbk > 1) {
     std::vector<GemmTask> ts;
     double fl = 0.0;
     for (int j = 0; j + 1 < nbk; ++j) {
+      if (early(j)) continue;
       const int rows = n - (j + 1) * 64;
       double* Ajj = A + (int64_t)j * 64 * (ld + 1);
       double* panel = Ajj + 64;

@@ -55,6 +55,9 @@ CASES = {
     "no_fixed": lambda: W.scaled("nof", 6, 4, 1, 0, 60, seed=10),
     "bivariate": lambda: W.scaled("bi", 6, 3, 2, 1, 40, seed=11),
     "multi_tile": lambda: W.scaled("mt", 12, 3, 1, 2, 300, seed=12),
+    # b = 1156: 19 tiles per block, so the first panels of every diagonal
+    # block are solved in place before their trailing update
+    "solved_panels": lambda: W.scaled("sp", 34, 4, 1, 2, 800, seed=18),
     # non-separable diffusion-based model: 25-point spatial stencil, the
     # fourth FEM piece, nt = 2 (both steps are end steps) and ragged tiles
     "diff_uni": lambda: W.scaled("du", 7, 5, 1, 2, 80, seed=13, model="diffusion"),

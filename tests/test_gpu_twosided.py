@@ -45,6 +45,7 @@ CASES = {
     "no_fixed_nt6": lambda: W.scaled("nof", 6, 6, 1, 0, 60, seed=10),
     "diff_uni_nt5": lambda: W.scaled("du", 7, 5, 1, 2, 80, seed=13, model="diffusion"),
     "diff_tri_nt6": lambda: W.scaled("dt", 5, 6, 3, 2, 40, seed=15, model="diffusion"),
+    "solved_panels_nt4": lambda: W.scaled("sp", 34, 4, 1, 2, 800, seed=18),
 }
 
 

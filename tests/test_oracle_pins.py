@@ -279,3 +279,23 @@ def test_generator_is_deterministic():
     r = a.responses[0]
     np.testing.assert_allclose(r.w.sum(axis=1), 1.0, atol=1e-15)
     assert np.bincount(r.t).tolist() == [40] * 10
+
+
+@pytest.mark.parametrize("model", ["separable", "diffusion"])
+@pytest.mark.parametrize("nv", [1, 3])
+def test_sub_diagonal_blocks_are_symmetric(nv, model):
+    """Q(t+1, t) = Q(t, t+1) for every pair of neighbouring time steps, in
+    Q_p and Q_c: the coupling blocks are weighted sums of symmetric spatial
+    FEM matrices with weights symmetric in the response pair (Eq. 11), and
+    observations couple only one time step.  Eliminating the second half of
+    the time domain backward uses the assembled B_t as Q(t, t+1)."""
+    wl = W.scaled("sym", 5, 4, nv, 2, 40, seed=3, model=model)
+    th = wl.theta + 0.1 * np.cos(np.arange(wl.dim_theta))
+    perm = M.bta_permutation(nv, wl.ns, wl.nt, wl.nr)
+    b = wl.b
+    for Q in (M.prior_precision(wl, th), M.conditional_precision(wl, th)):
+        Qb = Q[perm][:, perm].toarray()
+        for t in range(wl.nt - 1):
+            B = Qb[(t + 1) * b:(t + 2) * b, t * b:(t + 1) * b]
+            assert np.abs(B).max() > 0
+            np.testing.assert_allclose(B, B.T, rtol=0, atol=1e-13 * np.abs(B).max())
