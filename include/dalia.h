@@ -361,6 +361,11 @@ dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
 dl_status dl_ws_profile_end(dl_ws* ws, double* ms_by_cat,
                             int64_t* launches_by_cat, double* flops_by_cat,
                             double* bytes_by_cat);
+/* Pause (on = 0) or resume (on != 0) the recording started by
+ * dl_ws_profile_begin without touching its event pool, so that a caller can
+ * bracket the launches of chosen calls only (each pair of events costs a
+ * few microseconds of stream time).  Recording starts resumed. */
+dl_status dl_ws_profile_enable(dl_ws* ws, int32_t on);
 
 const char* dl_status_string(dl_status s);
 

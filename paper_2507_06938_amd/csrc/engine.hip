@@ -441,7 +441,7 @@ struct dl_ws {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool use_graph = false;
   // launch profiling (measurement only)
-  int prof_mask = 0, prof_by_kernel = 0, prof_used = 0;
+  int prof_mask = 0, prof_by_kernel = 0, prof_used = 0, prof_paused = 0;
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_cat;
   std::vector<double> prof_flops, prof_bytes;
@@ -468,7 +468,7 @@ static dl_status ensure_partials(dl_ws* W, int64_t elems, hipStream_t s) {
 }
 
 static int prof_begin(dl_ws* W, int cat, int kind, hipStream_t s) {
-  if (!W->prof_mask || !((W->prof_mask >> cat) & 1)) return -1;
+  if (!W->prof_mask || W->prof_paused || !((W->prof_mask >> cat) & 1)) return -1;
   if (W->prof_used >= (int)W->prof_cat.size()) return -1;
   const int k = W->prof_used++;
   if (hipEventRecord(W->prof_ev[2 * k], s) != hipSuccess) return -1;
@@ -1657,6 +1657,13 @@ extern "C" dl_status dl_ws_profile_begin(dl_ws* W, int32_t mask, int32_t max_lau
   W->prof_flops.assign(max_launches, 0.0);
   W->prof_bytes.assign(max_launches, 0.0);
   W->prof_mask = mask & 0xffff;
+  W->prof_paused = 0;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_profile_enable(dl_ws* W, int32_t on) {
+  if (!W) return DL_EINVAL;
+  W->prof_paused = on ? 0 : 1;
   return DL_OK;
 }
 

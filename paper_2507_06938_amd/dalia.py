@@ -100,6 +100,7 @@ def lib():
             "mlp_mse_grad": (i32, [vp, vp, i32, vp, vp, vp]),
             "mlp_adam": (i32, [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
             "dl_ws_profile_end": (i32, [vp, vp, vp, vp, vp]),
+            "dl_ws_profile_enable": (i32, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -333,6 +334,10 @@ class Workspace:
             mask |= 1 << 16
         _check("dl_ws_profile_begin",
                lib().dl_ws_profile_begin(self.h, mask, int(max_launches)))
+
+    def profile_enable(self, on: bool):
+        """Pause or resume the recording of profile_begin (no allocation)."""
+        _check("dl_ws_profile_enable", lib().dl_ws_profile_enable(self.h, 1 if on else 0))
 
     def profile_end(self) -> dict:
         n = len(CATEGORIES)
