@@ -214,3 +214,78 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(W, [[1.0 - 0.01 * 0.3 / (0.3 + 1e-8),
                                     -2.0 + 0.01 * 4.0 / (4.0 + 1e-8)]], rtol=1e-14)
     np.testing.assert_allclose(b, [0.5 - 0.01 * 1e-3 / (1e-3 + 1e-8)], rtol=1e-14)
+
+
+# ---- eigenvector reparametrisation of the hyperparameter marginals ----------------
+
+def _random_negdef(d, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    lam = rng.uniform(0.5, 4.0, d)
+    return -(Q * lam) @ Q.T, Q, lam
+
+
+def test_skew_correction_of_a_quadratic_is_gaussian():
+    """f quadratic: every axis drops by delta^2/2, so sigma^+- = 1, the points
+    lie at Mahalanobis distance delta under -H, and the asymmetric standard
+    deviations are the Gaussian marginal ones on both sides."""
+    d = 5
+    H, _, _ = _random_negdef(d, 3)
+    x0 = np.linspace(-1.0, 1.0, d)
+    f = lambda t: 7.0 + 0.5 * (t - x0) @ H @ (t - x0)
+    A = OH.eigen_axes(H)
+    for delta in (1.0, 0.5):
+        pts = OH.skew_points(x0, A, delta)
+        for p in pts:
+            assert abs((p - x0) @ (-H) @ (p - x0) - delta ** 2) < 1e-12
+        sp, sm = OH.skew_scales(f(x0), [f(p) for p in pts], delta)
+        np.testing.assert_allclose(sp, 1.0, rtol=1e-12)
+        np.testing.assert_allclose(sm, 1.0, rtol=1e-12)
+        up, dn = OH.asymmetric_sd(A, sp, sm)
+        want = np.sqrt(np.diag(np.linalg.inv(-H)))
+        np.testing.assert_allclose(up, want, rtol=1e-12)
+        np.testing.assert_allclose(dn, want, rtol=1e-12)
+
+
+def test_skew_correction_recovers_split_normal_scales():
+    """f the log density of independent split normals along the axes of a
+    known -H (scale s+ on the positive side, s- on the negative side): the
+    correction returns exactly those scales, axis by axis (eigen_axes may
+    order and orient the axes differently: matched by direction)."""
+    d = 4
+    H, Q, lam = _random_negdef(d, 8)
+    rng = np.random.default_rng(9)
+    s_plus = rng.uniform(0.5, 2.0, d)
+    s_minus = rng.uniform(0.5, 2.0, d)
+    x0 = rng.standard_normal(d)
+
+    def f(t):
+        z = np.sqrt(lam) * (Q.T @ (t - x0))   # coordinates with -H = Q lam Q^T
+        s = np.where(z >= 0.0, s_plus, s_minus)
+        return -0.5 * np.sum((z / s) ** 2)
+
+    A = OH.eigen_axes(H)
+    pts = OH.skew_points(x0, A, 1.0)
+    sp, sm = OH.skew_scales(f(x0), [f(p) for p in pts], 1.0)
+    V = A * np.sqrt(np.linalg.eigvalsh(-H))[None, :]     # unit eigenvectors
+    for k in range(d):
+        dots = Q.T @ V[:, k]
+        j = int(np.argmax(np.abs(dots)))
+        assert abs(abs(dots[j]) - 1.0) < 1e-10
+        want_p, want_m = (s_plus[j], s_minus[j]) if dots[j] > 0 else (s_minus[j], s_plus[j])
+        assert abs(sp[k] - want_p) < 1e-10 and abs(sm[k] - want_m) < 1e-10
+
+
+def test_skew_correction_in_one_dimension_is_the_split_normal():
+    """d = 1: theta = theta* + a z with z split normal; the upper and lower
+    standard deviations of theta are a s+ and a s-."""
+    a, s_plus, s_minus, x0 = 0.7, 1.6, 0.6, 0.3
+    H = np.array([[-1.0 / a ** 2]])
+    f = lambda t: -0.5 * (((t[0] - x0) / a) / (s_plus if t[0] >= x0 else s_minus)) ** 2
+    A = OH.eigen_axes(H)
+    pts = OH.skew_points(np.array([x0]), A, 1.0)
+    sp, sm = OH.skew_scales(f(np.array([x0])), [f(p) for p in pts], 1.0)
+    up, dn = OH.asymmetric_sd(A, sp, sm)
+    assert abs(up[0] - a * s_plus) < 1e-12 and abs(dn[0] - a * s_minus) < 1e-12
+    with pytest.raises(ValueError):
+        OH.skew_scales(0.0, [0.5, -1.0], 1.0)     # f rises: not a mode
