@@ -10,6 +10,15 @@ passes of the library (a workspace of `batch` instances, the last pass
 padded).  The Gaussian approximation of the marginals has covariance
 (-H)^{-1} at the mode.
 
+Skewed marginals (the eigenvector reparametrisation the paper cites from
+Martins et al., 2013): in the coordinates z with theta = theta* + A z,
+A = V diag(lambda)^{-1/2} for -H = V diag(lambda) V^T, the Gaussian
+approximation is standard; f_obj at z = +-delta e_k (2 d more values, one
+batched pass for d <= batch/2) gives each axis a scale per side,
+delta / sqrt(2 (f(theta*) - f)), 1 for an exactly Gaussian posterior, and
+the upper (lower) standard deviation of theta_j sums A_jk^2 times the
+squared scale of the side of axis k that raises (lowers) theta_j.
+
 Host-side logic only; every f_obj value comes from the library's kernels.
 
     python -m paper_2507_06938_amd.hessian [c1|c2] [--batch B]
@@ -63,23 +72,70 @@ def second_differences(f: np.ndarray, d: int, h: float) -> np.ndarray:
     return H
 
 
-def fobj_hessian(ws, theta: np.ndarray, h: float = 1e-3):
-    """(H, f(theta), values) of f_obj at theta from batched passes of the
-    workspace `ws` (all instances of one model); values: f_obj at the
-    stencil points."""
+def batched_values(ws, pts: np.ndarray) -> np.ndarray:
+    """f_obj at the rows of pts in passes of the workspace `ws` (all
+    instances of one model; the last pass padded with copies of its first
+    point)."""
     import torch
-    pts = stencil_points(theta, h)
     B = ws.B
     vals = np.empty(pts.shape[0])
     for k0 in range(0, pts.shape[0], B):
         chunk = pts[k0:k0 + B]
         n = chunk.shape[0]
-        if n < B:  # pad the last pass with copies of its first point
+        if n < B:
             chunk = np.concatenate([chunk, np.repeat(chunk[:1], B - n, axis=0)])
         f, _, info = ws.fobj(chunk)
         vals[k0:k0 + n] = f.cpu().numpy()[:n]
     torch.cuda.synchronize()
+    return vals
+
+
+def fobj_hessian(ws, theta: np.ndarray, h: float = 1e-3):
+    """(H, f(theta), values) of f_obj at theta from batched passes of the
+    workspace `ws` (all instances of one model); values: f_obj at the
+    stencil points."""
+    pts = stencil_points(theta, h)
+    vals = batched_values(ws, pts)
     return second_differences(vals, pts.shape[1], h), vals[0], vals
+
+
+def reparam_axes(H: np.ndarray) -> np.ndarray:
+    """Columns V_k / sqrt(lambda_k) for -H = V diag(lambda) V^T, eigenvalues
+    ascending, each column oriented so that its largest-magnitude entry is
+    positive.  Raises ValueError unless H is negative definite."""
+    lam, V = np.linalg.eigh(-H)
+    if not np.all(lam > 0.0):
+        raise ValueError("Hessian not negative definite")
+    cols = np.arange(V.shape[1])
+    sign = np.sign(V[np.abs(V).argmax(axis=0), cols])
+    return V * (sign / np.sqrt(lam))[None, :]
+
+
+def fobj_skew(ws, theta: np.ndarray, H: np.ndarray, f0: float, delta: float = 1.0):
+    """(A, scale_plus, scale_minus, values): f_obj at theta +- delta A e_k
+    (rows alternate + and - per axis) and the split-normal scale of each
+    axis per side; the scales are None when f does not drop along every
+    axis (theta is then not a mode)."""
+    A = reparam_axes(H)
+    d = A.shape[1]
+    pts = np.empty((2 * d, d))
+    pts[0::2] = theta[None, :] + delta * A.T
+    pts[1::2] = theta[None, :] - delta * A.T
+    vals = batched_values(ws, pts)
+    drop = f0 - vals
+    if not np.all(drop > 0.0):
+        return A, None, None, vals
+    scale = delta / np.sqrt(2.0 * drop)
+    return A, scale[0::2], scale[1::2], vals
+
+
+def skew_sd(A: np.ndarray, scale_plus: np.ndarray, scale_minus: np.ndarray):
+    """(upper, lower) standard deviations of every theta_j."""
+    sq_p, sq_m = scale_plus ** 2, scale_minus ** 2
+    raise_side = np.where(A >= 0.0, sq_p[None, :], sq_m[None, :])
+    lower_side = np.where(A >= 0.0, sq_m[None, :], sq_p[None, :])
+    A2 = A * A
+    return np.sqrt((A2 * raise_side).sum(axis=1)), np.sqrt((A2 * lower_side).sum(axis=1))
 
 
 def marginal_sd(H: np.ndarray) -> np.ndarray:
@@ -121,6 +177,12 @@ def main(argv=None):
            "negative_definite": bool(ev.max() < 0)}
     if out["negative_definite"]:
         out["gaussian_marginal_sd"] = marginal_sd(H).tolist()
+        A, sp, sm, sv = fobj_skew(ws, wl.theta, H, f0)
+        out["skew_points"] = int(sv.size)
+        if sp is not None:
+            up, dn = skew_sd(A, sp, sm)
+            out.update(skew_scale_plus=sp.tolist(), skew_scale_minus=sm.tolist(),
+                       skew_sd_upper=up.tolist(), skew_sd_lower=dn.tolist())
     print(json.dumps(out), flush=True)
 
 
