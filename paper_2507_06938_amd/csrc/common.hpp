@@ -133,33 +133,34 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
 
 // ---- fused panel step of a blocked diagonal-block Cholesky -------------------
 // For the n x n block A (nbk x nbk tiles of 64, column-major, ld) whose
-// tiles 0..j are factored (diagonal tiles hold G_kk = L_kk^{-1}, the tiles
-// below diagonal tile k still hold the unsolved panel P_k = A(:, k) as
-// updated by panels < k), one step j applies the trailing update of panel j
-// to the lower tiles (I, J), j < J <= I:
-//     A(I, J) -= L(I, j) L(J, j)^T,   L(., j) = P_j G_jj^T
-// (L formed in the workgroup, not stored), and in the same launch factors
-// the updated diagonal tile j+1 (mode 1, logdiag, info).  The panels are
-// solved afterwards, all at once (L(I, k) = P_k(I) G_kk^T).  With `solved`
-// set, panel j already holds L(., j) (solved in place by a launch before
-// this one) and the workgroups read it instead of forming it: one tile
-// product per tile instead of three, for the panels whose trailing grid is
-// large enough that the work, not the factor path, sets the launch time.
-// One workgroup per tile; the tiles that factor are numbered first.
+// tiles 0..j are factored and whose panel j below the diagonal holds
+// L(., j), one step j applies the trailing update of panel j to the lower
+// tiles (I, J), j < J <= I:
+//     A(I, J) -= L(I, j) L(J, j)^T,
+// factors the updated diagonal tile j+1 (logdiag, info) and solves the panel
+// below it, L(I, j+1) = A(I, j+1) G_{j+1}^T, so the next step again finds
+// its panel solved.  One workgroup per tile: the factoring workgroups
+// first, then the workgroups of column j+1 (each updates the diagonal tile
+// j+1 in LDS the same way, factors it and solves its own tile with the
+// result), then the rest.  While column j+1 reads the diagonal tile, the
+// factoring workgroup puts G_{j+1} into the side ring gside (two 64 x 64
+// tiles, slot (j+1) % 2) instead; step j+1 moves it into place (nobody reads
+// diagonal tile j+1 then).  The last step, which has no column below its
+// tile, writes G in place.
 struct PanelTask {
   double* A;
   int64_t ld;
   double* logdiag;     // 64 entries for tile j+1
   int64_t* info;
   int64_t row0;        // global row of tile j+1
+  double* gside;       // 2 x 64 x 64 doubles (ld 64)
   int32_t j, nbk;
-  int32_t tile_begin;  // first non-factor workgroup of this task (after the
-                       // count factor workgroups of the launch)
-  int32_t ntiles;      // lower tiles of the trailing grid, factor tile included
-  int32_t solved;      // panel j holds L(., j)
+  int32_t col_begin;   // first column workgroup of this task among all tasks'
+  int32_t rest_begin;  // first remaining workgroup of this task among all tasks'
+  int32_t ncol_total;  // column workgroups of the launch (same in every task)
   int32_t pad_;
 };
-// Fill tile_begin/ntiles; return the grid size.
+// Fill col_begin/rest_begin/ncol_total; return the grid size.
 int finalize_panels(PanelTask* t, int n);
 hipError_t launch_panel_updates(const PanelTask* tasks_dev, int ntask, int grid,
                                 hipStream_t s);

@@ -186,19 +186,19 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
 
 // ---- fused panel step ---------------------------------------------------------------
 //
-// Workgroup g < ntask factors: it updates diagonal tile j+1 of task g and then
-// factors it; the others update one lower tile (I, J) each.  Per tile, with
-// the 64 x 64 operands staged in LDS (S0 = P_j(I), S1 = G_jj, S2 = P_j(J)):
-//   L_I = P_j(I) G_jj^T and L_J = P_j(J) G_jj^T  (G_jj lower triangular:
-//        block column c of L needs k < 16 (c + 1) only),
-//   A(I, J) -= L_I L_J^T,
+// Roles by workgroup (task order within each segment): factor (one per
+// task), column (tiles (I, j+1), I > j+1), rest (I >= J > j+1).  Per tile,
+// with the 64 x 64 operands staged in LDS (S0 = L(I, j), S2 = L(J, j)):
+//   A(I, J) -= L(I, j) L(J, j)^T
 // on FP64 MFMA, one 16 x 16 block per wave, with the operand roles chosen so
 // that a lane's results lie along the rows of the column-major output
-// (coalesced stores).  Every
-// global load (the operand tiles and the elements of A(I, J) a lane updates)
-// is issued before the first LDS store, so their latencies overlap.  The
-// factoring workgroup (I = J) forms L_I once, stages the updated tile in LDS
-// (S1) and runs the tile factor on it with S0 and S2 as its scratch tiles.
+// (coalesced stores).  Every global load (the operand tiles and the elements
+// a lane updates) is issued before the first LDS store, so their latencies
+// overlap.  The factoring workgroup stages its updated tile in LDS (S1) and
+// runs the tile factor on it with S0 and S2 as scratch.  A column workgroup
+// also updates the diagonal tile j+1 (from L(J, j) in S2: the factoring
+// workgroup's product, bit for bit), factors it in LDS without writing it,
+// and stores L(I, j+1) = A(I, j+1) G^T in place of its tile.
 __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __restrict__ tasks,
                                                            int ntask) {
   __shared__ __align__(16) double pool[3 * TILE_LDS];
@@ -206,27 +206,42 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   double* S0 = pool;
   double* S1 = pool + TILE_LDS;
   double* S2 = pool + 2 * TILE_LDS;
-  const bool fac = (int)blockIdx.x < ntask;
-  int ti, lt;
-  if (fac) {
-    ti = blockIdx.x;
-    lt = 0;
-  } else {
-    const int g = blockIdx.x - ntask;
+  const int ncol_total = tasks[0].ncol_total;
+  const int b = blockIdx.x;
+  int ti, I, J, role;  // role 0: factor, 1: column j+1, 2: rest
+  if (b < ntask) {
+    ti = b;
+    I = J = 0;
+    role = 0;
+  } else if (b < ntask + ncol_total) {
+    const int g = b - ntask;
     int lo = 0, hi = ntask - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tasks[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+      if (tasks[mid].col_begin <= g) lo = mid; else hi = mid - 1;
     }
     ti = lo;
-    lt = 1 + g - tasks[ti].tile_begin;
+    I = 1 + g - tasks[ti].col_begin;
+    J = 0;
+    role = 1;
+  } else {
+    const int g = b - ntask - ncol_total;
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].rest_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    ti = lo;
+    // row-major enumeration of the lower triangle of tiles (I, J), J >= 1
+    const int lt = g - tasks[ti].rest_begin;
+    int R = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
+    while ((R + 1) * (R + 2) / 2 <= lt) ++R;
+    while (R * (R + 1) / 2 > lt) --R;
+    I = R + 1;
+    J = lt - R * (R + 1) / 2 + 1;
+    role = 2;
   }
   const PanelTask T = tasks[ti];
-  // row-major enumeration of the lower triangle of the trailing tile grid
-  int I = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= lt) ++I;
-  while (I * (I + 1) / 2 > lt) --I;
-  const int J = lt - I * (I + 1) / 2;
   const int64_t ti0 = (int64_t)(T.j + 1 + I) * NB, tj0 = (int64_t)(T.j + 1 + J) * NB;
   const int64_t pc = (int64_t)T.j * NB * T.ld;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -234,75 +249,102 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   const int lr = l & 15, lk = l >> 4;
   const int p0 = 16 * (wv >> 2), q0 = 16 * (wv & 3);  // this wave's 16 x 16 block
   double* C = T.A + ti0 + tj0 * T.ld;
+  const bool diag = (I == J);
   constexpr int PER = NB * NB / POTRF_NT;
-  // panel tiles (I, j) and (J, j): P or, when solved, L; S0[c][m] = X(m, c)
-  const bool solved = T.solved != 0;
-  double vp[PER], vg[PER], vq[PER], cpre[4];
+  double vp[PER], vq[PER], cpre[4], dpre[4];
   {
-    const double* Pi = T.A + ti0 + pc;
-    const double* Gj = T.A + (int64_t)T.j * NB * (T.ld + 1);  // G_jj
-    const double* Pj = T.A + tj0 + pc;
+    const double* Li = T.A + ti0 + pc;
+    const double* Lj = T.A + tj0 + pc;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = threadIdx.x + e * POTRF_NT;
       const int64_t o = (idx & 63) + (int64_t)(idx >> 6) * T.ld;
-      vp[e] = Pi[o];
-      vg[e] = solved ? 0.0 : Gj[o];
-      vq[e] = (I != J) ? Pj[o] : 0.0;
+      vp[e] = Li[o];
+      vq[e] = diag ? 0.0 : Lj[o];
     }
 #pragma unroll
     for (int rg = 0; rg < 4; ++rg) cpre[rg] = C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld];
+    if (role == 1) {
+      const double* Dj = T.A + (int64_t)(T.j + 1) * NB * (T.ld + 1);
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg)
+        dpre[rg] = Dj[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld];
+    }
+    if (role == 0 && T.j >= 1) {
+      // G_j from the side ring into diagonal tile j (read by nobody now)
+      const double* src = T.gside + (int64_t)(T.j & 1) * NB * NB;
+      double* dst = T.A + (int64_t)T.j * NB * (T.ld + 1);
+      for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT)
+        dst[(idx & 63) + (int64_t)(idx >> 6) * T.ld] = src[idx];
+    }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = threadIdx.x + e * POTRF_NT;
       const int o = (idx >> 6) * LDL + (idx & 63);
       S0[o] = vp[e];
-      if (!solved) S1[o] = vg[e];
-      if (I != J) S2[o] = vq[e];
+      if (!diag) S2[o] = vq[e];
     }
   }
   __syncthreads();
-  if (!solved) {
-    // L^T = G P^T: D[c][m] = sum_k G(c, k) P(m, k), k <= c < p0 + 16
-    v4d a0 = {0.0, 0.0, 0.0, 0.0}, b0 = {0.0, 0.0, 0.0, 0.0};
-    mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L_I(m = q0 + lr, c = p0 + lk + 4r)
-    if (I != J) mfma1_k64(S1, p0, S2, q0, b0, p0 + 16);
-    __syncthreads();
-#pragma unroll
-    for (int rg = 0; rg < 4; ++rg) {
-      const int c = p0 + lk + 4 * rg;
-      S0[c * LDL + q0 + lr] = a0[rg];
-      if (I != J) S2[c * LDL + q0 + lr] = b0[rg];
-    }
-    __syncthreads();
-  }
   // (L_I L_J^T)^T = L_J L_I^T: D[n][m] = sum_c L_J(n, c) L_I(m, c)
-  const double* LJ = (I != J) ? S2 : S0;
+  const double* LJ = diag ? S0 : S2;
   v4d u0 = {0.0, 0.0, 0.0, 0.0};
   mfma1_k64(LJ, p0, S0, q0, u0);  // u: update(m = q0 + lr, n = p0 + lk + 4r)
-  if (!fac) {
+  if (role == 2) {
 #pragma unroll
     for (int rg = 0; rg < 4; ++rg)
       C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld] = cpre[rg] - u0[rg];
     return;
   }
-  __syncthreads();  // S1 (G_jj) is read no more
+  if (role == 1) {
+    // the diagonal tile j+1 updated exactly as the factoring workgroup does
+    v4d v0 = {0.0, 0.0, 0.0, 0.0};
+    mfma1_k64(S2, p0, S2, q0, v0);
+    __syncthreads();  // S0, S2 are read no more
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) S1[(p0 + lk + 4 * rg) * LDL + q0 + lr] = dpre[rg] - v0[rg];
+    __syncthreads();
+    potrf_body<POTRF_CW>(S1, LDL, S0, S2, &sbad, nullptr, 0, nullptr, nullptr, nullptr, 0, 1);
+    __syncthreads();
+    // G staged as S1[k][r] = G(r, k) (zero above the diagonal); the updated
+    // panel tile as S0[c][m] = A(m, c)
+    for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT) {
+      const int r = idx & 63, k = idx >> 6;
+      S1[k * LDL + r] = (r >= k) ? S2[r * LDL + k] : 0.0;
+    }
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) S0[(p0 + lk + 4 * rg) * LDL + q0 + lr] = cpre[rg] - u0[rg];
+    __syncthreads();
+    // L^T = G A^T: D[c][m] = sum_k G(c, k) A(m, k), k <= c < p0 + 16
+    v4d a0 = {0.0, 0.0, 0.0, 0.0};
+    mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L(m = q0 + lr, c = p0 + lk + 4r)
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+      C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld] = a0[rg];
+    return;
+  }
+  __syncthreads();  // S0 is read no more
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg) S1[(p0 + lk + 4 * rg) * LDL + q0 + lr] = cpre[rg] - u0[rg];
   __syncthreads();
-  potrf_body<POTRF_CW>(S1, LDL, S0, S2, &sbad, C, T.ld, nullptr, T.logdiag, T.info,
-                       T.row0, 1);
+  // while column j+1 below reads diagonal tile j+1, G_{j+1} goes to the ring
+  const bool side = T.j + 2 < T.nbk;
+  double* dst = side ? T.gside + (int64_t)((T.j + 1) & 1) * NB * NB : C;
+  potrf_body<POTRF_CW>(S1, LDL, S0, S2, &sbad, dst, side ? NB : T.ld, nullptr, T.logdiag,
+                       T.info, T.row0, 1);
 }
 
 int finalize_panels(PanelTask* t, int n) {
-  int total = 0;
+  int ncol = 0, nrest = 0;
   for (int i = 0; i < n; ++i) {
-    const int m = t[i].nbk - t[i].j - 1;
-    t[i].ntiles = m * (m + 1) / 2;
-    t[i].tile_begin = total;
-    total += t[i].ntiles - 1;
+    const int m = t[i].nbk - t[i].j - 1;  // trailing tile rows (>= 1)
+    t[i].col_begin = ncol;
+    ncol += m - 1;
+    t[i].rest_begin = nrest;
+    nrest += m * (m - 1) / 2;
   }
-  return n + total;
+  for (int i = 0; i < n; ++i) t[i].ncol_total = ncol;
+  return n + ncol + nrest;
 }
 
 hipError_t launch_panel_updates(const PanelTask* tasks, int ntask, int grid,

@@ -240,27 +240,18 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
   return s;
 }
 
-// Panels whose trailing grid has at least this many tile rows are solved
-// in place by a GEMM launch before their trailing update (the update then
-// does one tile product per tile instead of forming L in every tile).
-constexpr int PANEL_SOLVE_MIN_ROWS = 16;
-
 // Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
 // panels of 64 columns.  Diagonal tiles are overwritten by their inverses
-// G_jj (they are used only through them).  Tile 0 is factored alone; step j
-// then updates the trailing tiles with L(., j) = P_j G_jj^T and factors tile
-// j+1 in the same launch.  L(., j) is formed inside each tile from the
-// unsolved panel for small trailing grids, and solved in place by a GEMM
-// launch just before the step for large ones; the panels left unsolved are
-// solved at the end in one launch, L(I, j) = P_j(I) G_jj^T.  `breal`:
-// unpadded size (operation count).  Keys (major, group 1, j, sub): (0, 0)
-// tile 0, (j, 1) the in-place solve of panel j, (j, 2) step j, (255, 0) the
-// remaining panel solves.
+// G_jj (they are used only through them).  Tile 0 is factored alone and its
+// panel solved in place, L(., 0) = P_0 G_00^T; step j then updates the
+// trailing tiles with L(., j), factors tile j+1 and solves panel j+1 in the
+// same launch (gside: two 64 x 64 tiles the step uses to hand G_{j+1} over,
+// see PanelTask).  `breal`: unpadded size (operation count).  Keys (major,
+// group 1, j, sub): (0, 0) tile 0, (0, 1) the solve of panel 0, (j, 2) step j.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
-                      int breal) {
+                      int breal, double* gside) {
   const int nbk = n / 64;
-  auto early = [&](int j) { return nbk - j - 1 >= PANEL_SOLVE_MIN_ROWS; };
   auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
   auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
   {
@@ -278,44 +269,31 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     s.potrf.mode = 1;
     q.push_back(s);
   }
+  if (nbk > 1) {
+    double* panel = A + 64;
+    q.push_back(gemm_step(K(major, 1, 0, 1), DL_CAT_PANEL_TRSM, below(0) * width(0) * width(0),
+                          {mk(panel, ld, A, ld, panel, ld, n - 64, 64, 64, F_TB | F_BETA0,
+                              1.0, 0.0)}));
+  }
   for (int j = 0; j + 1 < nbk; ++j) {
     const double w = width(j), w1 = width(j + 1), bl = below(j);
-    if (early(j)) {
-      double* Ajj = A + (int64_t)j * 64 * (ld + 1);
-      double* panel = Ajj + 64;
-      q.push_back(gemm_step(K(major, 1, j, 1), DL_CAT_PANEL_TRSM, bl * w * w,
-                            {mk(panel, ld, Ajj, ld, panel, ld, n - (j + 1) * 64, 64, 64,
-                                F_TB | F_BETA0, 1.0, 0.0)}));
-    }
     Step s;
     s.key = K(major, 1, j, 2);
     s.kind = OP_PANEL;
     s.cat = DL_CAT_PANEL_SYRK;
-    // the trailing update of a right-looking Cholesky plus the tile factor
-    s.flops = bl * bl * w + w1 * w1 * w1 / 3.0;
+    // the trailing update of a right-looking Cholesky, the tile factor and
+    // the solve of the next panel
+    s.flops = bl * bl * w + w1 * w1 * w1 / 3.0 + below(j + 1) * w1 * w1;
     PanelTask& t = s.panel;
     t.A = A;
     t.ld = ld;
     t.logdiag = logdiag + (int64_t)(j + 1) * 64;
     t.info = info;
     t.row0 = row0 + (int64_t)(j + 1) * 64;
+    t.gside = gside;
     t.j = j;
     t.nbk = nbk;
-    t.solved = early(j) ? 1 : 0;
     q.push_back(s);
-  }
-  if (nbk > 1) {
-    std::vector<GemmTask> ts;
-    double fl = 0.0;
-    for (int j = 0; j + 1 < nbk; ++j) {
-      if (early(j)) continue;
-      const int rows = n - (j + 1) * 64;
-      double* Ajj = A + (int64_t)j * 64 * (ld + 1);
-      double* panel = Ajj + 64;
-      ts.push_back(mk(panel, ld, Ajj, ld, panel, ld, rows, 64, 64, F_TB | F_BETA0, 1.0, 0.0));
-      fl += below(j) * width(j) * width(j);
-    }
-    q.push_back(gemm_step(K(major, 1, 255, 0), DL_CAT_PANEL_TRSM, fl, std::move(ts)));
   }
 }
 
@@ -699,10 +677,12 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
       if (chain == 1 && t - 1 > mid)
         asm_qp(t - 1, Dt(t - 1), BRs(3 + (t - 1) % 2), K(major, 0));
     }
+    // the inverse's temporary is free until the inverse, so the panel steps
+    // borrow two tiles of it
+    double* tmp = chain == 1 ? I.ttempB[w] : I.ttemp[w];
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
-              (int64_t)t * m.b, m.b);
-    seq_trtri(q, major, Dt(t), bp, bp, chain == 1 ? I.ttempB[w] : I.ttemp[w],
-              count_inv ? m.b : 0, xf);
+              (int64_t)t * m.b, m.b, tmp);
+    seq_trtri(q, major, Dt(t), bp, bp, tmp, count_inv ? m.b : 0, xf);
     const int M = (root ? 0 : bp) + apr;
     if (M <= 0) return;
     const double b = m.b, ar = apr ? m.a : 0;
