@@ -159,7 +159,16 @@ enum {
                          Needs nt >= 4 (otherwise one-sided).  Results
                          differ from the one-sided order by rounding only.
                          Relies on symmetric sub-diagonal blocks, which
-                         every model of this library has                    */
+                         every model of this library has                    */,
+  DL_WS_FOLD_INV = 64 /* form each diagonal block's inverse L_tt^-1 inside
+                         the launches of its blocked factorisation (one row
+                         of 64 x 64 tiles per panel step, left-looking)
+                         instead of by recursive GEMM halving after it:
+                         about 12 fewer dependent launches per block, faster
+                         when few blocks are factored at once (single
+                         evaluations); for wide batches the recursive
+                         inversion is faster.  Results differ from the
+                         default by rounding only                           */
 };
 #define DL_REFINE_STEPS 3
 

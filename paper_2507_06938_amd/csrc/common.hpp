@@ -139,14 +139,20 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args_dev, int count,
 //     A(I, J) -= L(I, j) L(J, j)^T,
 // factors the updated diagonal tile j+1 (logdiag, info) and solves the panel
 // below it, L(I, j+1) = A(I, j+1) G_{j+1}^T, so the next step again finds
-// its panel solved.  One workgroup per tile: the factoring workgroups
-// first, then the workgroups of column j+1 (each updates the diagonal tile
-// j+1 in LDS the same way, factors it and solves its own tile with the
-// result), then the rest.  While column j+1 reads the diagonal tile, the
-// factoring workgroup puts G_{j+1} into the side ring gside (two 64 x 64
-// tiles, slot (j+1) % 2) instead; step j+1 moves it into place (nobody reads
-// diagonal tile j+1 then).  The last step, which has no column below its
-// tile, writes G in place.
+// its panel solved.  The same launch advances the inverse G = L^{-1}
+// (left-looking, one row of tiles per step):
+//     G(j, c) = -G_jj (S(j, c) + L(j, j-1) G(j-1, c)),   c < j,
+//     S(r, c) += L(r, j-1) G(j-1, c),                     r > j, c < j,
+// S(r, c) = sum over k = c .. j-2 of L(r, k) G(k, c) accumulated in
+// `stage`.  Workgroup roles, in grid segments: factor (the workgroup of
+// tile j+1), column (tiles (I, j+1), I > j+1: each updates the diagonal
+// tile j+1 in LDS the same way, factors it and solves its own tile), inverse
+// row (G(j, c)), inverse accumulate (S(r, c)), rest (I >= J > j+1).
+// Hand-overs: while column j+1 reads diagonal tile j+1, G_{j+1} goes to the
+// side ring (gside slot (j+1) % 2) and step j+1 moves it into place; while
+// row j of the inverse reads L(j, j-1), G(j, j-1) stays in stage and step j+1
+// moves it into place.  The closing launch (last = 1, j = nbk-1) computes
+// the inverse's last row only; its G(nbk-1, nbk-2) is left in stage.
 struct PanelTask {
   double* A;
   int64_t ld;
@@ -154,13 +160,14 @@ struct PanelTask {
   int64_t* info;
   int64_t row0;        // global row of tile j+1
   double* gside;       // 2 x 64 x 64 doubles (ld 64)
+  double* stage;       // tile (r, c), c < r: ((r (r-1)) / 2 + c) * 4096 (ld 64)
   int32_t j, nbk;
-  int32_t col_begin;   // first column workgroup of this task among all tasks'
-  int32_t rest_begin;  // first remaining workgroup of this task among all tasks'
-  int32_t ncol_total;  // column workgroups of the launch (same in every task)
-  int32_t pad_;
+  int32_t last;
+  int32_t inv;         // 0: no inverse workgroups (the recursive inverse follows)
+  int32_t beg[5];      // first workgroup of this task in each role segment
+  int32_t tot[5];      // workgroups of each role in the launch (every task)
 };
-// Fill col_begin/rest_begin/ncol_total; return the grid size.
+// Fill beg/tot; return the grid size.
 int finalize_panels(PanelTask* t, int n);
 hipError_t launch_panel_updates(const PanelTask* tasks_dev, int ntask, int grid,
                                 hipStream_t s);

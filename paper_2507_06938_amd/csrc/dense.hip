@@ -186,19 +186,102 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
 
 // ---- fused panel step ---------------------------------------------------------------
 //
-// Roles by workgroup (task order within each segment): factor (one per
-// task), column (tiles (I, j+1), I > j+1), rest (I >= J > j+1).  Per tile,
-// with the 64 x 64 operands staged in LDS (S0 = L(I, j), S2 = L(J, j)):
-//   A(I, J) -= L(I, j) L(J, j)^T
-// on FP64 MFMA, one 16 x 16 block per wave, with the operand roles chosen so
-// that a lane's results lie along the rows of the column-major output
-// (coalesced stores).  Every global load (the operand tiles and the elements
-// a lane updates) is issued before the first LDS store, so their latencies
-// overlap.  The factoring workgroup stages its updated tile in LDS (S1) and
-// runs the tile factor on it with S0 and S2 as scratch.  A column workgroup
-// also updates the diagonal tile j+1 (from L(J, j) in S2: the factoring
-// workgroup's product, bit for bit), factors it in LDS without writing it,
-// and stores L(I, j+1) = A(I, j+1) G^T in place of its tile.
+// Per tile, with the 64 x 64 operands staged in LDS (S0 = L(I, j), S2 =
+// L(J, j)):  A(I, J) -= L(I, j) L(J, j)^T  on FP64 MFMA, one 16 x 16 block
+// per wave, with the operand roles chosen so that a lane's results lie along
+// the rows of the column-major output (coalesced stores).  Every global load
+// (the operand tiles and the elements a lane updates) is issued before the
+// first LDS store, so their latencies overlap.  The factoring workgroup
+// stages its updated tile in LDS (S1) and runs the tile factor on it with S0
+// and S2 as scratch.  A column workgroup also updates the diagonal tile j+1
+// (from L(J, j) in S2: the factoring workgroup's product, bit for bit),
+// factors it in LDS without writing it, and stores L(I, j+1) = A(I, j+1) G^T
+// in place of its tile.  The inverse's workgroups form one or two tile
+// products each (see PanelTask).
+
+// S[k*LDL + r] = X(r, k) for the 64 x 64 tile X (ld), coalesced along r.
+__device__ __forceinline__ void stage_cols(const double* __restrict__ X, int64_t ld, double* S) {
+  for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT) {
+    const int r = idx & 63, k = idx >> 6;
+    S[k * LDL + r] = X[r + (int64_t)k * ld];
+  }
+}
+
+// S[k*LDL + r] = X(k, r) (the transpose), coalesced along k.
+__device__ __forceinline__ void stage_rows(const double* __restrict__ X, int64_t ld, double* S) {
+  for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT) {
+    const int k = idx & 63, r = idx >> 6;
+    S[k * LDL + r] = X[k + (int64_t)r * ld];
+  }
+}
+
+__device__ __forceinline__ double* stage_tile(const PanelTask& T, int r, int c) {
+  return T.stage + ((int64_t)(r * (r - 1) / 2 + c)) * (NB * NB);
+}
+
+// The inverse's workgroups of step j (role 2: row j, column c; role 3:
+// accumulator (r, c), r > j).  With X(r', c) the product Y X^T of staged
+// tiles (mfma1_k64), lane results lie at (q0 + lr, p0 + lk + 4 rg).
+__device__ void panel_inverse(const PanelTask& T, int role, int loc, double* S0, double* S1) {
+  const int j = T.j;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int p0 = 16 * (wv >> 2), q0 = 16 * (wv & 3);
+  const int64_t ld = T.ld;
+  double* const A = T.A;
+  auto tileA = [&](int r, int c) { return A + (int64_t)r * NB + (int64_t)c * NB * ld; };
+  const int r = (role == 2) ? j : j + 1 + loc / j;
+  const int c = (role == 2) ? loc : loc % j;
+  if (role == 2 && c == 0 && j >= 2) {
+    // G(j-1, j-2) from stage into place (L(j-1, j-2) is read no more)
+    const double* src = stage_tile(T, j - 1, j - 2);
+    double* dst = tileA(j - 1, j - 2);
+    for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT)
+      dst[(idx & 63) + (int64_t)(idx >> 6) * ld] = src[idx];
+  }
+  // G(j-1, c): the diagonal tile, the staged G(j-1, j-2), or in place
+  const double* Gk;
+  int64_t ldg;
+  if (c == j - 1) { Gk = tileA(j - 1, j - 1); ldg = ld; }
+  else if (c == j - 2) { Gk = stage_tile(T, j - 1, j - 2); ldg = NB; }
+  else { Gk = tileA(j - 1, c); ldg = ld; }
+  double prev[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c <= j - 2) {
+    const double* Sp = stage_tile(T, r, c);
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) prev[rg] = Sp[(q0 + lr) + (p0 + lk + 4 * rg) * NB];
+  }
+  stage_cols(tileA(r, j - 1), ld, S0);  // Y = L(r, j-1)
+  stage_rows(Gk, ldg, S1);              // X = G(j-1, c)^T
+  __syncthreads();
+  v4d t = {prev[0], prev[1], prev[2], prev[3]};
+  mfma1_k64(S1, p0, S0, q0, t);         // t = S(r, c) + L(r, j-1) G(j-1, c)
+  if (role == 3) {
+    double* Sd = stage_tile(T, r, c);
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) Sd[(q0 + lr) + (p0 + lk + 4 * rg) * NB] = t[rg];
+    return;
+  }
+  // G(j, c) = -G_jj t: G_jj from the side ring during the panel steps, in
+  // place for the closing launch
+  const double* Gjj = T.last ? tileA(j, j) : T.gside + (int64_t)(j & 1) * NB * NB;
+  const int64_t ldj = T.last ? ld : NB;
+  __syncthreads();  // S0, S1 are read no more
+  stage_cols(Gjj, ldj, S0);             // Y = G_jj
+#pragma unroll
+  for (int rg = 0; rg < 4; ++rg) S1[(q0 + lr) * LDL + p0 + lk + 4 * rg] = t[rg];  // X = t^T
+  __syncthreads();
+  v4d g = {0.0, 0.0, 0.0, 0.0};
+  mfma1_k64(S1, p0, S0, q0, g, q0 + 16);  // G_jj is lower triangular
+  double* dst;
+  int64_t ldd;
+  if (c == j - 1) { dst = stage_tile(T, j, j - 1); ldd = NB; }
+  else { dst = tileA(j, c); ldd = ld; }
+#pragma unroll
+  for (int rg = 0; rg < 4; ++rg) dst[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ldd] = -g[rg];
+}
+
 __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __restrict__ tasks,
                                                            int ntask) {
   __shared__ __align__(16) double pool[3 * TILE_LDS];
@@ -206,42 +289,38 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   double* S0 = pool;
   double* S1 = pool + TILE_LDS;
   double* S2 = pool + 2 * TILE_LDS;
-  const int ncol_total = tasks[0].ncol_total;
-  const int b = blockIdx.x;
-  int ti, I, J, role;  // role 0: factor, 1: column j+1, 2: rest
-  if (b < ntask) {
-    ti = b;
-    I = J = 0;
-    role = 0;
-  } else if (b < ntask + ncol_total) {
-    const int g = b - ntask;
-    int lo = 0, hi = ntask - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tasks[mid].col_begin <= g) lo = mid; else hi = mid - 1;
-    }
-    ti = lo;
-    I = 1 + g - tasks[ti].col_begin;
-    J = 0;
-    role = 1;
-  } else {
-    const int g = b - ntask - ncol_total;
-    int lo = 0, hi = ntask - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tasks[mid].rest_begin <= g) lo = mid; else hi = mid - 1;
-    }
-    ti = lo;
-    // row-major enumeration of the lower triangle of tiles (I, J), J >= 1
-    const int lt = g - tasks[ti].rest_begin;
-    int R = (int)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
-    while ((R + 1) * (R + 2) / 2 <= lt) ++R;
-    while (R * (R + 1) / 2 > lt) --R;
-    I = R + 1;
-    J = lt - R * (R + 1) / 2 + 1;
-    role = 2;
+  // role segments: 0 factor, 1 column, 2 inverse row, 3 inverse accumulate,
+  // 4 rest; then the task whose share of the segment holds this workgroup
+  int g = blockIdx.x, role = 0;
+  while (role < 4 && g >= tasks[0].tot[role]) {
+    g -= tasks[0].tot[role];
+    ++role;
   }
-  const PanelTask T = tasks[ti];
+  int lo = 0, hi = ntask - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].beg[role] <= g) lo = mid; else hi = mid - 1;
+  }
+  const int loc = g - tasks[lo].beg[role];
+  const PanelTask T = tasks[lo];
+  if (role == 2 || role == 3) {
+    panel_inverse(T, role, loc, S0, S1);
+    return;
+  }
+  int I, J;
+  if (role == 0) {
+    I = J = 0;
+  } else if (role == 1) {
+    I = 1 + loc;
+    J = 0;
+  } else {
+    // row-major enumeration of the lower triangle of tiles (I, J), J >= 1
+    int R = (int)((sqrt(8.0 * (double)loc + 1.0) - 1.0) * 0.5);
+    while ((R + 1) * (R + 2) / 2 <= loc) ++R;
+    while (R * (R + 1) / 2 > loc) --R;
+    I = R + 1;
+    J = loc - R * (R + 1) / 2 + 1;
+  }
   const int64_t ti0 = (int64_t)(T.j + 1 + I) * NB, tj0 = (int64_t)(T.j + 1 + J) * NB;
   const int64_t pc = (int64_t)T.j * NB * T.ld;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -290,7 +369,7 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
   const double* LJ = diag ? S0 : S2;
   v4d u0 = {0.0, 0.0, 0.0, 0.0};
   mfma1_k64(LJ, p0, S0, q0, u0);  // u: update(m = q0 + lr, n = p0 + lk + 4r)
-  if (role == 2) {
+  if (role == 4) {
 #pragma unroll
     for (int rg = 0; rg < 4; ++rg)
       C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * T.ld] = cpre[rg] - u0[rg];
@@ -335,16 +414,31 @@ __global__ __launch_bounds__(POTRF_NT) void k_panel_update(const PanelTask* __re
 }
 
 int finalize_panels(PanelTask* t, int n) {
-  int ncol = 0, nrest = 0;
+  int tot[5] = {0, 0, 0, 0, 0};
   for (int i = 0; i < n; ++i) {
-    const int m = t[i].nbk - t[i].j - 1;  // trailing tile rows (>= 1)
-    t[i].col_begin = ncol;
-    ncol += m - 1;
-    t[i].rest_begin = nrest;
-    nrest += m * (m - 1) / 2;
+    const int j = t[i].j, nbk = t[i].nbk;
+    int cnt[5];
+    if (t[i].last) {
+      cnt[0] = cnt[1] = cnt[3] = cnt[4] = 0;
+      cnt[2] = j;
+    } else {
+      const int m = nbk - j - 1;  // trailing tile rows (>= 1)
+      cnt[0] = 1;
+      cnt[1] = m - 1;
+      cnt[2] = t[i].inv ? j : 0;
+      cnt[3] = t[i].inv ? (nbk - 1 - j) * j : 0;
+      cnt[4] = m * (m - 1) / 2;
+    }
+    for (int k = 0; k < 5; ++k) {
+      t[i].beg[k] = tot[k];
+      tot[k] += cnt[k];
+    }
   }
-  for (int i = 0; i < n; ++i) t[i].ncol_total = ncol;
-  return n + ncol + nrest;
+  int grid = 0;
+  for (int k = 0; k < 5; ++k) grid += tot[k];
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 5; ++k) t[i].tot[k] = tot[k];
+  return grid;
 }
 
 hipError_t launch_panel_updates(const PanelTask* tasks, int ntask, int grid,

@@ -241,19 +241,27 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
 }
 
 // Blocked right-looking Cholesky of the n x n block A (n multiple of 64),
-// panels of 64 columns.  Diagonal tiles are overwritten by their inverses
-// G_jj (they are used only through them).  Tile 0 is factored alone and its
-// panel solved in place, L(., 0) = P_0 G_00^T; step j then updates the
-// trailing tiles with L(., j), factors tile j+1 and solves panel j+1 in the
-// same launch (gside: two 64 x 64 tiles the step uses to hand G_{j+1} over,
-// see PanelTask).  `breal`: unpadded size (operation count).  Keys (major,
-// group 1, j, sub): (0, 0) tile 0, (0, 1) the solve of panel 0, (j, 2) step j.
+// panels of 64 columns.  With `fold`, the inverse G = L^{-1} is formed
+// alongside and on return the block holds G (lower triangle); otherwise the
+// block holds L with its diagonal tiles inverted (seq_trtri completes G).  Tile 0 is factored alone (its
+// inverse in place) and its panel solved in place, L(., 0) = P_0 G_00^T;
+// step j then updates the trailing tiles with L(., j), factors tile j+1,
+// solves panel j+1 and advances the inverse by one row of tiles (see
+// PanelTask); a closing launch forms the inverse's last row and one tile
+// copy puts its G(nbk-1, nbk-2) in place.  `tmp` holds the two-tile side
+// ring and the inverse's accumulators (2 + nbk (nbk - 1) / 2 tiles).
+// `breal`: unpadded size (operation count); `count_inv`: count the
+// inverse's b^3/3 (else it is extra work of the inverse-based solves).
+// Keys (major, group 1, j, sub): (0, 0) tile 0, (0, 1) the solve of panel 0,
+// (j, 2) step j and the closing launch (j = nbk - 1), (nbk - 1, 3) the copy.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
-                      int breal, double* gside) {
+                      int breal, double* tmp, bool count_inv, bool fold) {
   const int nbk = n / 64;
   auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
   auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
+  double* gside = tmp;
+  double* stage = tmp + 2 * 4096;
   {
     const double w = width(0);
     Step s;
@@ -269,21 +277,27 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     s.potrf.mode = 1;
     q.push_back(s);
   }
-  if (nbk > 1) {
+  if (nbk == 1) return;
+  {
     double* panel = A + 64;
     q.push_back(gemm_step(K(major, 1, 0, 1), DL_CAT_PANEL_TRSM, below(0) * width(0) * width(0),
                           {mk(panel, ld, A, ld, panel, ld, n - 64, 64, 64, F_TB | F_BETA0,
                               1.0, 0.0)}));
   }
-  for (int j = 0; j + 1 < nbk; ++j) {
-    const double w = width(j), w1 = width(j + 1), bl = below(j);
+  for (int j = 0; j < (fold ? nbk : nbk - 1); ++j) {
+    const bool last = (j + 1 == nbk);
     Step s;
     s.key = K(major, 1, j, 2);
     s.kind = OP_PANEL;
     s.cat = DL_CAT_PANEL_SYRK;
-    // the trailing update of a right-looking Cholesky, the tile factor and
-    // the solve of the next panel
-    s.flops = bl * bl * w + w1 * w1 * w1 / 3.0 + below(j + 1) * w1 * w1;
+    if (!last) {
+      // the trailing update of a right-looking Cholesky, the tile factor and
+      // the solve of the next panel
+      const double w = width(j), w1 = width(j + 1), bl = below(j);
+      s.flops = bl * bl * w + w1 * w1 * w1 / 3.0 + below(j + 1) * w1 * w1;
+    } else if (count_inv) {
+      s.flops = (double)breal * breal * breal / 3.0;  // the whole inverse
+    }
     PanelTask& t = s.panel;
     t.A = A;
     t.ld = ld;
@@ -291,10 +305,23 @@ static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t l
     t.info = info;
     t.row0 = row0 + (int64_t)(j + 1) * 64;
     t.gside = gside;
+    t.stage = stage;
     t.j = j;
     t.nbk = nbk;
+    t.last = last ? 1 : 0;
+    t.inv = fold ? 1 : 0;
     q.push_back(s);
   }
+  if (!fold) return;
+  // G(nbk-1, nbk-2) from the accumulators into place
+  Step cp = misc_step(K(major, 1, nbk - 1, 3), DL_CAT_PANEL_SYRK, MJ_COPY2D,
+                      A + (int64_t)(nbk - 1) * 64 + (int64_t)(nbk - 2) * 64 * ld,
+                      stage + (int64_t)((nbk - 1) * (nbk - 2) / 2 + (nbk - 2)) * 4096, 0);
+  cp.misc.rows = 64;
+  cp.misc.cols = 64;
+  cp.misc.lds = 64;
+  cp.misc.ldd = ld;
+  q.push_back(cp);
 }
 
 // In-place inverse of the lower-triangular factor whose diagonal tiles
@@ -396,6 +423,7 @@ struct dl_ws {
   int flags = 0;
   bool sel = false, keep_qp = false, mixed = false;
   bool splitk = false;
+  bool fold_inv = false;  // inverses inside the panel launches (DL_WS_FOLD_INV)
   double* partials = nullptr;  // split-k partial tiles (shared by all launches)
   int64_t partials_cap = 0;    // doubles allocated at `partials`
   int dim_total = 0;
@@ -677,12 +705,11 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
       if (chain == 1 && t - 1 > mid)
         asm_qp(t - 1, Dt(t - 1), BRs(3 + (t - 1) % 2), K(major, 0));
     }
-    // the inverse's temporary is free until the inverse, so the panel steps
-    // borrow two tiles of it
+    // factor and inverse of the diagonal block
     double* tmp = chain == 1 ? I.ttempB[w] : I.ttemp[w];
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
-              (int64_t)t * m.b, m.b, tmp);
-    seq_trtri(q, major, Dt(t), bp, bp, tmp, count_inv ? m.b : 0, xf);
+              (int64_t)t * m.b, m.b, tmp, count_inv, W->fold_inv);
+    if (!W->fold_inv) seq_trtri(q, major, Dt(t), bp, bp, tmp, count_inv ? m.b : 0, xf);
     const int M = (root ? 0 : bp) + apr;
     if (M <= 0) return;
     const double b = m.b, ar = apr ? m.a : 0;
@@ -1224,6 +1251,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->mixed = (flags & DL_WS_MIXED) != 0;
   W->use_graph = (flags & DL_WS_GRAPH) != 0;
   W->splitk = (flags & DL_WS_SPLITK) != 0;
+  W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
   const bool two_sided = (flags & DL_WS_TWOSIDED) != 0;
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
@@ -1268,8 +1296,14 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(tip, (void**)&I.Pc);
     A(tip, (void**)&I.GPc);
     A(tip, (void**)&I.GPp);
+    // per diagonal-block factorisation: the side ring and the folded
+    // inverse's accumulators (2 + nbk (nbk - 1) / 2 tiles of 64 x 64), or
+    // the recursive inverse's bp x (bp / 2 + 64) temporary (the larger)
+    const int64_t nbk = bp / 64;
+    const size_t ftemp = sizeof(double) * std::max<int64_t>(
+        4096 * (2 + nbk * (nbk - 1) / 2), (int64_t)bp * (nbk / 2 + 1) * 64);
     for (int w = 0; w < 2; ++w) {
-      A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttemp[w]);
+      A(ftemp, (void**)&I.ttemp[w]);
       A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
     }
     A(sizeof(double) * (I.dim + 1), (void**)&I.theta);
@@ -1286,8 +1320,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
     if (I.two) {
       A(tip, (void**)&I.PcB);
-      for (int w = 0; w < 2; ++w)
-        A(sizeof(double) * bp * (int64_t)((bp / 64) / 2 + 1) * 64, (void**)&I.ttempB[w]);
+      for (int w = 0; w < 2; ++w) A(ftemp, (void**)&I.ttempB[w]);
       A(sizeof(double) * I.ldbr, (void**)&I.uB);
       A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpartB);
       A(sizeof(double) * (ap > 0 ? ap : 1), (void**)&I.xPB);
