@@ -44,6 +44,9 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--skip-uneven", action="store_true")
     ap.add_argument("--skip-fd", action="store_true")
+    ap.add_argument("--order", choices=("one-sided", "two-sided"), default="one-sided",
+                    help="elimination order of every workspace (two-sided: the two "
+                         "halves of the time domain concurrently toward a middle block)")
     ap.add_argument("--tiles", default=os.path.join(root, "paper_2507_06938_amd",
                                                     "tiles_gfx950.txt"))
     args = ap.parse_args(argv)
@@ -68,15 +71,16 @@ def main(argv=None):
             pts[1 + 2 * i, i] += h
             pts[2 + 2 * i, i] -= h
         th = torch.tensor(pts, dtype=torch.float64, device="cuda")
-        res = {"workload": wl.name, "points": 2 * d + 1}
-        single = D.Workspace(model)
+        res = {"workload": wl.name, "points": 2 * d + 1, "order": args.order}
+        two = args.order == "two-sided"
+        single = D.Workspace(model, two_sided=two, fold_inverse=True)
         single.autotune(args.tiles)
         t1 = timed(lambda: single.fobj(th[:1]), args.reps)
         res["single_fp64_evals_per_s"] = 1.0 / t1
         del single
         torch.cuda.empty_cache()
         for mixed in (False, True):
-            ws = D.Workspace([model] * (2 * d + 1), graph=True, mixed=mixed)
+            ws = D.Workspace([model] * (2 * d + 1), graph=True, mixed=mixed, two_sided=two)
             ws.autotune(args.tiles)
             t = timed(lambda: ws.fobj(th), args.reps)
             f, parts, info = ws.fobj(th)
@@ -111,7 +115,8 @@ def main(argv=None):
                 waves.append(cur)
             total_t, ok, gb = 0.0, True, []
             for wave in waves:
-                ws = D.Workspace([models[k] for k in wave], graph=True, mixed=mixed)
+                ws = D.Workspace([models[k] for k in wave], graph=True, mixed=mixed,
+                                 two_sided=args.order == "two-sided")
                 ws.autotune(args.tiles)
                 th = np.concatenate([wls[k].theta for k in wave])
                 t = timed(lambda: ws.fobj(th), args.reps)
