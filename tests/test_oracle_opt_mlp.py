@@ -289,3 +289,26 @@ def test_skew_correction_in_one_dimension_is_the_split_normal():
     assert abs(up[0] - a * s_plus) < 1e-12 and abs(dn[0] - a * s_minus) < 1e-12
     with pytest.raises(ValueError):
         OH.skew_scales(0.0, [0.5, -1.0], 1.0)     # f rises: not a mode
+
+
+def test_gpu_hessian_driver_host_logic_matches_oracle():
+    """The Hessian driver's host-side steps (stencil order, second
+    differences, reparametrisation axes, asymmetric standard deviations)
+    against the oracle's independent code, on synthetic values."""
+    from paper_2507_06938_amd import hessian as GH
+    rng = np.random.default_rng(17)
+    d, h = 4, 1e-3
+    x = rng.standard_normal(d)
+    np.testing.assert_array_equal(GH.stencil_points(x, h), OH.hessian_stencil(x, h))
+    vals = rng.standard_normal(2 * d * d + 1)
+    np.testing.assert_allclose(GH.second_differences(vals, d, h),
+                               OH.hessian_from_values(vals, d, h), rtol=1e-12, atol=1e-6)
+    H = -(lambda B: B @ B.T + d * np.eye(d))(rng.standard_normal((d, d)))
+    np.testing.assert_allclose(GH.reparam_axes(H), OH.eigen_axes(H), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(GH.marginal_sd(H), OH.gaussian_marginal_sd(H), rtol=1e-12)
+    A = OH.eigen_axes(H)
+    sp, sm = rng.uniform(0.5, 2.0, d), rng.uniform(0.5, 2.0, d)
+    for got, want in zip(GH.skew_sd(A, sp, sm), OH.asymmetric_sd(A, sp, sm)):
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+    with pytest.raises(ValueError):
+        GH.reparam_axes(-H)
