@@ -312,3 +312,57 @@ def test_gpu_hessian_driver_host_logic_matches_oracle():
         np.testing.assert_allclose(got, want, rtol=1e-12)
     with pytest.raises(ValueError):
         GH.reparam_axes(-H)
+
+
+class _AnalyticEvaluator:
+    """Stands in for the batched GPU evaluator of the mode-search driver:
+    the same call interface (rows of theta in, values of F out, `ntrial`
+    points per line-search pass, a running count), values from a smooth
+    analytic function."""
+
+    def __init__(self, F, ntrial=4):
+        self.F = F
+        self.ntrial = ntrial
+        self.count = 0
+
+    def __call__(self, thetas):
+        thetas = np.atleast_2d(np.asarray(thetas, np.float64))
+        self.count += thetas.shape[0]
+        return np.array([self.F(t) for t in thetas])
+
+
+def _smooth_convex(d, seed):
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((d, d))
+    A = B @ B.T / d + 0.5 * np.eye(d)
+    b = rng.standard_normal(d)
+    return lambda x: float(0.5 * x @ A @ x - b @ x + 0.3 * np.sum(np.log(np.cosh(2.0 * x))))
+
+
+@pytest.mark.parametrize("d,seed,x0", [(4, 31, 3.0), (6, 32, -2.5)])
+def test_fd_bfgs_driver_host_logic_matches_oracle(d, seed, x0):
+    """The mode-search driver's host-side steps (stencil, Eq. 10 gradient,
+    capped quasi-Newton direction, Armijo ladder evaluated a pass at a time,
+    scaled first inverse Hessian, stopping rule) follow the oracle's BFGS
+    iterate for iterate: on the same function both visit the same points."""
+    from paper_2507_06938_amd import optimize as GO
+    F = _smooth_convex(d, seed)
+    h = 1e-3
+    theta0 = np.full(d, x0) + 0.1 * np.arange(d)
+    np.testing.assert_array_equal(GO.fd_points(theta0, h), OB.fd_stencil(theta0, h))
+    vals = np.array([F(p) for p in OB.fd_stencil(theta0, h)])
+    ev = _AnalyticEvaluator(F)
+    F0, g0 = GO.fd_gradient(ev, theta0, h)
+    assert F0 == vals[0] and ev.count == 2 * d + 1
+    np.testing.assert_array_equal(g0, OB.central_gradient_from_values(vals, h))
+
+    ev = _AnalyticEvaluator(F)
+    tr = GO.fd_bfgs(ev, theta0, h=h, ftol=1e-12, gtol=1e-7, max_iter=60)
+    fg = lambda t: (F(t), OB.central_gradient(F, t, h))
+    x_ref, f_ref, hist = OB.bfgs_minimize(fg, theta0, max_iter=60, ftol=1e-12, gtol=1e-7)
+    assert len(tr.theta) == len(hist) > 3
+    for k, (x, rec) in enumerate(zip(tr.theta, hist)):
+        np.testing.assert_allclose(x, rec["x"], rtol=1e-13, atol=1e-13, err_msg=str(k))
+        assert abs(tr.f[k] - rec["f"]) <= 1e-13 * max(1.0, abs(rec["f"])), k
+    # the start is several unit steps from the mode: the cap was active
+    assert np.linalg.norm(tr.theta[1] - tr.theta[0]) == pytest.approx(1.0, abs=1e-12)
