@@ -13,6 +13,8 @@ Modules:
   linalg  -- dense and RCM+banded Cholesky (log-determinant, solve,
              selected diagonal of the inverse)
   fobj    -- f_obj(theta) of Eq. 8 and its parts
+  laplace -- f_obj for a non-Gaussian (Poisson) likelihood: Newton search
+             for the inner mode, Laplace approximation (Eq. 3, 4, 8)
   bfgs    -- central differences (Eq. 10) and BFGS on -f_obj (Eq. 9)
   mlp     -- FP64 reference of the surrogate network
 """

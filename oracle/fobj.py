@@ -29,7 +29,14 @@ from .linalg import factor, NotSPD
 def fobj_parts(wl, theta, method: str = "auto", x=None,
                return_factors: bool = False) -> dict:
     """All parts of f_obj(theta) at x (default x = mu).  Returns -inf for f
-    and ``spd=False`` when Q_p or Q_c is not positive definite."""
+    and ``spd=False`` when Q_p or Q_c is not positive definite.  Workloads of
+    a non-Gaussian likelihood go to ``laplace.fobj_parts_laplace`` (x = the
+    inner mode; a given x is not supported there)."""
+    if M.likelihood_family(wl) != "gaussian":
+        if x is not None:
+            raise ValueError("x is the inner mode for a non-Gaussian likelihood")
+        from .laplace import fobj_parts_laplace
+        return fobj_parts_laplace(wl, theta, method)
     theta = np.asarray(theta, np.float64)
     Qp = M.prior_precision(wl, theta)
     A = M.design_matrix(wl)

@@ -38,15 +38,23 @@ def n_lambda(nv: int) -> int:
     return nv * (nv - 1) // 2
 
 
-def theta_dim(nv: int) -> int:
-    return 4 if nv == 1 else 4 * nv + n_lambda(nv)
+LIKELIHOODS = ("gaussian", "poisson")
 
 
-def theta_to_params(theta, nv: int, model: str = "separable") -> dict:
+def theta_dim(nv: int, likelihood: str = "gaussian") -> int:
+    """Gaussian responses carry one noise precision each; Poisson responses
+    have no likelihood hyperparameter."""
+    base = 4 if nv == 1 else 4 * nv + n_lambda(nv)
+    return base - nv if likelihood == "poisson" else base
+
+
+def theta_to_params(theta, nv: int, model: str = "separable",
+                    likelihood: str = "gaussian") -> dict:
     """Internal theta -> model parameters.
 
     Univariate: [log kappa, phi, log tau_u, log tau_y].
     Coregional: [log kappa_i, phi_i, log sigma_i, lambda_k, log tau_y_j].
+    A Poisson likelihood drops the trailing log tau_y slots (tau_y = None).
     rho = tanh(phi/2) inverts phi = log((1+rho)/(1-rho)), which keeps the AR1
     coefficient inside (-1, 1) for every real phi.  Optimisation is
     unconstrained over theta (Eq. 9).
@@ -57,19 +65,22 @@ def theta_to_params(theta, nv: int, model: str = "separable") -> dict:
     meaning, so the dimension of theta does not change.
     """
     th = np.asarray(theta, dtype=np.float64)
-    assert th.shape == (theta_dim(nv),)
+    if likelihood not in LIKELIHOODS:
+        raise ValueError(f"unknown likelihood {likelihood!r}")
+    assert th.shape == (theta_dim(nv, likelihood),)
     if model not in ("separable", "diffusion"):
         raise ValueError(f"unknown model family {model!r}")
+    gauss = likelihood == "gaussian"
     if nv == 1:
         out = dict(sigma=np.array([1.0 / math.sqrt(math.exp(th[2]))]),
-                   lam=np.zeros(0), tau_y=np.exp(th[3:4]),
+                   lam=np.zeros(0), tau_y=np.exp(th[3:4]) if gauss else None,
                    tau_u=math.exp(th[2]))
         head = (th[0:1], th[1:2])
     else:
         k = 2 * nv
         sigma = np.exp(th[k:k + nv]); k += nv
         lam = th[k:k + n_lambda(nv)].copy(); k += n_lambda(nv)
-        tau_y = np.exp(th[k:k + nv])
+        tau_y = np.exp(th[k:k + nv]) if gauss else None
         out = dict(sigma=sigma, lam=lam, tau_y=tau_y, tau_u=None)
         head = (th[0:nv], th[nv:2 * nv])
     if model == "diffusion":
@@ -256,6 +267,10 @@ def model_family(wl) -> str:
     return getattr(wl, "model", "separable")
 
 
+def likelihood_family(wl) -> str:
+    return getattr(wl, "likelihood", "gaussian")
+
+
 def prior_precision(wl, theta) -> sp.csr_matrix:
     """Q_p(theta) in model order.
 
@@ -267,7 +282,7 @@ def prior_precision(wl, theta) -> sp.csr_matrix:
     puts ``diffusion_precision`` in place of T (x) Q_s.
     """
     nv, nx, nt = wl.nv, wl.nx, wl.nt
-    p = theta_to_params(theta, nv, model_family(wl))
+    p = theta_to_params(theta, nv, model_family(wl), likelihood_family(wl))
     nst = nx * nx * nt
     if nv == 1:
         Qz = p["tau_u"] * process_precision(wl, p, 0)
@@ -318,7 +333,10 @@ def design_matrix(wl) -> sp.csr_matrix:
 
 def noise_precision(wl, theta) -> np.ndarray:
     """Diagonal of D(theta): the Gaussian likelihood's negative Hessian, i.e.
-    tau_y_j for every row of response j (Eq. 4)."""
+    tau_y_j for every row of response j (Eq. 4).  Gaussian responses only:
+    for other likelihoods D depends on x (see ``oracle.laplace``)."""
+    if likelihood_family(wl) != "gaussian":
+        raise ValueError("D(theta) alone is defined for Gaussian responses only")
     p = theta_to_params(theta, wl.nv, model_family(wl))
     return np.concatenate([np.full(r.y.shape[0], p["tau_y"][j])
                            for j, r in enumerate(wl.responses)])

@@ -29,6 +29,12 @@ with phi = log((1+rho)/(1-rho)).  A workload of the diffusion-based
 (non-separable) space-time model (``model="diffusion"``) puts log gamma_s and
 log gamma_t of each process in the slots of log kappa and phi; the other
 slots keep their meaning.
+
+A workload with ``likelihood="poisson"`` holds counts instead of Gaussian
+responses and its theta has no log tau_y slots.  Its counts are drawn as
+Poisson(exp(eta)) with the log rate eta = log(3) + 0.3 s + 0.3 X beta, s
+the smooth random space-time signal below at the row's cell and time, beta
+iid N(0,1): rates of about 1 to 10, zeros included.
 """
 from __future__ import annotations
 
@@ -63,6 +69,7 @@ class Workload:
     prior_fixed: float = 1e-3     # precision of each fixed effect
     seed: int = 0
     model: str = "separable"      # or "diffusion" (non-separable)
+    likelihood: str = "gaussian"  # or "poisson" (counts)
 
     @property
     def ns(self) -> int:
@@ -86,9 +93,8 @@ class Workload:
 
     @property
     def dim_theta(self) -> int:
-        if self.nv == 1:
-            return 4
-        return 4 * self.nv + self.nv * (self.nv - 1) // 2
+        base = 4 if self.nv == 1 else 4 * self.nv + self.nv * (self.nv - 1) // 2
+        return base - self.nv if self.likelihood == "poisson" else base
 
 
 def _phi(rho: float) -> float:
@@ -127,31 +133,45 @@ def _smooth_signal(rng: np.random.Generator, nx: int, nt: int, cells, t,
     return out
 
 
-def _check_model(model: str) -> None:
+def _check_model(model: str, likelihood: str = "gaussian") -> None:
     if model not in ("separable", "diffusion"):
         raise ValueError(f"unknown model family {model!r}")
+    if likelihood not in ("gaussian", "poisson"):
+        raise ValueError(f"unknown likelihood {likelihood!r}")
+
+
+def _counts(rng: np.random.Generator, nx: int, nt: int, cells, t, X) -> np.ndarray:
+    """Poisson counts around a smooth log rate (see the module notes)."""
+    beta = rng.standard_normal(X.shape[1])
+    eta = math.log(3.0) + 0.3 * _smooth_signal(rng, nx, nt, cells, t) + 0.3 * (X @ beta)
+    return rng.poisson(np.exp(eta)).astype(np.float64)
 
 
 def make_univariate(name: str, nx: int, nt: int, nr: int, m: int, *,
                     kappa: float = 1.0, rho: float = 0.7, tau_u: float = 1.0,
                     tau_y: float = 4.0, seed: int = 0,
                     model: str = "separable", gamma_s: float = 1.0,
-                    gamma_t: float = 2.0) -> Workload:
-    """Univariate workload: responses y ~ N(0,1), one observation set.
+                    gamma_t: float = 2.0, likelihood: str = "gaussian") -> Workload:
+    """Univariate workload: responses y ~ N(0,1), one observation set (or
+    counts, ``likelihood="poisson"``).
     ``model="diffusion"`` takes gamma_s, gamma_t in place of kappa, rho."""
-    _check_model(model)
+    _check_model(model, likelihood)
     rng = np.random.default_rng(seed)
-    t, nodes, w, X, _ = _draw_rows(rng, nx, nt, m, nr)
-    y = rng.standard_normal(m)
+    t, nodes, w, X, cells = _draw_rows(rng, nx, nt, m, nr)
+    if likelihood == "poisson":
+        y = _counts(rng, nx, nt, cells, t, X)
+    else:
+        y = rng.standard_normal(m)
     if model == "diffusion":
         head = [math.log(gamma_s), math.log(gamma_t)]
     else:
         head = [math.log(kappa), _phi(rho)]
-    theta = np.array(head + [math.log(tau_u), math.log(tau_y)])
+    tail = [math.log(tau_y)] if likelihood == "gaussian" else []
+    theta = np.array(head + [math.log(tau_u)] + tail)
     return Workload(name=name, nx=nx, nt=nt, nv=1, nr=nr,
                     responses=[Response(t, nodes, w, X, y)],
                     theta=theta, theta_prior_mean=theta.copy(), seed=seed,
-                    model=model)
+                    model=model, likelihood=likelihood)
 
 
 def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
@@ -159,7 +179,8 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
                     tau_y=(4.0, 4.0, 4.0), seed: int = 0,
                     nv: int = 3, model: str = "separable",
                     gamma_s=(0.5, 1.0, 2.0),
-                    gamma_t=(1.0, 2.0, 4.0)) -> Workload:
+                    gamma_t=(1.0, 2.0, 4.0),
+                    likelihood: str = "gaussian") -> Workload:
     """Coregional workload with nv responses.
 
     sigma_i = max(|z|, 0.5) and lambda_i ~ N(0,1) play the role of the
@@ -168,8 +189,9 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
     each row, plus covariate effects, plus N(0, 1/tau_y) noise, so that the
     optimum of the objective lies inside the parameter space.
     ``model="diffusion"`` takes gamma_s, gamma_t in place of kappa, rho.
+    ``likelihood="poisson"``: counts per response (module notes), no tau_y.
     """
-    _check_model(model)
+    _check_model(model, likelihood)
     rng = np.random.default_rng(seed)
     z = rng.standard_normal(nv)
     sigma = np.maximum(np.abs(z), 0.5)
@@ -180,6 +202,9 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
         responses.append([t, nodes, w, X, cells])
     for j in range(nv):
         t, nodes, w, X, cells = responses[j]
+        if likelihood == "poisson":
+            responses[j] = Response(t, nodes, w, X, _counts(rng, nx, nt, cells, t, X))
+            continue
         beta = rng.standard_normal(nr)
         sig = _smooth_signal(rng, nx, nt, cells, t)
         noise = rng.standard_normal(m_per) / math.sqrt(tau_y[j])
@@ -191,11 +216,12 @@ def make_trivariate(name: str, nx: int, nt: int, nr: int, m_per: int, *,
     else:
         head = [np.log(np.asarray(kappa[:nv])),
                 np.array([_phi(r) for r in rho[:nv]])]
-    theta = np.concatenate(head + [np.log(sigma), lam,
-                                   np.log(np.asarray(tau_y[:nv]))])
+    tail = [np.log(np.asarray(tau_y[:nv]))] if likelihood == "gaussian" else []
+    theta = np.concatenate(head + [np.log(sigma), lam] + tail)
     return Workload(name=name, nx=nx, nt=nt, nv=nv, nr=nr,
                     responses=responses, theta=theta,
-                    theta_prior_mean=theta.copy(), seed=seed, model=model)
+                    theta_prior_mean=theta.copy(), seed=seed, model=model,
+                    likelihood=likelihood)
 
 
 # --- the named configurations ------------------------------------------------
@@ -224,12 +250,14 @@ def config2(seed: int = 0, model: str = "separable") -> Workload:
 
 
 def scaled(name: str, nx: int, nt: int, nv: int, nr: int, m_per: int,
-           seed: int = 0, model: str = "separable") -> Workload:
+           seed: int = 0, model: str = "separable",
+           likelihood: str = "gaussian") -> Workload:
     """Same generator at other sizes (parity cases, edge cases)."""
     if nv == 1:
-        return make_univariate(name, nx, nt, nr, m_per, seed=seed, model=model)
+        return make_univariate(name, nx, nt, nr, m_per, seed=seed, model=model,
+                               likelihood=likelihood)
     return make_trivariate(name, nx, nt, nr, m_per, seed=seed, nv=nv,
-                           model=model)
+                           model=model, likelihood=likelihood)
 
 
 def uneven_instance(k: int) -> Workload:
