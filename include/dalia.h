@@ -76,6 +76,7 @@ typedef struct dl_model_desc {
   int32_t family;                 /* DL_MODEL_SEPARABLE (0, what a zeroed
                                      descriptor selects) or
                                      DL_MODEL_DIFFUSION                    */
+  int32_t likelihood;             /* DL_LIK_GAUSSIAN (0) or DL_LIK_POISSON */
 } dl_model_desc;
 
 /* Model families of each univariate process (Section II-A; Section III-B,
@@ -93,16 +94,41 @@ typedef struct dl_model_desc {
  *                       distance 3 (25 points) instead of 2 (13 points). */
 enum { DL_MODEL_SEPARABLE = 0, DL_MODEL_DIFFUSION = 1 };
 
+/* Likelihood of the responses (Section II-B, conditional Gaussian
+ * distribution: D in Q_c = Q_p + A^T D A is the negative Hessian of the
+ * log-likelihood, Eq. 4).
+ *   DL_LIK_GAUSSIAN  y_i ~ N((A x)_i, 1/tau_y_j) (Eq. 2): D = tau_y, p_G is
+ *                    exact and its mean solves Q_c mu = A^T D y.
+ *   DL_LIK_POISSON   counts y_i ~ Poisson(exp((A x)_i)) (log link): D
+ *                    depends on x, so fobj_eval first finds the mode x* of
+ *                    h(x) = log l(y | A x) - 1/2 x^T Q_p x by damped Newton
+ *                    from x = 0 (see fobj_eval) and evaluates Eq. 8 there
+ *                    (Laplace approximation).  theta has no log tau_y
+ *                    slots; every y must be a non-negative integer. */
+enum { DL_LIK_GAUSSIAN = 0, DL_LIK_POISSON = 1 };
+
+/* Inner Newton iteration of DL_LIK_POISSON models: stop after a full step
+ * with max|x_N - x| <= DL_NEWTON_TOL (1 + max|x_N|); at most
+ * DL_NEWTON_MAX steps, each halved at most DL_NEWTON_HALVINGS times until
+ * h(new) >= h(x) - DL_ASCENT_SLACK (1 + |h(x)|). */
+#define DL_NEWTON_TOL 1e-9
+#define DL_NEWTON_MAX 40
+#define DL_NEWTON_HALVINGS 30
+#define DL_ASCENT_SLACK 1e-12
+
 /* Parts of f_obj (Eq. 8) written by fobj_eval, one record per theta. */
 typedef struct dl_fobj_parts {
   double f;          /* f_obj(theta)                                   */
   double logdet_p;   /* log|Q_p|                                       */
   double logdet_c;   /* log|Q_c|                                       */
   double quad_p;     /* mu^T Q_p mu                                    */
-  double quad_obs;   /* (y - A mu)^T D (y - A mu)                      */
+  double quad_obs;   /* (y - A mu)^T D (y - A mu); Poisson: -2 log l(y|mu)
+                        (log(y!) included)                             */
   double log_prior;  /* log p(theta)                                   */
-  double log_lik_const; /* sum_j m_j/2 log tau_j - m/2 log(2 pi)      */
-  double rel_residual;  /* |A^T D y - Q_c mu| / |A^T D y| of the final mu */
+  double log_lik_const; /* sum_j m_j/2 log tau_j - m/2 log(2 pi); Poisson: 0 */
+  double rel_residual;  /* |A^T D y - Q_c mu| / |A^T D y| of the final mu;
+                           Poisson: |A^T g - Q_p mu| / |A^T (g + D A mu)|
+                           at the mode (g: the log-likelihood's gradient) */
 } dl_fobj_parts;
 
 /* Number of hyperparameters: 4 for nv = 1, 4*nv + nv(nv-1)/2 otherwise.
@@ -112,12 +138,17 @@ typedef struct dl_fobj_parts {
  * DL_MODEL_DIFFUSION reads log gamma_s in the slots of log kappa and
  * log gamma_t in the slots of phi; the other slots keep their meaning. */
 int32_t dl_theta_dim(int32_t nv);
+/* The same for a likelihood: DL_LIK_POISSON drops the nv log tau_y slots
+ * (3 for nv = 1, 3*nv + nv(nv-1)/2 otherwise); -1 for an unknown value. */
+int32_t dl_theta_dim_lik(int32_t nv, int32_t likelihood);
 
 /* Upload a model.  Builds the spatial pattern (Section II-A, SPDE FEM) and
  * per-(response, time, node) observation index lists on the host (integer
  * work only) and copies all arrays to the device.  nv in {1,2,3}; nx >= 2;
  * nt >= 1 (>= 2 for DL_MODEL_DIFFUSION); nr >= 0; every obs_t < nt and every
- * node < nx*nx; family one of the DL_MODEL_* values.  DL_EINVAL otherwise. */
+ * node < nx*nx; family one of the DL_MODEL_* values; likelihood one of the
+ * DL_LIK_* values (DL_LIK_POISSON: every y a non-negative integer).
+ * DL_EINVAL otherwise. */
 dl_status dl_model_create(const dl_model_desc* desc_host, dl_model** out);
 void dl_model_destroy(dl_model* model);
 
@@ -191,11 +222,18 @@ void dl_ws_destroy(dl_ws* ws);
 /* Device bytes held by the workspace. */
 size_t dl_ws_bytes(const dl_ws* ws);
 
+/* Newton steps taken per instance in the last fobj_eval/fobj_selinv_eval
+ * pass of a DL_LIK_POISSON workspace (-1: not converged); steps_host holds
+ * dl_ws_batch(ws) values.  Gaussian workspaces report 0. */
+dl_status dl_ws_newton_steps(const dl_ws* ws, int32_t* steps_host);
+
 /* bta_assemble -- step a1+a2: theta (dim_theta doubles, device) ->
  * coefficient table and log p(theta), then the dense BTA blocks of Q_p and/or
  * Q_c (Eq. 4, Eq. 11, time-major permutation of Section III-B) and the
  * right-hand side A^T D y.  Only the lower triangle of each diagonal block
- * is stored. */
+ * is stored.  For DL_LIK_POISSON models D and the right-hand side come
+ * from the workspace's last inner iterate (D = 0 before the first
+ * fobj_eval). */
 dl_status bta_assemble(dl_ws* ws, const double* theta_dev, dl_which which,
                        void* stream);
 
@@ -226,7 +264,22 @@ dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
  * receive the results.  A batch workspace of B instances evaluates B thetas
  * per pass (ntheta may be any count when all instances share one model;
  * otherwise ntheta must equal B).  mu of the last pass stays in the
- * workspace. */
+ * workspace.
+ *
+ * DL_LIK_POISSON workspaces (every instance's model must have it) find the
+ * inner mode first, each Newton step as kernels over all instances of the
+ * pass: the observation weights D = exp(A x) and working values
+ * g + D A x from the current iterate, assembly of Q_c(x) and A^T (g + D A x),
+ * its factorisation and solve (x_N), then trial points x + alpha (x_N - x)
+ * with h evaluated by the quadratic-form kernels; the host reads 4 values
+ * per instance per trial to pick alpha and to stop.  An instance that has
+ * converged keeps its iterate while the others continue (so batch results
+ * equal single evaluations).  Q_c is then assembled and factored at x*
+ * (its factor serves bta_selinv) and Eq. 8 is evaluated at mu = x*; an
+ * instance that did not converge gets f = -inf.  These passes run eagerly
+ * (also for DL_WS_GRAPH workspaces) and synchronise the stream once per
+ * trial.  DL_WS_MIXED is not supported with DL_LIK_POISSON (DL_EINVAL at
+ * dl_ws_create). */
 dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                     double* fobj_dev, dl_fobj_parts* parts_dev,
                     int64_t* info_dev, void* stream);

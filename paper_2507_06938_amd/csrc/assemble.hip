@@ -37,11 +37,13 @@ __global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
       Li[i][j] = 0.0;
       for (int k = 0; k < 3; ++k) Mw[i][j][k] = 0.0;
     }
+  // Poisson responses have no noise precision in theta (tau = 1, unused)
+  const bool gauss = m.likelihood == DL_LIK_GAUSSIAN;
   if (nv == 1) {
     kap[0] = exp(theta[0]);
     rho[0] = tanh(0.5 * theta[1]);
     const double tau_u = exp(theta[2]);
-    tau[0] = exp(theta[3]);
+    tau[0] = gauss ? exp(theta[3]) : 1.0;
     Mw[0][0][0] = tau_u;
   } else {
     const int nl = nv * (nv - 1) / 2;
@@ -50,7 +52,7 @@ __global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
       kap[i] = exp(theta[i]);
       rho[i] = tanh(0.5 * theta[nv + i]);
       sg[i] = exp(theta[2 * nv + i]);
-      tau[i] = exp(theta[3 * nv + nl + i]);
+      tau[i] = gauss ? exp(theta[3 * nv + nl + i]) : 1.0;
     }
     for (int k = 0; k < nl; ++k) lam[k] = theta[3 * nv + k];
     // Lambda of Eq. 5 (nv = 2 keeps its leading 2x2 block)
@@ -142,7 +144,7 @@ __global__ void k_theta_coeffs(const ThetaJob* __restrict__ jobs) {
   double llc = 0.0;
   for (int j = 0; j < nv; ++j) {
     const double mj = (double)(m.m_off[j + 1] - m.m_off[j]);
-    llc += 0.5 * mj * log(tau[j]) - 0.5 * mj * log(two_pi);
+    if (gauss) llc += 0.5 * mj * log(tau[j]) - 0.5 * mj * log(two_pi);
     coef[C_TAU + j] = tau[j];
   }
   for (int d = 0; d < m.dim_theta; ++d)
@@ -164,7 +166,8 @@ hipError_t launch_theta_coeffs(const ThetaJob* jobs, int count, hipStream_t s) {
 // and coalesced, to the dense blocks: the diagonal block D_t (lower triangle;
 // rows above c are written as zero), the sub-diagonal block B_t of rows t+1,
 // and for Q_c the arrow block R_t.  Q_c's column is Q_p's plus the
-// observation terms tau_j w w^T (Eq. 4), added by one thread in a fixed order
+// observation terms tau_j w w^T (Eq. 4; d_row w w^T with the per-row weights
+// of a non-Gaussian likelihood), added by one thread in a fixed order
 // so the result does not depend on scheduling.  Padding columns c >= b
 // (up to the padded block size bp) carry a unit diagonal, which leaves the
 // log-determinant unchanged.
@@ -237,6 +240,8 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
   __syncthreads();
   if (tid == 0) {
     const double tau = J.coef[C_TAU + j];
+    const double* __restrict__ od = o.obs_d;
+    const double* __restrict__ oz = o.obs_z;
     const int64_t key = ((int64_t)j * m.nt + t) * ns + s;
     double racc = 0.0;
     const int nr = m.nr;
@@ -244,13 +249,14 @@ __global__ __launch_bounds__(256) void k_assemble_cols(const AsmJob* __restrict_
       const int64_t row = m.no_row[p];
       const int qs = m.no_q[p];
       const double wq = m.obs_w[row * 3 + qs];
+      const double wr = od ? od[row] : tau;
       for (int q2 = 0; q2 < 3; ++q2) {
         const int r = j * ns + m.obs_nodes[row * 3 + q2];
-        colD[r] += tau * m.obs_w[row * 3 + q2] * wq;
+        colD[r] += wr * m.obs_w[row * 3 + q2] * wq;
       }
       for (int rr = 0; rr < nr; ++rr)
-        colR[j * nr + rr] += tau * m.obs_x[row * nr + rr] * wq;
-      racc += tau * wq * m.obs_y[row];
+        colR[j * nr + rr] += wr * m.obs_x[row * nr + rr] * wq;
+      racc += od ? wq * oz[row] : tau * wq * m.obs_y[row];
     }
     rhs_s = racc;
   }
@@ -312,10 +318,15 @@ __global__ __launch_bounds__(256) void k_assemble_tip(const AsmJob* __restrict__
     r2 = 0;
   }
   const int64_t b0 = m.m_off[j], b1 = m.m_off[j + 1];
+  const double* __restrict__ od = o.obs_d;
+  const double* __restrict__ oz = o.obs_z;
   double acc = 0.0;
   for (int64_t row = b0 + tid; row < b1; row += 256) {
     const double xr = m.obs_x[row * nr + r];
-    acc += gram ? xr * m.obs_x[row * nr + r2] : xr * m.obs_y[row];
+    if (od)  // per-row weights: sum d x_r x_r2 and x_r z, no tau
+      acc += gram ? od[row] * xr * m.obs_x[row * nr + r2] : xr * oz[row];
+    else
+      acc += gram ? xr * m.obs_x[row * nr + r2] : xr * m.obs_y[row];
   }
   sh[tid] = acc;
   __syncthreads();
@@ -324,7 +335,7 @@ __global__ __launch_bounds__(256) void k_assemble_tip(const AsmJob* __restrict__
     __syncthreads();
   }
   if (tid == 0) {
-    const double tau = coef[C_TAU + j];
+    const double tau = od ? 1.0 : coef[C_TAU + j];
     if (gram) {
       const int rr = j * nr + r, cc = j * nr + r2;
       o.Pc[rr + (int64_t)cc * ap] = tau * sh[0] + (rr == cc ? m.prior_fixed : 0.0);
@@ -368,8 +379,9 @@ hipError_t launch_assemble_tips(const AsmJob* jobs, int count, int max_blocks,
 // responses j and spatial neighbours s of coef(t,t')_{kj} . (C, G, GC^-1G,
 // GC^-1GC^-1G) at (s', s) times mu(t', j, s); fixed effects add
 // prior_fixed * |mu_f|^2.
-// (y - A mu)^T D (y - A mu) row by row.  Both are reduced with a fixed tree
-// per block, then over blocks in order.
+// (y - A mu)^T D (y - A mu) row by row (Poisson: -2 log l(y | A mu) with
+// log(y!) = lgamma(y + 1)).  Both are reduced with a fixed tree per block,
+// then over blocks in order.
 __device__ __forceinline__ double blk_sum(double v, double* sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -444,8 +456,13 @@ __global__ __launch_bounds__(256) void k_quad_obs(const QuadJob* __restrict__ jo
     for (int q = 0; q < 3; ++q) pred += m.obs_w[row * 3 + q] * x[m.obs_nodes[row * 3 + q]];
     const double* xf = mu + (int64_t)m.nt * bp + j * nr;
     for (int r = 0; r < nr; ++r) pred += m.obs_x[row * nr + r] * xf[r];
-    const double res = m.obs_y[row] - pred;
-    acc += coef[C_TAU + j] * res * res;
+    const double y = m.obs_y[row];
+    if (m.likelihood == DL_LIK_POISSON) {
+      acc += -2.0 * (y * pred - exp(pred) - lgamma(y + 1.0));
+    } else {
+      const double res = y - pred;
+      acc += coef[C_TAU + j] * res * res;
+    }
   }
   const double s = blk_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -576,7 +593,7 @@ __global__ __launch_bounds__(256) void k_res_av(const ResJob* __restrict__ jobs)
     for (int q = 0; q < 3; ++q) a += m.obs_w[row * 3 + q] * x[m.obs_nodes[row * 3 + q]];
     const double* xf = R.v + (int64_t)m.nt * bp + j * nr;
     for (int r = 0; r < nr; ++r) a += m.obs_x[row * nr + r] * xf[r];
-    R.av[row] = R.coef[C_TAU + j] * a;
+    R.av[row] = (R.obs_d ? R.obs_d[row] : R.coef[C_TAU + j]) * a;
   }
 }
 
@@ -685,6 +702,104 @@ hipError_t launch_residual(const ResJob* jobs, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_res_rows, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
   hipLaunchKernelGGL(k_res_tip, dim3(3 * 64 + 1, count), dim3(256), 0, s, jobs);
   hipLaunchKernelGGL(k_res_final, dim3(count), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+// ---- inner Newton iteration of a Poisson likelihood -----------------------------
+//
+// Observation weights from the current iterate x: eta = (A x)_row (its three
+// barycentric nodes at its time step and its covariates), D = exp(eta) and
+// the right-hand-side value z = (y - exp(eta)) + D eta, which the assembly
+// gathers into A^T z.
+__global__ __launch_bounds__(256) void k_lap_weights(const LapJob* __restrict__ jobs) {
+  const LapJob J = jobs[blockIdx.y];
+  const ModelDev& m = *J.m;
+  const int ns = m.ns, nr = m.nr, bp = m.bp;
+  for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < m.m_total;
+       row += (int64_t)gridDim.x * 256) {
+    int j = 0;
+    while (j + 1 < m.nv && row >= m.m_off[j + 1]) ++j;
+    const int t = m.obs_t[row];
+    const double* x = J.x + (int64_t)t * bp + j * ns;
+    double eta = 0.0;
+    for (int q = 0; q < 3; ++q) eta += m.obs_w[row * 3 + q] * x[m.obs_nodes[row * 3 + q]];
+    const double* xf = J.x + (int64_t)m.nt * bp + j * nr;
+    for (int r = 0; r < nr; ++r) eta += m.obs_x[row * nr + r] * xf[r];
+    const double d = exp(eta);
+    J.obs_d[row] = d;
+    J.obs_z[row] = (m.obs_y[row] - d) + d * eta;
+  }
+}
+
+hipError_t launch_lap_weights(const LapJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lap_weights, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double blk_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// mu = x + alpha (xN - x) over the padded vector (alpha = 0 keeps x exactly:
+// an instance that has converged), with the block maxima of |xN - x| and
+// |xN| (NaN propagates through fmax only when both operands are NaN, so a
+// non-finite entry is flagged as +inf).
+__global__ __launch_bounds__(256) void k_trial(const TrialJob* __restrict__ jobs) {
+  __shared__ double sh[256];
+  const TrialJob T = jobs[blockIdx.y];
+  const int64_t n = T.m->Np;
+  const double a = *T.alpha;
+  double dmax = 0.0, nmax = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const double xi = T.x[i], xn = T.xN[i];
+    T.mu[i] = (a == 0.0) ? xi : xi + a * (xn - xi);
+    const double dv = fabs(xn - xi), nv = fabs(xn);
+    dmax = fmax(dmax, isfinite(dv) ? dv : __builtin_inf());
+    nmax = fmax(nmax, isfinite(nv) ? nv : __builtin_inf());
+  }
+  const double d = blk_max(dmax, sh);
+  const double v = blk_max(nmax, sh);
+  if (threadIdx.x == 0) {
+    T.partial[blockIdx.x] = d;
+    T.partial[QF_BLOCKS + blockIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trial_gather(const TrialJob* __restrict__ jobs) {
+  __shared__ double sh[256];
+  const TrialJob T = jobs[blockIdx.x];
+  for (int w = 0; w < 2; ++w) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < QF_BLOCKS; i += 256) acc = fmax(acc, T.partial[w * QF_BLOCKS + i]);
+    const double r = blk_max(acc, sh);
+    if (threadIdx.x == 0) T.out4[w] = r;
+  }
+  if (threadIdx.x == 0) {
+    T.out4[2] = T.quad2[0];
+    T.out4[3] = T.quad2[1];
+  }
+}
+
+hipError_t launch_trial(const TrialJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trial, dim3(QF_BLOCKS, count), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trial_gather(const TrialJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trial_gather, dim3(count), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

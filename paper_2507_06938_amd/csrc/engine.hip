@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <new>
 #include <vector>
@@ -414,6 +415,12 @@ struct Inst {
   bool mixed = false;       // [B_t; R_t] in FP32, their products on FP32 MFMA
   int eb = 8;               // bytes per element of the [B_t; R_t] storage
   double *mu_acc = nullptr, *av = nullptr, *rpart = nullptr, *rnorm = nullptr;
+  // inner Newton iteration (Poisson likelihood): per-observation weights and
+  // right-hand-side values, the accepted iterate, the Newton target, the
+  // trial maxima's partials, and views of the workspace's alpha / out4
+  bool poisson = false;
+  double *obs_d = nullptr, *obs_z = nullptr, *xcur = nullptr, *xN = nullptr;
+  double *tpart = nullptr, *alpha = nullptr, *out4 = nullptr;
 };
 
 struct dl_ws {
@@ -431,6 +438,14 @@ struct dl_ws {
   double* f_all = nullptr;       // [B]
   double* parts_all = nullptr;   // [B x 8]
   int64_t* info_all = nullptr;   // [B x 2]
+  // inner Newton iteration (all instances Poisson, or none)
+  bool poisson = false;
+  double* alpha_all = nullptr;   // [B] step lengths of the current trial
+  double* out4_all = nullptr;    // [B x 4] trial results read by the host
+  LapJob* d_lap = nullptr;
+  TrialJob* d_trial = nullptr;
+  QuadJob* d_nquad = nullptr;
+  std::vector<int32_t> newton_steps;
   Descs H;
   DevDescs Dd;
   std::vector<Launch> table;
@@ -580,6 +595,10 @@ static void seq_assemble(dl_ws* W, Inst& I, bool p, bool c, std::vector<Step>& q
   tip.asmj.o.Pp = p ? I.Pp : nullptr;
   tip.asmj.o.Pc = c ? I.Pc : nullptr;
   tip.asmj.o.rhs = I.rhs;
+  if (c && I.poisson) {
+    tip.asmj.o.obs_d = I.obs_d;
+    tip.asmj.o.obs_z = I.obs_z;
+  }
   tip.gx = 1 + m.nv * m.nr * m.nr + m.nv * m.nr;
   q.push_back(tip);
   const bool full_p = p && !I.qp_ring;
@@ -605,6 +624,10 @@ static void seq_assemble(dl_ws* W, Inst& I, bool p, bool c, std::vector<Step>& q
     }
     J.o.rhs = I.rhs;
     J.o.b32 = I.mixed ? 1 : 0;
+    if (c && I.poisson) {
+      J.o.obs_d = I.obs_d;
+      J.o.obs_z = I.obs_z;
+    }
     s.gx = m.bp;
     s.gy = m.nt;
     q.push_back(s);
@@ -1062,6 +1085,7 @@ static Step res_step(uint64_t key, Inst& I, const double* v, double* out) {
   s.res.av = I.av;
   s.res.partial = I.rpart;
   s.res.norms = I.rnorm;
+  s.res.obs_d = I.poisson ? I.obs_d : nullptr;
   return s;
 }
 
@@ -1220,6 +1244,20 @@ static dl_status build_plans(dl_ws* W) {
   up(H.quad, W->Dd.quad);
   up(H.comb, W->Dd.comb);
   up(H.res, W->Dd.res);
+  if (W->poisson) {
+    std::vector<LapJob> lap;
+    std::vector<TrialJob> trial;
+    std::vector<QuadJob> nquad;
+    for (auto& I : W->inst) {
+      lap.push_back(LapJob{I.model->dev, I.xcur, I.obs_d, I.obs_z});
+      trial.push_back(TrialJob{I.model->dev, I.xcur, I.xN, I.mu, I.alpha, I.tpart,
+                               I.quad2, I.out4});
+      nquad.push_back(QuadJob{I.model->dev, I.coef, I.mu, I.qpart, I.quad2});
+    }
+    up(lap, W->d_lap);
+    up(trial, W->d_trial);
+    up(nquad, W->d_nquad);
+  }
   return st;
 }
 
@@ -1253,6 +1291,18 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->splitk = (flags & DL_WS_SPLITK) != 0;
   W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
   const bool two_sided = (flags & DL_WS_TWOSIDED) != 0;
+  // one likelihood per workspace; the Newton iteration needs FP64 storage
+  W->poisson = models[0]->d.likelihood == DL_LIK_POISSON;
+  for (int k = 0; k < nmodels; ++k)
+    if ((models[k]->d.likelihood == DL_LIK_POISSON) != W->poisson) {
+      delete W;
+      return DL_EINVAL;
+    }
+  if (W->poisson && W->mixed) {
+    delete W;
+    return DL_EINVAL;
+  }
+  W->newton_steps.assign(nmodels, 0);
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
   auto A = [&](size_t bytes, void** p) {
@@ -1318,6 +1368,18 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     A(sizeof(double) * m.Np, (void**)&I.mu);
     A(sizeof(double) * I.ldbr, (void**)&I.u);
     A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
+    I.poisson = W->poisson;
+    if (I.poisson) {
+      A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_d);
+      A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_z);
+      A(sizeof(double) * m.Np, (void**)&I.xcur);
+      A(sizeof(double) * m.Np, (void**)&I.xN);
+      A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.tpart);
+      if (st == DL_OK &&
+          (hipMemset(I.obs_d, 0, sizeof(double) * (m.m_total + 1)) != hipSuccess ||
+           hipMemset(I.obs_z, 0, sizeof(double) * (m.m_total + 1)) != hipSuccess))
+        st = DL_EHIP;
+    }
     if (I.two) {
       A(tip, (void**)&I.PcB);
       for (int w = 0; w < 2; ++w) A(ftemp, (void**)&I.ttempB[w]);
@@ -1344,6 +1406,10 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   A(sizeof(double) * nmodels, (void**)&W->f_all);
   A(sizeof(double) * 8 * nmodels, (void**)&W->parts_all);
   A(sizeof(int64_t) * 2 * nmodels, (void**)&W->info_all);
+  if (W->poisson) {
+    A(sizeof(double) * nmodels, (void**)&W->alpha_all);
+    A(sizeof(double) * 4 * nmodels, (void**)&W->out4_all);
+  }
   if (st != DL_OK) {
     ws_free(W);
     return st;
@@ -1356,6 +1422,11 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
       off += I.dim;
     }
   }
+  if (W->poisson)
+    for (int k = 0; k < nmodels; ++k) {
+      W->inst[k].alpha = W->alpha_all + k;
+      W->inst[k].out4 = W->out4_all + 4 * k;
+    }
   if (W->max_shmem * 8 > 160 * 1024 ||
       prepare_assemble(W->max_shmem) != hipSuccess) {
     ws_free(W);
@@ -1478,6 +1549,122 @@ extern "C" dl_status dl_ws_mean(dl_ws* W, double* out_dev, void* stream) {
   return DL_OK;
 }
 
+// ---- inner mode of a Poisson likelihood (Laplace approximation) ------------------
+//
+// Damped Newton for the mode x* of h(x) = log l(y | A x) - 1/2 x^T Q_p x
+// from x = 0, for the first nk instances (the rest stay idle): each step
+// assembles Q_c(x) = Q_p + A^T D(x) A and A^T (g + D A x) from the weights
+// of the current iterate, factors and solves (x_N), and tries
+// x + alpha (x_N - x) for alpha = 1, 1/2, ... until h does not fall (up to
+// rounding); h comes from the quadratic-form kernels at the trial point.
+// A converged or failed instance keeps its iterate (alpha = 0) while the
+// others continue.  Then Q_c(x*) is assembled and factored and Eq. 8 is
+// evaluated at mu = x*.
+static dl_status eval_trials(dl_ws* W, const std::vector<double>& alpha,
+                             std::vector<double>& out, hipStream_t s) {
+  const int B = (int)W->inst.size();
+  DL_HIP_CHECK(hipMemcpyAsync(W->alpha_all, alpha.data(), sizeof(double) * B,
+                              hipMemcpyHostToDevice, s));
+  DL_HIP_CHECK(launch_trial(W->d_trial, B, s));
+  DL_HIP_CHECK(launch_quadforms(W->d_nquad, B, s));
+  DL_HIP_CHECK(launch_trial_gather(W->d_trial, B, s));
+  DL_HIP_CHECK(hipMemcpyAsync(out.data(), W->out4_all, sizeof(double) * 4 * B,
+                              hipMemcpyDeviceToHost, s));
+  DL_HIP_CHECK(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
+  const int B = (int)W->inst.size();
+  DL_HIP_CHECK(run(W, W->asm_p[0], s));
+  DL_HIP_CHECK(run(W, W->fac_p[0], s));
+  for (auto& I : W->inst) {
+    DL_HIP_CHECK(hipMemsetAsync(I.xcur, 0, sizeof(double) * I.m.Np, s));
+    DL_HIP_CHECK(hipMemsetAsync(I.xN, 0, sizeof(double) * I.m.Np, s));
+  }
+  // state: 0 iterating, 1 converged, -1 failed, 2 idle (k >= nk)
+  std::vector<int> state(B, 0), steps(B, 0), nh(B, 0);
+  std::vector<double> alpha(B, 0.0), out(4 * B, 0.0), hcur(B, 0.0);
+  for (int k = nk; k < B; ++k) state[k] = 2;
+  dl_status st = eval_trials(W, alpha, out, s);  // h(0)
+  if (st != DL_OK) return st;
+  for (int k = 0; k < B; ++k) hcur[k] = -0.5 * (out[4 * k + 2] + out[4 * k + 3]);
+  auto h_of = [&](int k) { return -0.5 * (out[4 * k + 2] + out[4 * k + 3]); };
+  for (int it = 0; it < DL_NEWTON_MAX; ++it) {
+    bool any = false;
+    for (int k = 0; k < B; ++k) any = any || state[k] == 0;
+    if (!any) break;
+    DL_HIP_CHECK(launch_lap_weights(W->d_lap, B, s));
+    DL_HIP_CHECK(run(W, W->asm_p[1], s));
+    DL_HIP_CHECK(run(W, W->fac_p[1], s));
+    DL_HIP_CHECK(run(W, W->solve_p, s));
+    for (auto& I : W->inst)
+      DL_HIP_CHECK(hipMemcpyAsync(I.xN, I.mu, sizeof(double) * I.m.Np,
+                                  hipMemcpyDeviceToDevice, s));
+    std::vector<int> live(B, 0);
+    for (int k = 0; k < B; ++k) {
+      live[k] = state[k] == 0;
+      alpha[k] = live[k] ? 1.0 : 0.0;
+      nh[k] = 0;
+    }
+    for (;;) {
+      if ((st = eval_trials(W, alpha, out, s)) != DL_OK) return st;
+      bool pending = false;
+      for (int k = 0; k < B; ++k) {
+        if (!live[k] || state[k] != 0) continue;
+        const double ht = h_of(k);
+        if (std::isfinite(ht) && ht >= hcur[k] - DL_ASCENT_SLACK * (1.0 + std::fabs(hcur[k])))
+          continue;  // accepted at this alpha
+        if (nh[k] == DL_NEWTON_HALVINGS) {
+          state[k] = -1;
+          alpha[k] = 0.0;
+        } else {
+          alpha[k] *= 0.5;
+          ++nh[k];
+          pending = true;
+        }
+      }
+      if (!pending) break;
+    }
+    // the last trial holds every live instance's accepted point (failed ones
+    // are discarded below); converged and idle ones kept x (alpha = 0)
+    for (int k = 0; k < B; ++k) {
+      if (!live[k] || state[k] != 0) continue;
+      ++steps[k];
+      hcur[k] = h_of(k);
+      Inst& I = W->inst[k];
+      DL_HIP_CHECK(hipMemcpyAsync(I.xcur, I.mu, sizeof(double) * I.m.Np,
+                                  hipMemcpyDeviceToDevice, s));
+      if (nh[k] == 0 && out[4 * k] <= DL_NEWTON_TOL * (1.0 + out[4 * k + 1])) state[k] = 1;
+    }
+  }
+  for (int k = 0; k < B; ++k)
+    if (state[k] == 0) state[k] = -1;
+  // Q_c and its factor at the mode, then Eq. 8 at mu = x*
+  DL_HIP_CHECK(launch_lap_weights(W->d_lap, B, s));
+  DL_HIP_CHECK(run(W, W->asm_p[1], s));
+  DL_HIP_CHECK(run(W, W->fac_p[1], s));
+  for (auto& I : W->inst)
+    DL_HIP_CHECK(hipMemcpyAsync(I.mu, I.xcur, sizeof(double) * I.m.Np,
+                                hipMemcpyDeviceToDevice, s));
+  DL_HIP_CHECK(run(W, W->refine_p, s));
+  static const double kBad = 1.0;
+  for (int k = 0; k < B; ++k) {
+    if (state[k] == -1)
+      DL_HIP_CHECK(hipMemcpyAsync(W->inst[k].coef + C_BAD, &kBad, sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+    W->newton_steps[k] = state[k] == 1 ? steps[k] : (state[k] == 2 ? 0 : -1);
+  }
+  DL_HIP_CHECK(run(W, W->post_p, s));
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_newton_steps(const dl_ws* W, int32_t* steps_host) {
+  if (!W || !steps_host) return DL_EINVAL;
+  for (size_t k = 0; k < W->inst.size(); ++k) steps_host[k] = W->newton_steps[k];
+  return DL_OK;
+}
+
 static dl_status run_eval(dl_ws* W, hipStream_t s) {
   if (!W->use_graph) {
     DL_HIP_CHECK(run(W, W->eval_p, s));
@@ -1519,7 +1706,8 @@ extern "C" dl_status fobj_eval(dl_ws* W, const double* theta_dev, int32_t ntheta
     const int nk = std::min(B, ntheta - k0);
     dl_status st = copy_theta_in(W, theta_dev + (int64_t)k0 * dim, nk, s);
     if (st != DL_OK) return st;
-    if ((st = run_eval(W, s)) != DL_OK) return st;
+    st = W->poisson ? laplace_pass(W, nk, s) : run_eval(W, s);
+    if (st != DL_OK) return st;
     if (fobj_dev)
       DL_HIP_CHECK(hipMemcpyAsync(fobj_dev + k0, W->f_all, sizeof(double) * nk,
                                   hipMemcpyDeviceToDevice, s));
@@ -1560,14 +1748,20 @@ extern "C" dl_status fobj_selinv_eval(dl_ws* W, const double* theta_dev, int32_t
   if (!W->ev_join) DL_HIP_CHECK(hipEventCreateWithFlags(&W->ev_join, hipEventDisableTiming));
   dl_status st = copy_theta_in(W, theta_dev, ntheta, s);
   if (st != DL_OK) return st;
-  DL_HIP_CHECK(run(W, W->asm_p[2], s));
-  DL_HIP_CHECK(run(W, W->fac_p[2], s));
-  DL_HIP_CHECK(hipEventRecord(W->ev_fork, s));
-  DL_HIP_CHECK(hipStreamWaitEvent(W->aux_stream, W->ev_fork, 0));
-  DL_HIP_CHECK(run(W, W->solve_p, W->aux_stream));
-  DL_HIP_CHECK(run(W, W->refine_p, W->aux_stream));
-  DL_HIP_CHECK(run(W, W->post_p, W->aux_stream));
-  DL_HIP_CHECK(hipEventRecord(W->ev_join, W->aux_stream));
+  if (W->poisson) {
+    // the mode search ends with the factor of Q_c(x*) and Eq. 8 evaluated
+    if ((st = laplace_pass(W, ntheta, s)) != DL_OK) return st;
+    DL_HIP_CHECK(hipEventRecord(W->ev_join, s));
+  } else {
+    DL_HIP_CHECK(run(W, W->asm_p[2], s));
+    DL_HIP_CHECK(run(W, W->fac_p[2], s));
+    DL_HIP_CHECK(hipEventRecord(W->ev_fork, s));
+    DL_HIP_CHECK(hipStreamWaitEvent(W->aux_stream, W->ev_fork, 0));
+    DL_HIP_CHECK(run(W, W->solve_p, W->aux_stream));
+    DL_HIP_CHECK(run(W, W->refine_p, W->aux_stream));
+    DL_HIP_CHECK(run(W, W->post_p, W->aux_stream));
+    DL_HIP_CHECK(hipEventRecord(W->ev_join, W->aux_stream));
+  }
   DL_HIP_CHECK(run(W, W->selinv_p, s));
   int64_t off = 0;
   for (auto& I : W->inst) {

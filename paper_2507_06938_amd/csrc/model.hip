@@ -15,6 +15,12 @@ extern "C" int32_t dl_theta_dim(int32_t nv) {
   return nv == 1 ? 4 : 4 * nv + nv * (nv - 1) / 2;
 }
 
+extern "C" int32_t dl_theta_dim_lik(int32_t nv, int32_t likelihood) {
+  if (likelihood == DL_LIK_GAUSSIAN) return dl_theta_dim(nv);
+  if (likelihood == DL_LIK_POISSON) return dl_theta_dim(nv) - nv;
+  return -1;
+}
+
 extern "C" const char* dl_status_string(dl_status s) {
   switch (s) {
     case DL_OK: return "ok";
@@ -40,6 +46,8 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
   const int family = desc->family;
   if (family != DL_MODEL_SEPARABLE && family != DL_MODEL_DIFFUSION) return DL_EINVAL;
   if (family == DL_MODEL_DIFFUSION && nt < 2) return DL_EINVAL;
+  const int lik = desc->likelihood;
+  if (lik != DL_LIK_GAUSSIAN && lik != DL_LIK_POISSON) return DL_EINVAL;
   const int ns = nx * nx;
   for (int j = 0; j < nv; ++j) {
     if (desc->m[j] < 0) return DL_EINVAL;
@@ -53,6 +61,10 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
         const int s = desc->obs_nodes[j][3 * i + q];
         if (s < 0 || s >= ns) return DL_EINVAL;
       }
+      if (lik == DL_LIK_POISSON) {
+        const double y = desc->y[j][i];
+        if (!(y >= 0.0) || !(y < 9.0e15) || y != floor(y)) return DL_EINVAL;
+      }
     }
   }
   dl_model* M = new (std::nothrow) dl_model();
@@ -63,7 +75,8 @@ extern "C" dl_status dl_model_create(const dl_model_desc* desc,
   d.b = nv * ns; d.a = nv * nr;
   d.bp = ((d.b + 63) / 64) * 64;
   d.ap = d.a > 0 ? 64 : 0;
-  d.dim_theta = dl_theta_dim(nv);
+  d.dim_theta = dl_theta_dim_lik(nv, lik);
+  d.likelihood = lik;
   d.N = (int64_t)nt * d.b + d.a;
   d.Np = (int64_t)nt * d.bp + d.ap;
   d.theta_prior_sd = desc->theta_prior_sd;

@@ -6,9 +6,9 @@ namespace dl {
 
 // Coefficient table written by k_theta_coeffs (FP64, device):
 //   [C_LOGPRIOR]        log p(theta)
-//   [C_LLCONST]         sum_j m_j/2 log tau_j - m/2 log 2pi
+//   [C_LLCONST]         sum_j m_j/2 log tau_j - m/2 log 2pi (Poisson: 0)
 //   [C_BAD]             1 if theta maps outside the model (NaN, |rho| = 1)
-//   [C_TAU + j]         tau_y of response j
+//   [C_TAU + j]         tau_y of response j (Poisson: 1, unused)
 //   [C_D + ((tt*3 + k)*3 + j)*NPIECE + c]
 //                       weight of FEM piece c (0: C, 1: G, 2: G C^-1 G,
 //                       3: G C^-1 G C^-1 G) in block (k, j) of a diagonal
@@ -29,6 +29,7 @@ enum : int {
 struct ModelDev {
   int nx, nt, nv, nr, ns, b, a, bp, ap, dim_theta;
   int family;             // DL_MODEL_SEPARABLE or DL_MODEL_DIFFUSION
+  int likelihood;         // DL_LIK_GAUSSIAN or DL_LIK_POISSON
   int64_t N, Np;          // unpadded and padded vector lengths
   // spatial pattern (13 points, or 25 for the diffusion model), CSR over
   // nodes, with the values of the four FEM pieces (G3 is zero for the
@@ -74,6 +75,10 @@ struct AssembleOut {
   double* Pc;   // ap x ap (tip of Q_c)
   double* rhs;  // Np
   int b32;      // Bp and BRc are stored in FP32 (mixed precision)
+  // per-observation D and right-hand-side values (m_total each) in place of
+  // tau_y and tau_y y (non-Gaussian likelihoods; null: Gaussian)
+  const double* obs_d;
+  const double* obs_z;
 };
 
 struct ThetaJob {
@@ -94,7 +99,8 @@ struct QuadJob {
   const double* coef;
   const double* mu;
   double* partial;  // 2 * QF_BLOCKS
-  double* out2;     // [mu^T Q_p mu, (y - A mu)^T D (y - A mu)]
+  double* out2;     // [mu^T Q_p mu, (y - A mu)^T D (y - A mu)]; Poisson:
+                    // [mu^T Q_p mu, -2 log l(y | A mu)]
 };
 
 struct CombineJob {
@@ -132,9 +138,37 @@ struct ResJob {
   double* av;         // m_total scratch: (A v)_row
   double* partial;    // 2 * QF_BLOCKS
   double* norms;      // 2
+  const double* obs_d;  // per-observation D (non-Gaussian), else null
 };
 hipError_t launch_residual(const ResJob* jobs, int count, hipStream_t s);
 hipError_t launch_combine(const CombineJob* jobs, int count, hipStream_t s);
+
+// Inner Newton iteration of a Poisson likelihood (Section II-B): from the
+// iterate x (padded BTA order) every observation row gets eta = (A x)_row,
+// d = exp(eta) and z = y - d + d eta (the gradient plus D eta).
+struct LapJob {
+  const ModelDev* m;
+  const double* x;
+  double* obs_d;   // m_total
+  double* obs_z;   // m_total
+};
+hipError_t launch_lap_weights(const LapJob* jobs, int count, hipStream_t s);
+
+// Trial point mu = x + alpha (xN - x) of a damped Newton step, and
+// out4 = [max |xN - x|, max |xN|, mu^T Q_p mu, -2 log l] (the last two
+// copied from the quadratic forms of mu, run in between).
+struct TrialJob {
+  const ModelDev* m;
+  const double* x;
+  const double* xN;
+  double* mu;
+  const double* alpha;
+  double* partial;       // 2 * QF_BLOCKS
+  const double* quad2;
+  double* out4;
+};
+hipError_t launch_trial(const TrialJob* jobs, int count, hipStream_t s);
+hipError_t launch_trial_gather(const TrialJob* jobs, int count, hipStream_t s);
 hipError_t launch_pack(const ModelDev& m, const double* padded, double* out,
                        hipStream_t s);
 hipError_t launch_unpack(const ModelDev& m, const double* in, double* padded,

@@ -47,10 +47,11 @@ class _Desc(C.Structure):
                 ("obs_w", C.c_void_p * 3), ("obs_x", C.c_void_p * 3),
                 ("y", C.c_void_p * 3), ("theta_prior_mean", C.c_void_p),
                 ("theta_prior_sd", C.c_double), ("prior_fixed", C.c_double),
-                ("family", C.c_int32)]
+                ("family", C.c_int32), ("likelihood", C.c_int32)]
 
 
 MODEL_FAMILIES = {"separable": 0, "diffusion": 1}
+LIKELIHOODS = {"gaussian": 0, "poisson": 1}
 
 
 _lib = None
@@ -68,6 +69,8 @@ def lib():
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
             "dl_theta_dim": (i32, [i32]),
+            "dl_theta_dim_lik": (i32, [i32, i32]),
+            "dl_ws_newton_steps": (i32, [vp, C.POINTER(i32)]),
             "dl_model_create": (i32, [vp, C.POINTER(vp)]),
             "dl_model_destroy": (None, [vp]),
             "dl_model_dims": (i32, [vp] + [C.POINTER(i64)] * 5),
@@ -127,8 +130,8 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
-def theta_dim(nv: int) -> int:
-    return int(lib().dl_theta_dim(nv))
+def theta_dim(nv: int, likelihood: str = "gaussian") -> int:
+    return int(lib().dl_theta_dim_lik(nv, LIKELIHOODS[likelihood]))
 
 
 class Model:
@@ -136,15 +139,20 @@ class Model:
 
     def __init__(self, nx: int, nt: int, nv: int, nr: int,
                  responses: Sequence, theta_prior_mean, theta_prior_sd=1.0,
-                 prior_fixed=1e-3, family: str = "separable"):
+                 prior_fixed=1e-3, family: str = "separable",
+                 likelihood: str = "gaussian"):
         L = lib()
         if family not in MODEL_FAMILIES:
             raise ValueError(f"unknown model family {family!r}")
+        if likelihood not in LIKELIHOODS:
+            raise ValueError(f"unknown likelihood {likelihood!r}")
         self.nx, self.nt, self.nv, self.nr = nx, nt, nv, nr
         self.family = family
+        self.likelihood = likelihood
         d = _Desc()
         d.nx, d.nt, d.nv, d.nr = nx, nt, nv, nr
         d.family = MODEL_FAMILIES[family]
+        d.likelihood = LIKELIHOODS[likelihood]
         keep = []
         for j, r in enumerate(responses):
             t, nodes, w, X, y = r
@@ -171,14 +179,15 @@ class Model:
         vals = [C.c_int64() for _ in range(5)]
         _check("dl_model_dims", L.dl_model_dims(h, *[C.byref(v) for v in vals]))
         self.n, self.b, self.a, self.N, self.bp = [v.value for v in vals]
-        self.dim_theta = theta_dim(nv)
+        self.dim_theta = theta_dim(nv, likelihood)
 
     @classmethod
     def from_workload(cls, wl) -> "Model":
         resp = [(r.t, r.nodes, r.w, r.X, r.y) for r in wl.responses]
         return cls(wl.nx, wl.nt, wl.nv, wl.nr, resp, wl.theta_prior_mean,
                    wl.theta_prior_sd, wl.prior_fixed,
-                   getattr(wl, "model", "separable"))
+                   getattr(wl, "model", "separable"),
+                   getattr(wl, "likelihood", "gaussian"))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -336,6 +345,13 @@ class Workspace:
             mask |= 1 << 16
         _check("dl_ws_profile_begin",
                lib().dl_ws_profile_begin(self.h, mask, int(max_launches)))
+
+    def newton_steps(self) -> np.ndarray:
+        """Inner Newton steps per instance of the last f_obj pass (Poisson
+        likelihood; -1: not converged, 0: Gaussian)."""
+        out = (C.c_int32 * len(self.models))()
+        _check("dl_ws_newton_steps", lib().dl_ws_newton_steps(self.h, out))
+        return np.array(out[:], dtype=np.int32)
 
     def profile_enable(self, on: bool):
         """Pause or resume the recording of profile_begin (no allocation)."""

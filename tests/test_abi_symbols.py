@@ -55,6 +55,41 @@ def test_model_create_rejects_bad_family_before_any_device_call():
         h = ctypes.c_void_p()
         assert L.dl_model_create(ctypes.byref(d), ctypes.byref(h)) == 1  # DL_EINVAL
         assert not h.value
-    # dl_model_desc: 4 int32, 3 int64, 16 pointers, 2 doubles, int32 family,
-    # padded to a multiple of 8
+    # dl_model_desc: 4 int32, 3 int64, 16 pointers, 2 doubles, int32 family
+    # and int32 likelihood
     assert ctypes.sizeof(D._Desc) == 16 + 24 + 128 + 16 + 8
+
+
+def test_model_create_rejects_bad_likelihood_and_counts_before_any_device_call():
+    """An unknown likelihood, and for the Poisson likelihood a negative or
+    non-integer count, give DL_EINVAL from the host-side checks; the theta
+    dimension drops the noise precisions."""
+    import numpy as np
+    from paper_2507_06938_amd import build as B
+    from paper_2507_06938_amd import dalia as D
+    if not os.path.exists(B.LIB):
+        B.build(verbose=False)
+    L = D.lib()
+    assert L.dl_theta_dim_lik(1, 0) == 4 and L.dl_theta_dim_lik(3, 0) == 15
+    assert L.dl_theta_dim_lik(1, 1) == 3 and L.dl_theta_dim_lik(3, 1) == 12
+    assert L.dl_theta_dim_lik(2, 1) == 7 and L.dl_theta_dim_lik(1, 9) == -1
+    pm = np.zeros(4)
+    t = np.zeros(2, np.int32)
+    nodes = np.array([0, 1, 4, 1, 4, 5], np.int32)
+    w = np.full(6, 1.0 / 3.0)
+    X = np.ones(2)
+    for lik, yv in ((5, (1.0, 2.0)), (-1, (1.0, 2.0)), (1, (1.0, -1.0)), (1, (0.5, 2.0)),
+                    (1, (np.nan, 2.0))):
+        y = np.array(yv)
+        d = D._Desc()
+        d.nx, d.nt, d.nv, d.nr = 4, 3, 1, 1
+        d.m[0] = 2
+        d.obs_t[0], d.obs_nodes[0], d.obs_w[0] = t.ctypes.data, nodes.ctypes.data, w.ctypes.data
+        d.obs_x[0], d.y[0] = X.ctypes.data, y.ctypes.data
+        d.theta_prior_mean = pm.ctypes.data
+        d.theta_prior_sd = 1.0
+        d.prior_fixed = 1e-3
+        d.likelihood = lik
+        h = ctypes.c_void_p()
+        assert L.dl_model_create(ctypes.byref(d), ctypes.byref(h)) == 1, (lik, yv)
+        assert not h.value

@@ -1,0 +1,190 @@
+"""Poisson likelihood (non-Gaussian, Section II-B): the inner mode by damped
+Newton on the GPU and f_obj by the Laplace approximation at it, against the
+oracle's independent implementation (oracle/laplace.py) on the same seeded
+count workloads.
+
+Tolerances (FP64): the mode is converged to ~1e-13 relative on both sides,
+so the log-determinants and f_obj agree to 1e-10 of |log|Q_p|| + |log|Q_c||,
+the mode to 1e-8 of its largest entry, and the marginal variances of the
+Laplace approximation (diagonal of Q_c(x*)^{-1}) to 1e-8 relative.  The
+Newton step counts may differ by one when a step ends within rounding of the
+stopping threshold.  Batches equal single evaluations bit for bit (an
+instance that has converged keeps its iterate).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fobj as OF
+from oracle import model as OM
+from oracle.linalg import DenseSPD
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_06938_amd import dalia
+    dalia.lib()
+    return dalia
+
+
+def _pois(name, nx, nt, nv, nr, m, seed, model="separable"):
+    return lambda: W.scaled(name, nx, nt, nv, nr, m, seed=seed, model=model,
+                            likelihood="poisson")
+
+
+CASES = {
+    "uni_2tiles": _pois("u", 10, 6, 1, 2, 300, 3),
+    "tri_damped": _pois("t", 8, 5, 3, 2, 200, 3),          # first step halved
+    "diff_uni": _pois("d", 13, 5, 1, 1, 90, 3, "diffusion"),
+    "ragged_nt7": _pois("r", 9, 7, 1, 3, 140, 17),
+    "uni_19tiles": _pois("s", 34, 4, 1, 2, 800, 18),        # b = 1156
+    "tri_diff_nt6": _pois("td", 5, 6, 3, 2, 40, 15, "diffusion"),
+}
+
+
+def oracle_ref(wl, theta):
+    parts = OF.fobj_parts(wl, theta)
+    perm = OM.bta_permutation(wl.nv, wl.ns, wl.nt, wl.nr)
+    parts["mu_bta"] = parts["mu"][perm]
+    parts["var_bta"] = DenseSPD(parts["Qc"]).inv_diag()[perm]
+    return parts
+
+
+def evaluate(ws, theta):
+    f, parts, info = ws.fobj(theta)
+    mu = ws.mean()
+    var = ws.selinv()
+    torch.cuda.synchronize()
+    return (f.cpu().numpy(), parts.cpu().numpy(), info.cpu().numpy(),
+            mu.cpu().numpy(), var.cpu().numpy())
+
+
+@pytest.mark.parametrize("variant", ["default", "two_sided_fold", "keep_qp"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_poisson_laplace_against_oracle(D, name, variant):
+    wl = CASES[name]()
+    theta = wl.theta + 0.05 * np.sin(np.arange(wl.dim_theta) + 1.0)
+    print(name, variant, flush=True)
+    ref = oracle_ref(wl, theta)
+    assert ref["converged"]
+    model = D.Model.from_workload(wl)
+    assert model.dim_theta == wl.dim_theta
+    kw = dict(default={}, two_sided_fold=dict(two_sided=True, fold_inverse=True),
+              keep_qp=dict(keep_qp=True))[variant]
+    ws = D.Workspace(model, selinv=True, **kw)
+    f, p, info, mu, var = evaluate(ws, theta)
+    steps = ws.newton_steps()
+    p = p[0]
+    print(f"  f {f[0]:.12f} oracle {ref['f']:.12f}  steps {steps[0]} oracle "
+          f"{ref['newton_steps']}  rel residual {p[7]:.2e}", flush=True)
+    assert info.tolist() == [[0, 0]]
+    assert abs(int(steps[0]) - ref["newton_steps"]) <= 1
+    scale = abs(ref["logdet_p"]) + abs(ref["logdet_c"])
+    assert abs(p[1] - ref["logdet_p"]) <= 1e-10 * abs(ref["logdet_p"])
+    assert abs(p[2] - ref["logdet_c"]) <= 1e-10 * scale
+    assert abs(f[0] - ref["f"]) <= 1e-10 * scale
+    assert abs(p[4] - ref["quad_obs"]) <= 1e-10 * scale
+    assert p[6] == 0.0                       # no Gaussian constant
+    assert p[7] <= 1e-9                      # gradient of h at the mode
+    assert np.max(np.abs(mu - ref["mu_bta"])) <= 1e-8 * np.max(np.abs(ref["mu_bta"]))
+    np.testing.assert_allclose(var, ref["var_bta"], rtol=1e-8)
+
+
+def test_poisson_batch_equals_single_calls(D):
+    wls = [CASES["uni_2tiles"](), CASES["tri_damped"](), CASES["diff_uni"]()]
+    models = [D.Model.from_workload(w) for w in wls]
+    ws = D.Workspace(models, selinv=True)
+    thetas = np.concatenate([w.theta for w in wls])
+    fb, pb, ib = ws.fobj(thetas)
+    var_b = ws.selinv().cpu().numpy()
+    steps_b = ws.newton_steps()
+    torch.cuda.synchronize()
+    off = 0
+    for k, (w, mdl) in enumerate(zip(wls, models)):
+        ws1 = D.Workspace(mdl, selinv=True)
+        f1, p1, i1 = ws1.fobj(w.theta)
+        v1 = ws1.selinv().cpu().numpy()
+        torch.cuda.synchronize()
+        assert ws1.newton_steps()[0] == steps_b[k] > 0
+        assert fb.cpu().numpy()[k] == f1.cpu().numpy()[0], k
+        assert np.array_equal(pb.cpu().numpy()[k], p1.cpu().numpy()[0]), k
+        assert np.array_equal(var_b[off:off + w.N], v1), k
+        off += w.N
+
+
+def test_poisson_several_passes_and_graph_flag(D):
+    """ntheta > B on one model (two passes, the second one partly idle), and
+    a DL_WS_GRAPH workspace (the mode search runs eagerly): both equal
+    single evaluations bit for bit."""
+    wl = CASES["uni_2tiles"]()
+    model = D.Model.from_workload(wl)
+    rng = np.random.default_rng(5)
+    th = wl.theta[None] + 0.1 * rng.standard_normal((3, wl.dim_theta))
+    ws2 = D.Workspace([model] * 2)
+    f2, p2, _ = ws2.fobj(th)
+    wsg = D.Workspace(model, graph=True)
+    single = []
+    for r in range(3):
+        f1, _, _ = wsg.fobj(th[r])
+        single.append(f1.cpu().numpy()[0])
+    torch.cuda.synchronize()
+    assert f2.cpu().numpy().tolist() == single
+    ref = [OF.fobj(wl, t) for t in th]
+    np.testing.assert_allclose(single, ref, rtol=1e-11)
+
+
+def test_poisson_fobj_selinv_equals_fobj_then_selinv(D):
+    wl = CASES["tri_damped"]()
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True, two_sided=True)
+    f, p, i, var = ws.fobj_selinv(wl.theta)
+    var = var.cpu().numpy()
+    ws2 = D.Workspace(model, selinv=True, two_sided=True)
+    f2, p2, _ = ws2.fobj(wl.theta)
+    var2 = ws2.selinv().cpu().numpy()
+    torch.cuda.synchronize()
+    assert f.cpu().numpy().tolist() == f2.cpu().numpy().tolist()
+    assert np.array_equal(var, var2)
+
+
+def test_poisson_rejects_mixed_precision_and_mixed_likelihoods(D):
+    pw = CASES["uni_2tiles"]()
+    gw = W.config0()
+    pm, gm = D.Model.from_workload(pw), D.Model.from_workload(gw)
+    with pytest.raises(D.DaliaError):
+        D.Workspace(pm, mixed=True)
+    with pytest.raises(D.DaliaError):
+        D.Workspace([pm, gm])
+    # a Gaussian workspace reports no Newton steps
+    ws = D.Workspace(gm)
+    ws.fobj(gw.theta)
+    torch.cuda.synchronize()
+    assert ws.newton_steps().tolist() == [0]
+
+
+def test_poisson_production_size_converges(D):
+    """Counts on the production univariate mesh (45 x 45, nt = 100,
+    m = 200000): the mode search converges, the gradient at the mode is
+    at rounding level, and the two-sided order with folded inverses agrees
+    with the default order to rounding."""
+    wl = W.make_univariate("c1_poisson", 45, 100, 4, 200_000, seed=0,
+                           likelihood="poisson")
+    model = D.Model.from_workload(wl)
+    out = {}
+    for tag, kw in (("default", {}), ("two_fold", dict(two_sided=True, fold_inverse=True))):
+        ws = D.Workspace(model, **kw)
+        f, p, info = ws.fobj(wl.theta)
+        torch.cuda.synchronize()
+        out[tag] = (f.cpu().numpy()[0], p.cpu().numpy()[0], ws.newton_steps()[0])
+        print(tag, out[tag][0], "steps", out[tag][2], "rel residual", out[tag][1][7], flush=True)
+        assert info.cpu().tolist() == [[0, 0]]
+        del ws
+    (f0, p0, s0), (f1, p1, s1) = out["default"], out["two_fold"]
+    assert np.isfinite(f0) and 0 < s0 <= 20 and abs(s1 - s0) <= 1
+    assert p0[7] <= 1e-9 and p1[7] <= 1e-9
+    assert abs(f1 - f0) <= 1e-10 * (abs(p0[1]) + abs(p0[2]))
