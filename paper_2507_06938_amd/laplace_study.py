@@ -5,7 +5,7 @@ same mesh: time per evaluation, Newton steps, time per Newton step, and a
 batched central-difference gradient (2 dim + 1 = 7 points, Eq. 10) whose
 instances converge at their own step counts.
 
-    python -m paper_2507_06938_amd.laplace_study [--reps 3]
+    python -m paper_2507_06938_amd.laplace_study [--reps 3] [--poisson-only]
 
 Prints one JSON document.
 """
@@ -29,6 +29,8 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="only the single Poisson evaluation (for kernel profiles)")
     ap.add_argument("--tiles", default=os.path.join(root, "paper_2507_06938_amd",
                                                     "tiles_gfx950.txt"))
     args = ap.parse_args(argv)
@@ -44,7 +46,7 @@ def main(argv=None):
 
     out = {}
     kw = dict(two_sided=True, fold_inverse=True)
-    for lik in ("gaussian", "poisson"):
+    for lik in (("poisson",) if args.poisson_only else ("gaussian", "poisson")):
         wl = W.make_univariate(f"c1_{lik}", 45, 100, 4, 200_000, seed=0, likelihood=lik)
         model = D.Model.from_workload(wl)
         ws = D.Workspace(model, **kw)
@@ -66,7 +68,7 @@ def main(argv=None):
         out[lik] = res
         del ws
         torch.cuda.empty_cache()
-        if lik == "poisson":
+        if lik == "poisson" and not args.poisson_only:
             d = wl.dim_theta
             h = 1e-3
             pts = np.repeat(wl.theta[None], 2 * d + 1, axis=0)
