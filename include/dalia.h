@@ -199,7 +199,14 @@ enum {
                          when few blocks are factored at once (single
                          evaluations); for wide batches the recursive
                          inversion is faster.  Results differ from the
-                         default by rounding only                           */
+                         default by rounding only                           */,
+  DL_WS_WARM_START = 128 /* DL_LIK_POISSON: start each instance's inner
+                         Newton search from its mode of the previous pass
+                         (when that pass converged) instead of x = 0.  For
+                         nearby thetas (line searches, difference stencils)
+                         it takes fewer steps; the mode is unique, so results
+                         differ from a cold start by rounding only, but they
+                         depend on the call history                        */
 };
 #define DL_REFINE_STEPS 3
 

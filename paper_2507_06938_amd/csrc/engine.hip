@@ -446,6 +446,8 @@ struct dl_ws {
   TrialJob* d_trial = nullptr;
   QuadJob* d_nquad = nullptr;
   std::vector<int32_t> newton_steps;
+  bool warm = false;             // DL_WS_WARM_START
+  std::vector<char> has_mode;    // instance holds a converged mode in xcur
   Descs H;
   DevDescs Dd;
   std::vector<Launch> table;
@@ -1303,6 +1305,8 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     return DL_EINVAL;
   }
   W->newton_steps.assign(nmodels, 0);
+  W->warm = (flags & DL_WS_WARM_START) != 0;
+  W->has_mode.assign(nmodels, 0);
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
   auto A = [&](size_t bytes, void** p) {
@@ -1552,7 +1556,8 @@ extern "C" dl_status dl_ws_mean(dl_ws* W, double* out_dev, void* stream) {
 // ---- inner mode of a Poisson likelihood (Laplace approximation) ------------------
 //
 // Damped Newton for the mode x* of h(x) = log l(y | A x) - 1/2 x^T Q_p x
-// from x = 0, for the first nk instances (the rest stay idle): each step
+// from x = 0 (or, with DL_WS_WARM_START, from the instance's previous mode),
+// for the first nk instances (the rest stay idle): each step
 // assembles Q_c(x) = Q_p + A^T D(x) A and A^T (g + D A x) from the weights
 // of the current iterate, factors and solves (x_N), and tries
 // x + alpha (x_N - x) for alpha = 1, 1/2, ... until h does not fall (up to
@@ -1578,15 +1583,17 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
   const int B = (int)W->inst.size();
   DL_HIP_CHECK(run(W, W->asm_p[0], s));
   DL_HIP_CHECK(run(W, W->fac_p[0], s));
-  for (auto& I : W->inst) {
-    DL_HIP_CHECK(hipMemsetAsync(I.xcur, 0, sizeof(double) * I.m.Np, s));
+  for (int k = 0; k < B; ++k) {
+    Inst& I = W->inst[k];
+    if (!(W->warm && W->has_mode[k] && k < nk))
+      DL_HIP_CHECK(hipMemsetAsync(I.xcur, 0, sizeof(double) * I.m.Np, s));
     DL_HIP_CHECK(hipMemsetAsync(I.xN, 0, sizeof(double) * I.m.Np, s));
   }
   // state: 0 iterating, 1 converged, -1 failed, 2 idle (k >= nk)
   std::vector<int> state(B, 0), steps(B, 0), nh(B, 0);
   std::vector<double> alpha(B, 0.0), out(4 * B, 0.0), hcur(B, 0.0);
   for (int k = nk; k < B; ++k) state[k] = 2;
-  dl_status st = eval_trials(W, alpha, out, s);  // h(0)
+  dl_status st = eval_trials(W, alpha, out, s);  // h at the start
   if (st != DL_OK) return st;
   for (int k = 0; k < B; ++k) hcur[k] = -0.5 * (out[4 * k + 2] + out[4 * k + 3]);
   auto h_of = [&](int k) { return -0.5 * (out[4 * k + 2] + out[4 * k + 3]); };
@@ -1654,6 +1661,7 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
       DL_HIP_CHECK(hipMemcpyAsync(W->inst[k].coef + C_BAD, &kBad, sizeof(double),
                                   hipMemcpyHostToDevice, s));
     W->newton_steps[k] = state[k] == 1 ? steps[k] : (state[k] == 2 ? 0 : -1);
+    if (state[k] != 2) W->has_mode[k] = state[k] == 1;
   }
   DL_HIP_CHECK(run(W, W->post_p, s));
   return DL_OK;

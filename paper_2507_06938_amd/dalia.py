@@ -22,6 +22,7 @@ DL_WS_SELINV, DL_WS_KEEP_QP, DL_WS_GRAPH, DL_WS_MIXED = 1, 2, 4, 8
 DL_WS_SPLITK = 16
 DL_WS_TWOSIDED = 32
 DL_WS_FOLD_INV = 64
+DL_WS_WARM_START = 128
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
@@ -202,7 +203,8 @@ class Workspace:
 
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
                  graph: bool = False, mixed: bool = False, splitk: bool = False,
-                 two_sided: bool = False, fold_inverse: bool = False):
+                 two_sided: bool = False, fold_inverse: bool = False,
+                 warm_start: bool = False):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
@@ -211,7 +213,8 @@ class Workspace:
                  | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
                  | (DL_WS_SPLITK if splitk else 0)
                  | (DL_WS_TWOSIDED if two_sided else 0)
-                 | (DL_WS_FOLD_INV if fold_inverse else 0))
+                 | (DL_WS_FOLD_INV if fold_inverse else 0)
+                 | (DL_WS_WARM_START if warm_start else 0))
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
         _check("dl_ws_create_batch",

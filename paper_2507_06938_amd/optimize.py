@@ -52,12 +52,15 @@ class Evaluator:
     `batch` instances for gradient stencils and one of `ntrial` instances for
     line searches."""
 
-    def __init__(self, model: "D.Model", batch: int, graph: bool = True, ntrial: int = 4):
+    def __init__(self, model: "D.Model", batch: int, graph: bool = True, ntrial: int = 4,
+                 warm_start: bool = False):
         self.model = model
         self.B = batch
         self.ntrial = ntrial
-        self.ws = D.Workspace([model] * batch, graph=graph)
-        self.ws_ls = D.Workspace([model] * ntrial, graph=graph)
+        # warm_start (Poisson likelihood): each instance's inner Newton search
+        # starts from its mode of the previous pass
+        self.ws = D.Workspace([model] * batch, graph=graph, warm_start=warm_start)
+        self.ws_ls = D.Workspace([model] * ntrial, graph=graph, warm_start=warm_start)
         self.dim = model.dim_theta
         self.count = 0
         self.archive_x: List[np.ndarray] = []

@@ -3,6 +3,9 @@ Newton on the GPU and f_obj by the Laplace approximation at it, against the
 oracle's independent implementation (oracle/laplace.py) on the same seeded
 count workloads.
 
+The mode search over theta and the Hessian at its optimum run on the Poisson
+f_obj as on the Gaussian one.
+
 Tolerances (FP64): the mode is converged to ~1e-13 relative on both sides,
 so the log-determinants and f_obj agree to 1e-10 of |log|Q_p|| + |log|Q_c||,
 the mode to 1e-8 of its largest entry, and the marginal variances of the
@@ -188,3 +191,63 @@ def test_poisson_production_size_converges(D):
     assert np.isfinite(f0) and 0 < s0 <= 20 and abs(s1 - s0) <= 1
     assert p0[7] <= 1e-9 and p1[7] <= 1e-9
     assert abs(f1 - f0) <= 1e-10 * (abs(p0[1]) + abs(p0[2]))
+
+
+def test_poisson_mode_search_and_hessian_match_oracle(D):
+    """The hyperparameter mode search (Eq. 9, batched central differences,
+    Eq. 10) and the Hessian at the mode on the Poisson f_obj: the GPU
+    drivers reach the oracle BFGS optimum value (|F - F*| <= 1e-6 |F*|), and
+    the second differences at the oracle's optimum agree with the oracle's
+    (|dH| <= 2e-12 |f| / h^2, as for the Gaussian likelihood)."""
+    from oracle import bfgs as OB
+    from oracle import hessian as OH
+    from paper_2507_06938_amd import hessian as GH
+    from paper_2507_06938_amd import optimize as O
+    wl = W.scaled("opt_pois", 5, 4, 1, 2, 60, seed=11, likelihood="poisson")
+    theta0 = W.random_theta_near(wl.theta, 0.25, seed=3)
+    F = lambda t: -OF.fobj(wl, t)
+    fg = lambda t: (F(t), OB.central_gradient(F, t, 1e-3))
+    xs, fs, _ = OB.bfgs_minimize(fg, theta0, max_iter=300, ftol=1e-13, gtol=1e-6)
+    model = D.Model.from_workload(wl)
+    ev = O.Evaluator(model, batch=2 * wl.dim_theta + 1)
+    tr = O.fd_bfgs(ev, theta0, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300)
+    print(f"oracle F*={fs:.12f}  gpu F={tr.f[-1]:.12f}  iters={len(tr.f) - 1}", flush=True)
+    assert abs(tr.f[-1] - fs) <= 1e-6 * abs(fs)
+    d = wl.dim_theta
+    ws = D.Workspace([model] * (2 * d * d + 1))
+    H_gpu, f0, vals = GH.fobj_hessian(ws, xs, 1e-3)
+    ref_vals = np.array([OF.fobj(wl, p) for p in OH.hessian_stencil(xs, 1e-3)])
+    H_ref = OH.hessian_from_values(ref_vals, d, 1e-3)
+    print("max |dH|", np.max(np.abs(H_gpu - H_ref)), flush=True)
+    assert np.max(np.abs(H_gpu - H_ref)) <= 2e-12 * abs(ref_vals[0]) / 1e-6
+    assert np.linalg.eigvalsh(H_gpu).max() < 0
+    np.testing.assert_allclose(GH.marginal_sd(H_gpu), OH.gaussian_marginal_sd(H_ref), rtol=1e-5)
+
+
+def test_poisson_warm_start(D):
+    """DL_WS_WARM_START: the first pass starts from x = 0 (identical to a
+    cold workspace), later passes from the previous mode; at a nearby theta
+    the search takes fewer steps and reaches the same f_obj to rounding."""
+    wl = CASES["uni_19tiles"]()
+    model = D.Model.from_workload(wl)
+    warm = D.Workspace(model, warm_start=True)
+    cold = D.Workspace(model)
+    th1 = wl.theta
+    th2 = wl.theta + 0.02 * np.array([1.0, -1.0, 0.5])
+    fw1, _, _ = warm.fobj(th1)
+    fc1, _, _ = cold.fobj(th1)
+    torch.cuda.synchronize()
+    assert fw1.cpu().tolist() == fc1.cpu().tolist()
+    assert warm.newton_steps().tolist() == cold.newton_steps().tolist()
+    fw2, pw2, _ = warm.fobj(th2)
+    sw = int(warm.newton_steps()[0])
+    fc2, pc2, _ = cold.fobj(th2)
+    sc = int(cold.newton_steps()[0])
+    torch.cuda.synchronize()
+    print("steps warm", sw, "cold", sc, flush=True)
+    assert 0 < sw < sc
+    p = pc2.cpu().numpy()[0]
+    scale = abs(p[1]) + abs(p[2])
+    assert abs(fw2.item() - fc2.item()) <= 1e-10 * scale
+    assert abs(fw2.item() - OF.fobj(wl, th2)) <= 1e-10 * scale
+    assert pw2.cpu().numpy()[0][7] <= 1e-9
