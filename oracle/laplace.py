@@ -148,7 +148,7 @@ def laplace_parts(Qp, A, lik, log_prior: float, a: int = 0, method: str = "auto"
         f = -math.inf
     out.update(f=f, spd=True, converged=ok, newton_steps=steps, halvings=halvings,
                logdet_p=logdet_p, logdet_c=logdet_c, quad_p=quad_p,
-               log_lik=log_lik, log_prior=log_prior, mu=x, D=Dv, Qp=Qp, Qc=Qc,
+               log_lik=log_lik, log_prior=log_prior, mu=x, D=Dv, Qp=Qp, Qc=Qc, Fp=Fp, Fc=Fc,
                r=A.T @ (lik.grad(eta) + Dv * eta))
     return out
 

@@ -3,7 +3,9 @@ search for the inner mode) on the production univariate mesh (45 x 45,
 nt = 100, 4 fixed effects, m = 200000), against the Gaussian f_obj of the
 same mesh: time per evaluation, Newton steps, time per Newton step, and a
 batched central-difference gradient (2 dim + 1 = 7 points, Eq. 10) whose
-instances converge at their own step counts.
+instances converge at their own step counts, cold and warm-started (the next
+gradient of an optimiser, 0.01 away, each Newton search starting from the
+previous gradient's modes).
 
     python -m paper_2507_06938_amd.laplace_study [--reps 3] [--poisson-only]
 
@@ -88,6 +90,26 @@ def main(argv=None):
                 "gradient": ((fb[1::2] - fb[2::2]) / (2 * h)).cpu().numpy().tolist()}
             print("fd", json.dumps(out["poisson_fd_gradient"]), file=sys.stderr, flush=True)
             del wsb
+            torch.cuda.empty_cache()
+            # the next gradient of an optimiser, 0.01 away, with each instance's
+            # Newton search started from its mode of the previous gradient
+            wsw = D.Workspace([model] * (2 * d + 1), warm_start=True, **kw)
+            wsw.autotune(args.tiles)
+            wsw.fobj(thb)
+            torch.cuda.synchronize()
+            shift = torch.full_like(thb, 0.0)
+            shift[:, 0] = 0.01
+            t0 = time.perf_counter()
+            fw, _, iw = wsw.fobj(thb + shift)
+            torch.cuda.synchronize()
+            tw = time.perf_counter() - t0
+            out["poisson_fd_gradient_warm"] = {
+                "points": 2 * d + 1, "s_per_gradient": tw, "evals_per_s": (2 * d + 1) / tw,
+                "newton_steps": wsw.newton_steps().tolist(),
+                "all_spd": bool((iw == 0).all().item())}
+            print("fd warm", json.dumps(out["poisson_fd_gradient_warm"]), file=sys.stderr,
+                  flush=True)
+            del wsw
             torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 

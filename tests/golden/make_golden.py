@@ -1,12 +1,15 @@
 """Write the stored expected values of the full-size parity tests.
 
-    python tests/golden/make_golden.py c1 [c2] [c1_diffusion]
+    python tests/golden/make_golden.py c1 [c2] [c1_diffusion] [c1_poisson]
 
 Calls only the CPU oracle (``oracle/``) on the seeded workloads of
 ``workloads/``; nothing here touches the GPU path.  For each configuration it
 stores log|Q_p|, log|Q_c|, the parts of f_obj, and the conditional mean and
 the marginal variances diag(Q_c^{-1}) at seeded sample positions (BTA order,
-plus every fixed effect), computed with the RCM + banded LAPACK route.
+plus every fixed effect), computed with the RCM + banded LAPACK route.  For
+the Poisson workload the mean is the inner mode and the variances are those
+of the Laplace approximation, diag(Q_c(x*)^{-1}); the Newton step count is
+stored too.
 """
 import json
 import os
@@ -23,7 +26,8 @@ from oracle import fobj as OF  # noqa: E402
 from oracle import model as OM  # noqa: E402
 
 CONFIGS = {"c1": W.config1, "c2": W.config2,
-           "c1_diffusion": lambda: W.config1(model="diffusion")}
+           "c1_diffusion": lambda: W.config1(model="diffusion"),
+           "c1_poisson": lambda: W.config1(likelihood="poisson")}
 
 
 def sample_positions(N, a, k, seed):
@@ -52,6 +56,7 @@ def make(name):
         var_index_bta=var_idx.tolist(), var=var.tolist(),
         oracle="RCM + LAPACK banded Cholesky (dpbtrf) with a Schur border",
         bandwidth_Qc=int(p["Fc"].kd),
+        newton_steps=int(p.get("newton_steps", 0)),
         seconds=dict(fobj=t1 - t0, variances=t2 - t1),
     )
     path = os.path.join(HERE, f"{name}_golden.json")

@@ -251,3 +251,40 @@ def test_poisson_warm_start(D):
     assert abs(fw2.item() - fc2.item()) <= 1e-10 * scale
     assert abs(fw2.item() - OF.fobj(wl, th2)) <= 1e-10 * scale
     assert pw2.cpu().numpy()[0][7] <= 1e-9
+
+
+@pytest.mark.parametrize("kw", [{}, {"two_sided": True, "fold_inverse": True}])
+def test_poisson_fullsize_against_banded_oracle(D, kw):
+    """The production-size count workload (45 x 45, nt = 100, m = 200000)
+    against values stored by tests/golden/make_golden.py (oracle: damped
+    Newton with RCM + banded LAPACK Cholesky): log-determinants, f_obj, the
+    inner mode and the Laplace marginal variances at seeded positions."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c1_poisson_golden.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = json.load(open(path))
+    wl = W.config1(likelihood="poisson")
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True, **kw)
+    f, parts, info = ws.fobj(np.asarray(g["theta"]))
+    mu = ws.mean()
+    var = ws.selinv()
+    torch.cuda.synchronize()
+    p = parts.cpu().numpy()[0]
+    steps = int(ws.newton_steps()[0])
+    print(kw, "f", p[0], "oracle", g["f"], "steps", steps, "oracle", g["newton_steps"], flush=True)
+    assert info.cpu().tolist() == [[0, 0]]
+    assert abs(steps - g["newton_steps"]) <= 1
+    assert abs(p[1] - g["logdet_p"]) <= 1e-10 * abs(g["logdet_p"])
+    scale = abs(g["logdet_p"]) + abs(g["logdet_c"])
+    assert abs(p[2] - g["logdet_c"]) <= 1e-10 * scale
+    assert abs(p[0] - g["f"]) <= 1e-10 * scale
+    mu_s = mu.cpu().numpy()[np.asarray(g["mu_index_bta"])]
+    want = np.asarray(g["mu"])
+    assert np.max(np.abs(mu_s - want)) <= 1e-8 * np.max(np.abs(want))
+    v_s = var.cpu().numpy()[np.asarray(g["var_index_bta"])]
+    np.testing.assert_allclose(v_s, np.asarray(g["var"]), rtol=1e-8)
+    v = var.cpu().numpy()
+    assert np.all(np.isfinite(v)) and np.all(v > 0)

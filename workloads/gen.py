@@ -236,10 +236,15 @@ def _suffix(model: str) -> str:
     return "" if model == "separable" else "_" + model
 
 
-def config1(seed: int = 0, model: str = "separable") -> Workload:
-    """Production univariate: 45x45 grid (b=2025), nt=100, nr=4, m=200000."""
-    return make_univariate("c1_univariate_45x45_nt100" + _suffix(model), 45,
-                           100, 4, 200_000, seed=seed, model=model)
+def config1(seed: int = 0, model: str = "separable",
+            likelihood: str = "gaussian") -> Workload:
+    """Production univariate: 45x45 grid (b=2025), nt=100, nr=4, m=200000
+    (counts with ``likelihood="poisson"``)."""
+    name = "c1_univariate_45x45_nt100" + _suffix(model)
+    if likelihood != "gaussian":
+        name += "_" + likelihood
+    return make_univariate(name, 45, 100, 4, 200_000, seed=seed, model=model,
+                           likelihood=likelihood)
 
 
 def config2(seed: int = 0, model: str = "separable") -> Workload:
