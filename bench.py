@@ -22,9 +22,11 @@ the dominant kernel (HIP events around its launches during the timed steps)
 and the CPU oracle timed on a bounded sample of the same workload.  GEMM
 tiles are the measured choices of the library's autotuner (cache file
 paper_2507_06938_amd/tiles_gfx950.txt; missing shapes are timed and added).
-Two further measurements of the same workload are extra fields of the
-line: the 9-point central-difference gradient as one batched,
-graph-replayed evaluation, and f_obj in mixed precision with its errors.
+Three further measurements of the same mesh are extra fields of the line:
+the 9-point central-difference gradient as one batched, graph-replayed
+evaluation, f_obj in mixed precision with its errors, and f_obj with
+Poisson counts in place of the Gaussian responses (inner damped Newton and
+Laplace approximation) with its errors against stored oracle values.
 """
 from __future__ import annotations
 
@@ -127,6 +129,37 @@ def fd_batch(D, W, wl, model, single_ms, tiles, two_sided=False):
             "evals_per_s": (2 * d + 1) * 1000.0 / ms,
             "speedup_vs_sequential": (2 * d + 1) * single_ms / ms,
             "gradient": grad, "all_spd": ok}
+
+
+def poisson(D, W, tiles, two_sided=False):
+    """f_obj of the same mesh with Poisson counts (inner damped Newton for
+    the mode, Laplace approximation), against the stored oracle values."""
+    import torch
+    wl = W.config1(likelihood="poisson")
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, two_sided=two_sided, fold_inverse=True)
+    if tiles:
+        ws.autotune(tiles)
+    th = torch.tensor(wl.theta, dtype=torch.float64, device="cuda")
+    ms = _events_ms(torch, lambda: ws.fobj(th), 2)
+    f, parts, info = ws.fobj(th)
+    torch.cuda.synchronize()
+    p = parts.cpu().numpy()[0]
+    out = {"workload": wl.name, "evals_per_s": 1000.0 / ms, "ms": ms,
+           "newton_steps": int(ws.newton_steps()[0]), "f": float(p[0]),
+           "rel_gradient_at_mode": float(p[7]),
+           "spd": bool((info == 0).all().item())}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "c1_poisson_golden.json")
+    if os.path.exists(path):
+        g = json.load(open(path))
+        scale = abs(g["logdet_p"]) + abs(g["logdet_c"])
+        out["err_vs_fp64_oracle"] = {"f_rel_scale": abs(p[0] - g["f"]) / scale,
+                                     "logdet_c_rel": abs(p[2] - g["logdet_c"]) / abs(g["logdet_c"]),
+                                     "oracle_newton_steps": g["newton_steps"]}
+    del ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def mixed(D, wl, model, errors, tiles, two_sided=False):
@@ -319,6 +352,8 @@ def main():
         out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles,
                                             two_sided)
         out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles, two_sided)
+        if args.model == "separable":
+            out["poisson_likelihood"] = poisson(D, W, args.tiles, two_sided)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt, model=args.model)
     print(json.dumps(out), flush=True)
