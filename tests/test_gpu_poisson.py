@@ -35,6 +35,12 @@ def D():
     return dalia
 
 
+def _zeroed(wl):
+    for r in wl.responses:
+        r.y[:] = 0.0
+    return wl
+
+
 def _pois(name, nx, nt, nv, nr, m, seed, model="separable"):
     return lambda: W.scaled(name, nx, nt, nv, nr, m, seed=seed, model=model,
                             likelihood="poisson")
@@ -47,6 +53,13 @@ CASES = {
     "ragged_nt7": _pois("r", 9, 7, 1, 3, 140, 17),
     "uni_19tiles": _pois("s", 34, 4, 1, 2, 800, 18),        # b = 1156
     "tri_diff_nt6": _pois("td", 5, 6, 3, 2, 40, 15, "diffusion"),
+    # degenerate cases: no observations (Q_c = Q_p, mode 0), all counts
+    # zero, a single time step (one block), two responses
+    "no_obs": _pois("e", 6, 3, 1, 2, 0, 1),
+    "zero_counts": lambda: _zeroed(W.scaled("z", 6, 4, 1, 2, 120, seed=1,
+                                            likelihood="poisson")),
+    "nt1": _pois("n1", 8, 1, 1, 2, 100, 2),
+    "bivariate": _pois("bv", 6, 5, 2, 1, 80, 2),
 }
 
 
@@ -288,3 +301,20 @@ def test_poisson_fullsize_against_banded_oracle(D, kw):
     np.testing.assert_allclose(v_s, np.asarray(g["var"]), rtol=1e-8)
     v = var.cpu().numpy()
     assert np.all(np.isfinite(v)) and np.all(v > 0)
+
+
+def test_poisson_without_observations_is_the_prior(D):
+    """No observations: Q_c = Q_p, the mode is 0 after one Newton step, and
+    f_obj reduces to log p(theta) (the two half log-determinants cancel)."""
+    wl = CASES["no_obs"]()
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model, selinv=True)
+    f, p, info = ws.fobj(wl.theta)
+    mu = ws.mean()
+    torch.cuda.synchronize()
+    p = p.cpu().numpy()[0]
+    assert info.cpu().tolist() == [[0, 0]] and ws.newton_steps().tolist() == [1]
+    assert not np.any(mu.cpu().numpy())
+    assert p[2] == p[1] and p[3] == 0.0 and p[4] == 0.0
+    assert f.item() == pytest.approx(OM.log_prior_theta(wl.theta, wl.theta_prior_mean,
+                                                        wl.theta_prior_sd), rel=1e-14)
