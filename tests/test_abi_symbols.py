@@ -93,3 +93,29 @@ def test_model_create_rejects_bad_likelihood_and_counts_before_any_device_call()
         h = ctypes.c_void_p()
         assert L.dl_model_create(ctypes.byref(d), ctypes.byref(h)) == 1, (lik, yv)
         assert not h.value
+
+
+def test_model_create_rejects_blocks_beyond_the_lds_column_buffer():
+    """The assembly keeps a column of a diagonal and a sub-diagonal block
+    (2 bp + 64 doubles) in 160 KiB of LDS: one response on a 101 x 101
+    mesh (bp = 10240) or three on 59 x 59 (bp = 10496) are rejected on the
+    host; 100 x 100 and 3 x 58 x 58 are the largest accepted sizes."""
+    import numpy as np
+    from paper_2507_06938_amd import build as B
+    from paper_2507_06938_amd import dalia as D
+    if not os.path.exists(B.LIB):
+        B.build(verbose=False)
+    L = D.lib()
+    for nx, nv in ((101, 1), (59, 3)):
+        pm = np.zeros(L.dl_theta_dim(nv))
+        d = D._Desc()
+        d.nx, d.nt, d.nv, d.nr = nx, 3, nv, 1
+        d.theta_prior_mean = pm.ctypes.data
+        d.theta_prior_sd = 1.0
+        d.prior_fixed = 1e-3
+        h = ctypes.c_void_p()
+        assert L.dl_model_create(ctypes.byref(d), ctypes.byref(h)) == 1, (nx, nv)
+        assert not h.value
+    for nx, nv in ((100, 1), (58, 3)):
+        bp = (nv * nx * nx + 63) // 64 * 64
+        assert (2 * bp + 64) * 8 <= 160 * 1024
