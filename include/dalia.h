@@ -299,7 +299,9 @@ dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
  * (both only read the factor); every result is written to the caller's
  * stream order.  Requires flags bit 0 (DL_WS_SELINV), else DL_ESTATE;
  * DL_EINVAL for NULL pointers or an invalid ntheta.  Runs eagerly (also
- * for DL_WS_GRAPH workspaces). */
+ * for DL_WS_GRAPH workspaces).  DL_LIK_POISSON workspaces run fobj_eval's
+ * mode search on the caller's stream and then the selected inversion of
+ * Q_c(x*): the marginal variances of the Laplace approximation. */
 dl_status fobj_selinv_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                            double* fobj_dev, dl_fobj_parts* parts_dev, int64_t* info_dev,
                            double* diag_out_dev, void* stream);
