@@ -2,6 +2,10 @@
 surrogate-guided variant, from seeded starts theta_0 = theta* + 0.25 z.
 
     python -m paper_2507_06938_amd.opt_study --nx 12 --nt 12 --runs 16
+    python -m paper_2507_06938_amd.opt_study --config2 --runs 3
+
+``--config2`` takes the production trivariate model (30 x 30 mesh, nt = 48,
+b = 2700, 31-point gradients) instead of the generator at --nx/--nt.
 
 theta* and F* = -f_obj(theta*) come from a reference FD-BFGS run started at
 the generator's theta and driven to a small gradient.  Each method then runs
@@ -43,15 +47,35 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--config2", action="store_true",
+                    help="the production trivariate model (30x30, nt = 48)")
+    ap.add_argument("--progress-evals", type=int, default=500,
+                    help="print a progress line every this many exact evaluations")
     args = ap.parse_args(argv)
 
-    m_per = args.m_per or args.nv * args.nt * args.nx * args.nx
-    wl = W.scaled(f"opt_{args.nv}v_{args.nx}x{args.nx}_nt{args.nt}", args.nx, args.nt,
-                  args.nv, args.nr, m_per, seed=args.seed)
+    if args.config2:
+        wl = W.config2(seed=args.seed)
+    else:
+        m_per = args.m_per or args.nv * args.nt * args.nx * args.nx
+        wl = W.scaled(f"opt_{args.nv}v_{args.nx}x{args.nx}_nt{args.nt}", args.nx, args.nt,
+                      args.nv, args.nr, m_per, seed=args.seed)
     model = D.Model.from_workload(wl)
     d = wl.dim_theta
     B = 2 * d + 1
-    ev = O.Evaluator(model, B, graph=True)
+
+    class Logged(O.Evaluator):
+        """The batched evaluator with a progress line on stderr."""
+        mark = 0
+
+        def __call__(self, thetas):
+            v = super().__call__(thetas)
+            if self.count - self.mark >= args.progress_evals:
+                self.mark = self.count
+                print(f"  exact evaluations {self.count}, best F {min(self.archive_f):.10f}",
+                      file=sys.stderr, flush=True)
+            return v
+
+    ev = Logged(model, B, graph=True)
 
     # reference optimum
     t0 = time.perf_counter()
@@ -59,8 +83,12 @@ def main(argv=None):
     theta_star, F_star = ref.theta[-1], ref.f[-1]
     t_ref = time.perf_counter() - t0
 
+    print(f"reference: F* = {F_star:.12f}, {len(ref.f) - 1} iterations, {t_ref:.1f} s",
+          file=sys.stderr, flush=True)
+
     def fresh():
         ev.count = 0
+        ev.mark = 0
         ev.archive_x.clear()
         ev.archive_f.clear()
 
