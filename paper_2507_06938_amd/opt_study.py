@@ -49,6 +49,13 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--config2", action="store_true",
                     help="the production trivariate model (30x30, nt = 48)")
+    ap.add_argument("--ref-out", default=None,
+                    help="write theta* and F* of the reference run to this JSON file")
+    ap.add_argument("--ref-in", default=None,
+                    help="take theta* and F* from a file written by --ref-out "
+                         "instead of running the reference")
+    ap.add_argument("--first-run", type=int, default=0,
+                    help="index of the first seeded start (starts are drawn in order)")
     ap.add_argument("--progress-evals", type=int, default=500,
                     help="print a progress line every this many exact evaluations")
     args = ap.parse_args(argv)
@@ -78,13 +85,25 @@ def main(argv=None):
     ev = Logged(model, B, graph=True)
 
     # reference optimum
-    t0 = time.perf_counter()
-    ref = O.fd_bfgs(ev, wl.theta, h=1e-3, ftol=0.0, gtol=1e-5, max_iter=400)
-    theta_star, F_star = ref.theta[-1], ref.f[-1]
-    t_ref = time.perf_counter() - t0
-
-    print(f"reference: F* = {F_star:.12f}, {len(ref.f) - 1} iterations, {t_ref:.1f} s",
-          file=sys.stderr, flush=True)
+    if args.ref_in:
+        with open(args.ref_in) as fh:
+            saved = json.load(fh)
+        assert saved["workload"] == wl.name
+        theta_star, F_star = np.asarray(saved["theta_star"]), float(saved["F_star"])
+        ref_info = saved["reference"]
+    else:
+        t0 = time.perf_counter()
+        ref = O.fd_bfgs(ev, wl.theta, h=1e-3, ftol=0.0, gtol=1e-5, max_iter=400)
+        theta_star, F_star = ref.theta[-1], ref.f[-1]
+        t_ref = time.perf_counter() - t0
+        ref_info = {"iters": len(ref.f) - 1, "exact_evals": ref.exact_evals[-1],
+                    "wall_s": t_ref, "F_start": float(ref.f[0])}
+        print(f"reference: F* = {F_star:.12f}, {len(ref.f) - 1} iterations, {t_ref:.1f} s",
+              file=sys.stderr, flush=True)
+        if args.ref_out:
+            with open(args.ref_out, "w") as fh:
+                json.dump({"workload": wl.name, "theta_star": list(map(float, theta_star)),
+                           "F_star": float(F_star), "reference": ref_info}, fh)
 
     def fresh():
         ev.count = 0
@@ -94,8 +113,9 @@ def main(argv=None):
 
     runs = []
     rng = np.random.default_rng(12345 + args.seed)
-    starts = [theta_star + args.scale * rng.standard_normal(d) for _ in range(args.runs)]
-    for k, th0 in enumerate(starts):
+    starts = [theta_star + args.scale * rng.standard_normal(d)
+              for _ in range(args.first_run + args.runs)][args.first_run:]
+    for k, th0 in enumerate(starts, start=args.first_run):
         row = {"run": k}
         fresh()
         t0 = time.perf_counter()
@@ -133,8 +153,7 @@ def main(argv=None):
                 "mean_exact_evals": float(np.mean([r["exact_evals"] for r in ok])) if ok else None}
     out = {"workload": wl.name, "N": wl.N, "b": wl.b, "dim_theta": d, "batch": B,
            "F_star": float(F_star), "theta_star": list(map(float, theta_star)),
-           "reference": {"iters": len(ref.f) - 1, "exact_evals": ref.exact_evals[-1],
-                         "wall_s": t_ref, "F_start": float(ref.f[0])},
+           "reference": ref_info,
            "rtol": args.rtol, "start_scale": args.scale,
            "fd_bfgs": summ("fd"), "surrogate_bfgs": summ("surrogate"), "runs": runs}
     print(json.dumps(out), flush=True)
