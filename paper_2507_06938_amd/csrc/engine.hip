@@ -1581,14 +1581,16 @@ static dl_status eval_trials(dl_ws* W, const std::vector<double>& alpha,
 
 static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
   const int B = (int)W->inst.size();
-  DL_HIP_CHECK(run(W, W->asm_p[0], s));
-  DL_HIP_CHECK(run(W, W->fac_p[0], s));
   for (int k = 0; k < B; ++k) {
     Inst& I = W->inst[k];
     if (!(W->warm && W->has_mode[k] && k < nk))
       DL_HIP_CHECK(hipMemsetAsync(I.xcur, 0, sizeof(double) * I.m.Np, s));
     DL_HIP_CHECK(hipMemsetAsync(I.xN, 0, sizeof(double) * I.m.Np, s));
   }
+  // Q_p and the first step's Q_c(x0) share their launches
+  DL_HIP_CHECK(launch_lap_weights(W->d_lap, B, s));
+  DL_HIP_CHECK(run(W, W->asm_p[2], s));
+  DL_HIP_CHECK(run(W, W->fac_p[2], s));
   // state: 0 iterating, 1 converged, -1 failed, 2 idle (k >= nk)
   std::vector<int> state(B, 0), steps(B, 0), nh(B, 0);
   std::vector<double> alpha(B, 0.0), out(4 * B, 0.0), hcur(B, 0.0);
@@ -1601,9 +1603,11 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
     bool any = false;
     for (int k = 0; k < B; ++k) any = any || state[k] == 0;
     if (!any) break;
-    DL_HIP_CHECK(launch_lap_weights(W->d_lap, B, s));
-    DL_HIP_CHECK(run(W, W->asm_p[1], s));
-    DL_HIP_CHECK(run(W, W->fac_p[1], s));
+    if (it > 0) {
+      DL_HIP_CHECK(launch_lap_weights(W->d_lap, B, s));
+      DL_HIP_CHECK(run(W, W->asm_p[1], s));
+      DL_HIP_CHECK(run(W, W->fac_p[1], s));
+    }
     DL_HIP_CHECK(run(W, W->solve_p, s));
     for (auto& I : W->inst)
       DL_HIP_CHECK(hipMemcpyAsync(I.xN, I.mu, sizeof(double) * I.m.Np,
