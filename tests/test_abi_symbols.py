@@ -119,3 +119,21 @@ def test_model_create_rejects_blocks_beyond_the_lds_column_buffer():
     for nx, nv in ((100, 1), (58, 3)):
         bp = (nv * nx * nx + 63) // 64 * 64
         assert (2 * bp + 64) * 8 <= 160 * 1024
+
+
+def test_binding_constants_match_the_header():
+    """The flag, likelihood and family values the Python binding passes are
+    the ones include/dalia.h defines (read from the header text)."""
+    import re
+    from paper_2507_06938_amd import dalia as D
+    text = open(os.path.join(ROOT, "include", "dalia.h")).read()
+    vals = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"\b(DL_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    for name in ("DL_WS_SELINV", "DL_WS_KEEP_QP", "DL_WS_GRAPH", "DL_WS_MIXED",
+                 "DL_WS_SPLITK", "DL_WS_TWOSIDED", "DL_WS_FOLD_INV", "DL_WS_WARM_START",
+                 "DL_QP", "DL_QC", "DL_BOTH"):
+        assert getattr(D, name) == vals[name], name
+    assert D.LIKELIHOODS == {"gaussian": vals["DL_LIK_GAUSSIAN"],
+                             "poisson": vals["DL_LIK_POISSON"]}
+    assert D.MODEL_FAMILIES == {"separable": vals["DL_MODEL_SEPARABLE"],
+                                "diffusion": vals["DL_MODEL_DIFFUSION"]}

@@ -318,3 +318,26 @@ def test_poisson_without_observations_is_the_prior(D):
     assert p[2] == p[1] and p[3] == 0.0 and p[4] == 0.0
     assert f.item() == pytest.approx(OM.log_prior_theta(wl.theta, wl.theta_prior_mean,
                                                         wl.theta_prior_sd), rel=1e-14)
+
+
+def test_poisson_low_level_entry_points_use_the_last_iterate(D):
+    """After f_obj, bta_assemble and bta_factor of Q_c build Q_c with the
+    weights of the inner mode (the header's documented behaviour), so they
+    reproduce log|Q_c(x*)| bit for bit, and bta_solve of the assembled
+    right-hand side A^T (g + D A x*) returns x* itself (one more Newton
+    step from the mode)."""
+    wl = CASES["uni_2tiles"]()
+    model = D.Model.from_workload(wl)
+    ws = D.Workspace(model)
+    f, parts, _ = ws.fobj(wl.theta)
+    mode = ws.mean().clone()
+    torch.cuda.synchronize()
+    ws.assemble(wl.theta, D.DL_QC)
+    ld, info = ws.factor(D.DL_QC)
+    ws.solve()
+    x = ws.mean()
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0]
+    assert ld.cpu().item() == parts.cpu().numpy()[0][2]
+    m = mode.cpu().numpy()
+    assert np.max(np.abs(x.cpu().numpy() - m)) <= 1e-11 * np.max(np.abs(m))
