@@ -21,7 +21,10 @@ squared scale of the side of axis k that raises (lowers) theta_j.
 
 Host-side logic only; every f_obj value comes from the library's kernels.
 
-    python -m paper_2507_06938_amd.hessian [c1|c2] [--batch B]
+    python -m paper_2507_06938_amd.hessian [c1|c2|c1_poisson] [--batch B]
+
+(c1_poisson: the c1 mesh with counts; the batch workspace warm-starts each
+instance's inner Newton search from its previous mode.)
 
 prints one JSON document: the Hessian at the workload's generator theta,
 its eigenvalues, the evaluations and their rate.
@@ -153,17 +156,21 @@ def main(argv=None):
     from . import dalia as D
 
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("config", nargs="?", default="c1", choices=("c1", "c2"))
+    ap.add_argument("config", nargs="?", default="c1", choices=("c1", "c2", "c1_poisson"))
     ap.add_argument("--batch", type=int, default=0,
                     help="instances per pass (0: 2 dim + 1 for c1, 31 for c2)")
     ap.add_argument("--tiles", default=os.path.join(root, "paper_2507_06938_amd",
                                                     "tiles_gfx950.txt"))
     args = ap.parse_args(argv)
-    wl = W.config1() if args.config == "c1" else W.config2()
+    poisson = args.config == "c1_poisson"
+    wl = (W.config2() if args.config == "c2" else
+          W.config1(likelihood="poisson" if poisson else "gaussian"))
     d = wl.dim_theta
-    B = args.batch or (2 * d + 1 if args.config == "c1" else 31)
+    B = args.batch or (31 if args.config == "c2" else 2 * d + 1)
     model = D.Model.from_workload(wl)
-    ws = D.Workspace([model] * B, graph=True)
+    # counts: every instance's inner Newton search starts from its previous
+    # mode (the stencil points of consecutive passes are h apart)
+    ws = D.Workspace([model] * B, graph=True, warm_start=poisson)
     ws.autotune(args.tiles)
     fobj_hessian(ws, wl.theta)  # warm-up (graph capture)
     t0 = time.perf_counter()
@@ -175,6 +182,8 @@ def main(argv=None):
            "evals_per_s": vals.size / t, "f": float(f0),
            "hessian": H.tolist(), "eigenvalues": ev.tolist(),
            "negative_definite": bool(ev.max() < 0)}
+    if poisson:
+        out["newton_steps_last_pass"] = ws.newton_steps().tolist()
     if out["negative_definite"]:
         out["gaussian_marginal_sd"] = marginal_sd(H).tolist()
         A, sp, sm, sv = fobj_skew(ws, wl.theta, H, f0)
