@@ -285,8 +285,11 @@ dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
  * (its factor serves bta_selinv) and Eq. 8 is evaluated at mu = x*; an
  * instance that did not converge gets f = -inf.  These passes run eagerly
  * (also for DL_WS_GRAPH workspaces) and synchronise the stream once per
- * trial.  DL_WS_MIXED is not supported with DL_LIK_POISSON (DL_EINVAL at
- * dl_ws_create). */
+ * trial.  With DL_WS_MIXED every Newton solve is refined in FP64 against
+ * the sparse Q_c(x) (DL_REFINE_STEPS steps), so the mode is the FP64 one;
+ * log|Q_c(x*)| carries the FP32 error of the off-diagonal blocks, and mu is
+ * the refined solve at x* (one more Newton step from the mode, equal to it
+ * up to rounding). */
 dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                     double* fobj_dev, dl_fobj_parts* parts_dev,
                     int64_t* info_dev, void* stream);

@@ -1293,17 +1293,13 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   W->splitk = (flags & DL_WS_SPLITK) != 0;
   W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
   const bool two_sided = (flags & DL_WS_TWOSIDED) != 0;
-  // one likelihood per workspace; the Newton iteration needs FP64 storage
+  // one likelihood per workspace
   W->poisson = models[0]->d.likelihood == DL_LIK_POISSON;
   for (int k = 0; k < nmodels; ++k)
     if ((models[k]->d.likelihood == DL_LIK_POISSON) != W->poisson) {
       delete W;
       return DL_EINVAL;
     }
-  if (W->poisson && W->mixed) {
-    delete W;
-    return DL_EINVAL;
-  }
   W->newton_steps.assign(nmodels, 0);
   W->warm = (flags & DL_WS_WARM_START) != 0;
   W->has_mode.assign(nmodels, 0);
@@ -1609,6 +1605,8 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
       DL_HIP_CHECK(run(W, W->fac_p[1], s));
     }
     DL_HIP_CHECK(run(W, W->solve_p, s));
+    // mixed precision: refine x_N in FP64 against the sparse Q_c(x)
+    if (W->mixed) DL_HIP_CHECK(run(W, W->refine_p, s));
     for (auto& I : W->inst)
       DL_HIP_CHECK(hipMemcpyAsync(I.xN, I.mu, sizeof(double) * I.m.Np,
                                   hipMemcpyDeviceToDevice, s));

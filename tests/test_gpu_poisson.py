@@ -168,12 +168,10 @@ def test_poisson_fobj_selinv_equals_fobj_then_selinv(D):
     assert np.array_equal(var, var2)
 
 
-def test_poisson_rejects_mixed_precision_and_mixed_likelihoods(D):
+def test_poisson_rejects_mixed_likelihoods(D):
     pw = CASES["uni_2tiles"]()
     gw = W.config0()
     pm, gm = D.Model.from_workload(pw), D.Model.from_workload(gw)
-    with pytest.raises(D.DaliaError):
-        D.Workspace(pm, mixed=True)
     with pytest.raises(D.DaliaError):
         D.Workspace([pm, gm])
     # a Gaussian workspace reports no Newton steps
@@ -341,3 +339,28 @@ def test_poisson_low_level_entry_points_use_the_last_iterate(D):
     assert ld.cpu().item() == parts.cpu().numpy()[0][2]
     m = mode.cpu().numpy()
     assert np.max(np.abs(x.cpu().numpy() - m)) <= 1e-11 * np.max(np.abs(m))
+
+
+@pytest.mark.parametrize("name", ["uni_19tiles", "tri_damped"])
+def test_poisson_mixed_precision(D, name):
+    """DL_WS_MIXED with counts: the Newton solves are refined in FP64, so the
+    mode and the step count match the FP64 workspace; log|Q_p| and log|Q_c|
+    carry the FP32 error of the off-diagonal blocks (1e-4 relative, as for
+    the Gaussian likelihood) and the variances agree to 1e-2."""
+    wl = CASES[name]()
+    model = D.Model.from_workload(wl)
+    out = {}
+    for tag, kw in (("fp64", {}), ("mixed", {"mixed": True})):
+        ws = D.Workspace(model, selinv=True, two_sided=True, **kw)
+        out[tag] = evaluate(ws, wl.theta) + (ws.newton_steps()[0],)
+        del ws
+    f64, p64, i64, mu64, v64, s64 = out["fp64"]
+    fmx, pmx, imx, mumx, vmx, smx = out["mixed"]
+    print(name, "steps", s64, smx, "f", f64[0], fmx[0], flush=True)
+    assert imx.tolist() == [[0, 0]] and abs(int(smx) - int(s64)) <= 1
+    assert np.max(np.abs(mumx - mu64)) <= 1e-9 * np.max(np.abs(mu64))
+    assert pmx[0][7] <= 1e-12
+    assert abs(pmx[0][1] - p64[0][1]) <= 1e-4 * abs(p64[0][1])
+    assert abs(pmx[0][2] - p64[0][2]) <= 1e-4 * abs(p64[0][2])
+    assert abs(fmx[0] - f64[0]) <= 1e-4 * abs(p64[0][2])
+    np.testing.assert_allclose(vmx, v64, rtol=1e-2)
