@@ -1,6 +1,6 @@
 """Write the stored expected values of the full-size parity tests.
 
-    python tests/golden/make_golden.py c1 [c2] [c1_diffusion] [c1_poisson]
+    python tests/golden/make_golden.py c1 [c2] [c1_diffusion] [c1_poisson] [c2_poisson]
 
 Calls only the CPU oracle (``oracle/``) on the seeded workloads of
 ``workloads/``; nothing here touches the GPU path.  For each configuration it
@@ -27,7 +27,8 @@ from oracle import model as OM  # noqa: E402
 
 CONFIGS = {"c1": W.config1, "c2": W.config2,
            "c1_diffusion": lambda: W.config1(model="diffusion"),
-           "c1_poisson": lambda: W.config1(likelihood="poisson")}
+           "c1_poisson": lambda: W.config1(likelihood="poisson"),
+           "c2_poisson": lambda: W.config2(likelihood="poisson")}
 
 
 def sample_positions(N, a, k, seed):

@@ -265,18 +265,22 @@ def test_poisson_warm_start(D):
 
 
 @pytest.mark.parametrize("kw", [{}, {"two_sided": True, "fold_inverse": True}])
-def test_poisson_fullsize_against_banded_oracle(D, kw):
-    """The production-size count workload (45 x 45, nt = 100, m = 200000)
-    against values stored by tests/golden/make_golden.py (oracle: damped
-    Newton with RCM + banded LAPACK Cholesky): log-determinants, f_obj, the
-    inner mode and the Laplace marginal variances at seeded positions."""
+@pytest.mark.parametrize("name,make", [
+    ("c1_poisson", lambda: W.config1(likelihood="poisson")),
+    ("c2_poisson", lambda: W.config2(likelihood="poisson"))])
+def test_poisson_fullsize_against_banded_oracle(D, name, make, kw):
+    """The production-size count workloads (univariate 45 x 45, nt = 100,
+    m = 200000; trivariate 30 x 30, nt = 48, m = 3 x 43200) against values
+    stored by tests/golden/make_golden.py (oracle: damped Newton with RCM +
+    banded LAPACK Cholesky): log-determinants, f_obj, the inner mode and the
+    Laplace marginal variances at seeded positions."""
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "c1_poisson_golden.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_golden.json")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     g = json.load(open(path))
-    wl = W.config1(likelihood="poisson")
+    wl = make()
     model = D.Model.from_workload(wl)
     ws = D.Workspace(model, selinv=True, **kw)
     f, parts, info = ws.fobj(np.asarray(g["theta"]))

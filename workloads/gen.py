@@ -247,11 +247,15 @@ def config1(seed: int = 0, model: str = "separable",
                            likelihood=likelihood)
 
 
-def config2(seed: int = 0, model: str = "separable") -> Workload:
+def config2(seed: int = 0, model: str = "separable",
+            likelihood: str = "gaussian") -> Workload:
     """Trivariate coregional: 30x30 grid (b=2700), nt=48, nr=2 (a=6),
-    m = 3 x 48 x 900."""
-    return make_trivariate("c2_trivariate_30x30_nt48" + _suffix(model), 30,
-                           48, 2, 48 * 900, seed=seed, model=model)
+    m = 3 x 48 x 900 (counts with ``likelihood="poisson"``)."""
+    name = "c2_trivariate_30x30_nt48" + _suffix(model)
+    if likelihood != "gaussian":
+        name += "_" + likelihood
+    return make_trivariate(name, 30, 48, 2, 48 * 900, seed=seed, model=model,
+                           likelihood=likelihood)
 
 
 def scaled(name: str, nx: int, nt: int, nv: int, nr: int, m_per: int,
