@@ -53,12 +53,15 @@ class Evaluator:
     line searches."""
 
     def __init__(self, model: "D.Model", batch: int, graph: bool = True, ntrial: int = 4,
-                 warm_start: bool = False):
+                 warm_start: Optional[bool] = None):
         self.model = model
         self.B = batch
         self.ntrial = ntrial
-        # warm_start (Poisson likelihood): each instance's inner Newton search
-        # starts from its mode of the previous pass
+        # warm_start (Poisson likelihood; the default for it): each instance's
+        # inner Newton search starts from its mode of the previous pass, which
+        # the nearby points of consecutive gradients and line searches reuse
+        if warm_start is None:
+            warm_start = getattr(model, "likelihood", "gaussian") == "poisson"
         self.ws = D.Workspace([model] * batch, graph=graph, warm_start=warm_start)
         self.ws_ls = D.Workspace([model] * ntrial, graph=graph, warm_start=warm_start)
         self.dim = model.dim_theta

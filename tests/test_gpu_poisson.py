@@ -224,6 +224,12 @@ def test_poisson_mode_search_and_hessian_match_oracle(D):
     tr = O.fd_bfgs(ev, theta0, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300)
     print(f"oracle F*={fs:.12f}  gpu F={tr.f[-1]:.12f}  iters={len(tr.f) - 1}", flush=True)
     assert abs(tr.f[-1] - fs) <= 1e-6 * abs(fs)
+    # the evaluator warm-starts the inner search by default for counts, and a
+    # cold evaluator reaches the same optimum
+    assert ev.ws.newton_steps().max() <= 4
+    ev_cold = O.Evaluator(model, batch=2 * wl.dim_theta + 1, warm_start=False)
+    tr_cold = O.fd_bfgs(ev_cold, theta0, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300)
+    assert abs(tr_cold.f[-1] - fs) <= 1e-6 * abs(fs)
     d = wl.dim_theta
     ws = D.Workspace([model] * (2 * d * d + 1))
     H_gpu, f0, vals = GH.fobj_hessian(ws, xs, 1e-3)
