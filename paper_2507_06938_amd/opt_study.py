@@ -5,7 +5,9 @@ surrogate-guided variant, from seeded starts theta_0 = theta* + 0.25 z.
     python -m paper_2507_06938_amd.opt_study --config2 --runs 3
 
 ``--config2`` takes the production trivariate model (30 x 30 mesh, nt = 48,
-b = 2700, 31-point gradients) instead of the generator at --nx/--nt.
+b = 2700, 31-point gradients) instead of the generator at --nx/--nt, and
+``--config1`` the production univariate mesh (45 x 45, nt = 100); with
+``--likelihood poisson`` the responses are counts.
 
 theta* and F* = -f_obj(theta*) come from a reference FD-BFGS run started at
 the generator's theta and driven to a small gradient.  Each method then runs
@@ -49,6 +51,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--config2", action="store_true",
                     help="the production trivariate model (30x30, nt = 48)")
+    ap.add_argument("--config1", action="store_true",
+                    help="the production univariate mesh (45x45, nt = 100)")
+    ap.add_argument("--likelihood", choices=("gaussian", "poisson"), default="gaussian",
+                    help="responses: Gaussian, or counts (inner Newton search, "
+                         "warm-started by the evaluator)")
     ap.add_argument("--ref-out", default=None,
                     help="write theta* and F* of the reference run to this JSON file")
     ap.add_argument("--ref-in", default=None,
@@ -61,11 +68,13 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.config2:
-        wl = W.config2(seed=args.seed)
+        wl = W.config2(seed=args.seed, likelihood=args.likelihood)
+    elif args.config1:
+        wl = W.config1(seed=args.seed, likelihood=args.likelihood)
     else:
         m_per = args.m_per or args.nv * args.nt * args.nx * args.nx
         wl = W.scaled(f"opt_{args.nv}v_{args.nx}x{args.nx}_nt{args.nt}", args.nx, args.nt,
-                      args.nv, args.nr, m_per, seed=args.seed)
+                      args.nv, args.nr, m_per, seed=args.seed, likelihood=args.likelihood)
     model = D.Model.from_workload(wl)
     d = wl.dim_theta
     B = 2 * d + 1
