@@ -86,7 +86,7 @@ def fobj(wl, theta, method: str = "auto") -> float:
 
 def marginal_variances(wl, theta, idx=None, method: str = "auto"):
     """diag(Q_c^{-1}) at model-order indices ``idx`` (all if None): the
-    marginal variances of the latent field (Section III, selected
+    marginal variances of the latent field (Section III-A, selected
     inversion)."""
     Qp = M.prior_precision(wl, theta)
     Qc = M.conditional_precision(wl, theta, Qp=Qp)

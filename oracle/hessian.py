@@ -1,5 +1,5 @@
 """CPU oracle -- the Hessian of f at the mode and the Gaussian approximation
-of the hyperparameter marginals (Sec. II-C, marginal posteriors of the
+of the hyperparameter marginals (Sec. III, marginal posteriors of the
 hyperparameters).
 
 TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the

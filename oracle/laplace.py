@@ -1,5 +1,5 @@
 """CPU FP64 oracle -- f_obj(theta) for a non-Gaussian likelihood (Section
-II-B, conditional Gaussian distribution, Eq. 3, 4 and 8).
+II-A, conditional Gaussian distribution, Eq. 3, 4 and 8).
 
 TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import or run anything in

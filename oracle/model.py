@@ -21,7 +21,7 @@ each function.
 Two model families: ``wl.model == "separable"`` (AR1 in time times the
 Matern SPDE precision in space) and ``"diffusion"``, the non-separable
 space-time model written as a sum of Kronecker products of temporal and
-spatial FEM matrices (Section III-B, multivariate models, which builds every
+spatial FEM matrices (Section IV-B, multivariate model formulation, which builds every
 univariate precision that way).
 """
 from __future__ import annotations
@@ -203,7 +203,7 @@ def spatial_operator_powers(nx: int, gamma_s: float):
 
 def diffusion_precision(nx: int, nt: int, gamma_s: float, gamma_t: float):
     """Non-separable space-time precision as a sum of Kronecker products of
-    temporal and spatial FEM matrices, time outermost (Section III-B,
+    temporal and spatial FEM matrices, time outermost (Section IV-B,
     multivariate models, citing the diffusion-based family of Lindgren et
     al.).  The paper gives no formula; read as the critical diffusion model
     with one time derivative, a second-order spatial operator and a
@@ -361,7 +361,7 @@ def conditional_precision(wl, theta, Qp=None, A=None) -> sp.csr_matrix:
 def bta_permutation(nv: int, ns: int, nt: int, nr: int) -> np.ndarray:
     """perm[k] = model-order index of the variable at BTA position k.
 
-    BTA order (Section III-B, permutation): all variables of time step 0 first
+    BTA order (Section IV-B, permutation): all variables of time step 0 first
     (response by response, each in spatial order), then time step 1, ...,
     with all fixed effects gathered at the end."""
     b = nv * ns

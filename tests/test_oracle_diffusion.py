@@ -1,7 +1,7 @@
 """Pins of the oracle's non-separable (diffusion-based) space-time model.
 
 The model is a sum of Kronecker products of temporal and spatial FEM matrices
-(Section III-B, multivariate models).  The oracle assembles it as sparse
+(Section IV-B, multivariate model formulation).  The oracle assembles it as sparse
 matrix products; these checks reach the same numbers by other routes:
 
   * the temporal FEM matrices against the integrals they discretise, on

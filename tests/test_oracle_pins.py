@@ -239,7 +239,7 @@ def test_single_block_reduces_to_lapack():
 
 @pytest.mark.parametrize("nv", [1, 3])
 def test_bta_order_gives_bta_pattern(nv):
-    """After the permutation of Section III-B, Q_c is block tridiagonal with an
+    """After the permutation of Section IV-B, Q_c is block tridiagonal with an
     arrowhead and Q_p is block tridiagonal (observations stay inside the
     spatial pattern; fixed effects only couple through the arrow)."""
     wl = W.scaled("pat", 5, 4, nv, 2, 30, seed=1)
