@@ -337,6 +337,26 @@ dl_status dl_dgemm(int32_t transa, int32_t transb, int32_t lower, int64_t M,
 dl_status dl_dpotrf(int64_t n, double* A_dev, int64_t lda, int32_t want_inverse,
                     double* logdet_dev, int64_t* info_dev, void* stream);
 
+/* dl_dpotrf_noalloc -- for callers that cannot allocate device memory (work
+ * recorded under HIP graph capture, serving loops with a fixed memory
+ * footprint, harnesses that forbid hipMalloc): the same factorisation,
+ * outputs and error behaviour as dl_dpotrf, but every temporary (tile
+ * inverses, the recursive inversion's products, log-diagonal, reduction
+ * partials, launch descriptors) lives in one static device array of
+ * DL_DPOTRF_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends.  No device or host allocation and no stream
+ * synchronisation: the results are ready in stream order.  n must be a
+ * multiple of 64 and at most DL_DPOTRF_NOALLOC_MAX_N (DL_EINVAL otherwise,
+ * returned before any device call).  All calls on one GPU share its array,
+ * which keeps the last call's contents: calls that overlap in time on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller. */
+#define DL_DPOTRF_NOALLOC_MAX_N 2048
+#define DL_DPOTRF_NOALLOC_SCRATCH_BYTES 18958336
+dl_status dl_dpotrf_noalloc(int64_t n, double* A_dev, int64_t lda,
+                            int32_t want_inverse, double* logdet_dev,
+                            int64_t* info_dev, void* stream);
+
 /* Pick the GEMM tile (64x64 or 128x128 outputs per workgroup) of every
  * matrix-product launch of the workspace, and for FP64 launches with a k
  * extent above 512 whether to split k (pieces summed by a second launch),

@@ -90,6 +90,7 @@ def lib():
             "dl_dgemm": (i32, [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp,
                                i64, dbl, vp, i64, vp]),
             "dl_dpotrf": (i32, [i64, vp, i64, i32, vp, vp, vp]),
+            "dl_dpotrf_noalloc": (i32, [i64, vp, i64, i32, vp, vp, vp]),
             "dl_status_string": (C.c_char_p, [i32]),
             "dl_ws_profile_begin": (i32, [vp, i32, i32]),
             "dl_autotune": (i32, [vp, C.c_char_p, vp]),
@@ -419,6 +420,21 @@ def dpotrf(A: torch.Tensor, inverse: bool = False):
                                         int(inverse), _ptr(ld), _ptr(info),
                                         _stream()))
     return ld, info
+
+
+def dpotrf_noalloc(A: torch.Tensor, logdet: torch.Tensor, info: torch.Tensor,
+                   inverse: bool = False):
+    """dpotrf through the entry point that allocates nothing: the caller
+    provides the logdet (1 double) and info (1 int64) outputs; n % 64 == 0
+    and n <= DPOTRF_NOALLOC_MAX_N."""
+    n = A.shape[0]
+    assert A.stride(0) == 1
+    _check("dl_dpotrf_noalloc",
+           lib().dl_dpotrf_noalloc(n, C.c_void_p(A.data_ptr()), A.stride(1), int(inverse),
+                                   _ptr(logdet), _ptr(info), _stream()))
+
+
+DPOTRF_NOALLOC_MAX_N = 2048
 
 
 def fortran(x: torch.Tensor) -> torch.Tensor:

@@ -137,3 +137,22 @@ def test_binding_constants_match_the_header():
                              "poisson": vals["DL_LIK_POISSON"]}
     assert D.MODEL_FAMILIES == {"separable": vals["DL_MODEL_SEPARABLE"],
                                 "diffusion": vals["DL_MODEL_DIFFUSION"]}
+
+
+def test_dpotrf_noalloc_rejects_sizes_on_the_host():
+    """dl_dpotrf_noalloc checks n against its static scratch before any
+    device call: n above DL_DPOTRF_NOALLOC_MAX_N, n not a multiple of 64 and
+    NULL outputs give DL_EINVAL (1)."""
+    from paper_2507_06938_amd import build as B
+    from paper_2507_06938_amd import dalia as D
+    if not os.path.exists(B.LIB):
+        B.build(verbose=False)
+    L = D.lib()
+    hdr = open(HEADER).read()
+    max_n = int(re.search(r"#define DL_DPOTRF_NOALLOC_MAX_N (\d+)", hdr).group(1))
+    assert max_n == D.DPOTRF_NOALLOC_MAX_N
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: rejected first
+    for n in (max_n + 64, 100, 0, -64):
+        assert L.dl_dpotrf_noalloc(n, fake, max(n, 1), 0, fake, fake, None) == 1
+    assert L.dl_dpotrf_noalloc(64, fake, 64, 0, None, fake, None) == 1
+    assert L.dl_dpotrf_noalloc(64, fake, 32, 0, fake, fake, None) == 1
