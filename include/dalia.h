@@ -9,12 +9,12 @@
  *     (Section II-A), mixed over responses by the coregional form Eq. 11, with
  *     fixed effects appended (Eq. 2);
  *   - Q_c(theta) = Q_p + A^T D A (Eq. 4), block tridiagonal with arrowhead
- *     (BTA) once permuted time-major (Section III-B);
+ *     (BTA) once permuted time-major (Section IV-B, permutation);
  *   - f_obj(theta) = log p(theta) + log l(y|theta,x) + log p(x|theta)
  *                    - log p_G(x|theta,y)                         (Eq. 8)
  *     which needs log|Q_p|, log|Q_c| (Cholesky, Eq. 1, 3), the conditional
  *     mean mu (triangular solves) and, for marginal variances, selected
- *     entries of Q_c^{-1} (selected inversion, Section III).
+ *     entries of Q_c^{-1} (selected inversion, Section III-A).
  *
  * Conventions for every entry point below:
  *   - Pointers named *_dev are device pointers owned by the caller; pointers
@@ -79,8 +79,8 @@ typedef struct dl_model_desc {
   int32_t likelihood;             /* DL_LIK_GAUSSIAN (0) or DL_LIK_POISSON */
 } dl_model_desc;
 
-/* Model families of each univariate process (Section II-A; Section III-B,
- * multivariate models, which builds each univariate precision as a sum of
+/* Model families of each univariate process (Section II-A; Section IV-B,
+ * multivariate model formulation, which builds each univariate precision as a sum of
  * Kronecker products of temporal and spatial FEM matrices).
  *   DL_MODEL_SEPARABLE  T (x) Q_s: unit-variance AR1 in time times the SPDE
  *                       precision Q_s = kappa^4 C + 2 kappa^2 G + G C^-1 G.
@@ -94,8 +94,8 @@ typedef struct dl_model_desc {
  *                       distance 3 (25 points) instead of 2 (13 points). */
 enum { DL_MODEL_SEPARABLE = 0, DL_MODEL_DIFFUSION = 1 };
 
-/* Likelihood of the responses (Section II-B, conditional Gaussian
- * distribution: D in Q_c = Q_p + A^T D A is the negative Hessian of the
+/* Likelihood of the responses (Section II-A, its conditional Gaussian
+ * distribution part: D in Q_c = Q_p + A^T D A is the negative Hessian of the
  * log-likelihood, Eq. 4).
  *   DL_LIK_GAUSSIAN  y_i ~ N((A x)_i, 1/tau_y_j) (Eq. 2): D = tau_y, p_G is
  *                    exact and its mean solves Q_c mu = A^T D y.
@@ -170,8 +170,8 @@ enum {
                          cores (FP32 accumulation, subtracted into FP64
                          diagonal blocks and tips); diagonal-block Cholesky,
                          inverses and log-determinants stay FP64; the mean
-                         is refined in FP64 against the sparse Q_c
-                         (DL_REFINE_STEPS steps)                           */,
+                         is refined in FP64 against the sparse Q_c to
+                         DL_REFINE_TOL (see below)                         */,
   DL_WS_SPLITK = 16   /* split the long inner dimensions of the FP64 block
                          products (factor, inverse, selected inversion) into
                          pieces of 512 summed in a fixed order: more
@@ -179,7 +179,7 @@ enum {
                          differ from an unsplit workspace by rounding only
                          and do not depend on the tile sizes chosen         */,
   DL_WS_TWOSIDED = 32 /* time-domain partitioning into two partitions on one
-                         GPU (Sec. III-C, time-domain partitioning, with
+                         GPU (Sec. IV-C, time-domain partitioning, with
                          S3's nested dissection for two partitions, which
                          have no middle partition and so add no work): the
                          first half of the time steps is eliminated forward
@@ -208,7 +208,22 @@ enum {
                          differ from a cold start by rounding only, but they
                          depend on the call history                        */
 };
-#define DL_REFINE_STEPS 3
+/* FP64 iterative refinement of the mean (DL_WS_MIXED workspaces; any
+ * workspace through bta_solve on request): x <- x + c, where c solves
+ * (L L^T) c = rhs - Q_c x with the workspace's factor and the residual is
+ * formed with the sparse FP64 Q_c, until |rhs - Q_c x|_2 <= tol |rhs|_2.
+ * Eager evaluations take at most DL_REFINE_MAX corrections with tol =
+ * DL_REFINE_TOL (the host reads the residual norms after each one); a
+ * DL_WS_GRAPH workspace captures DL_REFINE_STEPS_GRAPH correction steps.
+ * Within a batch an instance that meets the tolerance keeps its iterate bit
+ * for bit while the others continue, so batch, single and graph-replayed
+ * results agree.  A refined mean that still misses the tolerance is
+ * reported as info_dev[2k+1] = DL_INFO_NOTCONV (the pivots were fine, f and
+ * its parts are written). */
+#define DL_REFINE_TOL 1e-12
+#define DL_REFINE_MAX 10
+#define DL_REFINE_STEPS_GRAPH 3
+#define DL_INFO_NOTCONV (-1)
 
 /* Allocate the dense BTA workspace for Q_p and Q_c of `model`.  All device
  * memory of the evaluation path is allocated here. */
@@ -234,41 +249,70 @@ size_t dl_ws_bytes(const dl_ws* ws);
  * dl_ws_batch(ws) values.  Gaussian workspaces report 0. */
 dl_status dl_ws_newton_steps(const dl_ws* ws, int32_t* steps_host);
 
-/* bta_assemble -- step a1+a2: theta (dim_theta doubles, device) ->
- * coefficient table and log p(theta), then the dense BTA blocks of Q_p and/or
- * Q_c (Eq. 4, Eq. 11, time-major permutation of Section III-B) and the
- * right-hand side A^T D y.  Only the lower triangle of each diagonal block
+/* bta_assemble -- theta (dim_theta doubles, device) -> the model
+ * coefficients (Eq. 5, Eq. 11) and log p(theta), then the dense BTA blocks
+ * of Q_p and/or Q_c (Eq. 4, Eq. 11; Section IV-B, permutation; Section
+ * IV-F, sparse to structured dense mapping) and the right-hand side
+ * A^T D y of Eq. 3.  DL_ESTATE never; asynchronous.  Only the lower triangle of each diagonal block
  * is stored.  For DL_LIK_POISSON models D and the right-hand side come
  * from the workspace's last inner iterate (D = 0 before the first
  * fobj_eval). */
 dl_status bta_assemble(dl_ws* ws, const double* theta_dev, dl_which which,
                        void* stream);
 
-/* bta_factor -- steps a3+a4: BTA Cholesky of Q_p and/or Q_c in place (per
- * time step: POTRF of the diagonal block, its inverse, TRSM of the
- * sub-diagonal and arrow blocks, SYRK/GEMM updates of the next diagonal
- * block, the arrow and the tip; finally POTRF of the tip).  Writes
- * log|Q| to logdet_dev[0] (and logdet_dev[1] for DL_BOTH: [Q_p, Q_c]) and
- * the first bad pivot to info_dev[0] (info_dev[1] for DL_BOTH). */
+/* bta_factor -- the BTA Cholesky factorisation and log-determinants
+ * (Section III-A, Cholesky factorization and triangular solve: the block
+ * recurrence of the structured solver; Eq. 1 and 3 need log|Q|).  In place
+ * on the assembled blocks of Q_p and/or Q_c: per time step POTRF of the
+ * diagonal block D_t and its inverse, [B_t; R_t] <- [B_t; R_t] L_tt^-T, the
+ * Schur updates of the next diagonal block, its arrow block and the tip;
+ * finally POTRF of the tip.  logdet_dev[0] (and logdet_dev[1] for DL_BOTH:
+ * [Q_p, Q_c]) receives log|Q| = 2 sum log L_ii; info_dev[0] (info_dev[1]
+ * for DL_BOTH) the first bad pivot as 1 + its BTA row (0: positive
+ * definite).  A batch workspace writes cnt values per instance (cnt = 2
+ * for DL_BOTH, else 1).  Either pointer may be NULL.  DL_ESTATE unless the
+ * matrix was assembled since its last factorisation.  Asynchronous. */
 dl_status bta_factor(dl_ws* ws, dl_which which, double* logdet_dev,
                      int64_t* info_dev, void* stream);
 
-/* bta_solve -- step a6: solves Q_c x = rhs with the factor of Q_c, in place
- * on rhs_inout_dev (N doubles, BTA order).  rhs_inout_dev may be NULL: then
- * the assembled A^T D y is solved and the mean mu is kept in the
- * workspace (read it with dl_ws_mean). */
-dl_status bta_solve(dl_ws* ws, double* rhs_inout_dev, void* stream);
+/* bta_solve -- Q_c x = r with the factor of Q_c (Section III-A, Cholesky
+ * factorization and triangular solve: forward then backward block
+ * substitution; with r = A^T D y, x is the conditional mean of Eq. 3).
+ *   rhs_inout_dev == NULL: solves the assembled A^T D y (nrhs 0 or 1) and
+ *     keeps the mean in the workspace (dl_ws_mean);
+ *   otherwise nrhs >= 1 right-hand sides of N_total doubles each (BTA
+ *     order, a batch workspace's instances packed in order), solved in
+ *     place one after the other (the workspace's own right-hand side is
+ *     overwritten).
+ * refine_max < 0: the workspace's default refinement (DL_WS_MIXED: to
+ * DL_REFINE_TOL in at most DL_REFINE_MAX corrections; FP64: none).
+ * refine_max >= 0 (at most 100): at most refine_max FP64 corrections
+ * against the sparse Q_c until |r - Q_c x|_2 <= refine_tol |r|_2 (see the
+ * refinement constants above); with refine_max > 0 the call reads residual
+ * norms on the host (it synchronises the stream) and returns DL_ENOTCONV
+ * when some solve still misses refine_tol (its x is written all the same).
+ * DL_EINVAL for a bad nrhs, refine_max or refine_tol; DL_ESTATE before a
+ * factorisation of Q_c. */
+dl_status bta_solve(dl_ws* ws, double* rhs_inout_dev, int32_t nrhs, int32_t refine_max,
+                    double refine_tol, void* stream);
 
-/* bta_selinv -- step a7: Takahashi selected inversion of Q_c from its factor
- * (backward in time); writes diag(Q_c^{-1}) to diag_out_dev (N doubles, BTA
- * order).  Requires flags bit 0 at dl_ws_create and a prior bta_factor of
- * Q_c; otherwise DL_ESTATE. */
+/* bta_selinv -- Takahashi selected inversion (Section III-A, selected
+ * inversion: the entries of Q_c^-1 on the BTA pattern from the factor,
+ * backward in time, Eq. 1's marginal variances on the diagonal); writes
+ * diag(Q_c^{-1}) to diag_out_dev (N doubles per instance, BTA order,
+ * instances packed).  Requires flags bit 0 (DL_WS_SELINV) at creation and a
+ * factorisation of Q_c; otherwise DL_ESTATE.  Asynchronous. */
 dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
 
-/* fobj_eval -- steps a1..a8: f_obj (Eq. 8) for ntheta hyperparameter vectors
+/* fobj_eval -- f_obj (Eq. 8, evaluated at the conditional mean) for ntheta
+ * hyperparameter vectors: assembly, both factorisations, the solve for the
+ * mean, the quadratic forms and the combination of Eq. 8's terms
  * (theta_dev: ntheta x dim_theta, row-major).  fobj_dev[k], parts_dev[k]
  * (may be NULL) and info_dev[2k..2k+1] (Q_p, Q_c pivots; may be NULL)
- * receive the results.  A batch workspace of B instances evaluates B thetas
+ * receive the results; info_dev[2k+1] = DL_INFO_NOTCONV flags a refined
+ * mean (DL_WS_MIXED) that missed DL_REFINE_TOL.  DL_WS_MIXED evaluations
+ * that run eagerly read the residual norms on the host after each
+ * correction (one synchronisation each).  A batch workspace of B instances evaluates B thetas
  * per pass (ntheta may be any count when all instances share one model;
  * otherwise ntheta must equal B).  mu of the last pass stays in the
  * workspace.
@@ -286,7 +330,7 @@ dl_status bta_selinv(dl_ws* ws, double* diag_out_dev, void* stream);
  * instance that did not converge gets f = -inf.  These passes run eagerly
  * (also for DL_WS_GRAPH workspaces) and synchronise the stream once per
  * trial.  With DL_WS_MIXED every Newton solve is refined in FP64 against
- * the sparse Q_c(x) (DL_REFINE_STEPS steps), so the mode is the FP64 one;
+ * the sparse Q_c(x) (to DL_REFINE_TOL), so the mode is the FP64 one;
  * log|Q_c(x*)| carries the FP32 error of the off-diagonal blocks, and mu is
  * the refined solve at x* (one more Newton step from the mode, equal to it
  * up to rounding). */
@@ -294,8 +338,8 @@ dl_status fobj_eval(dl_ws* ws, const double* theta_dev, int32_t ntheta,
                     double* fobj_dev, dl_fobj_parts* parts_dev,
                     int64_t* info_dev, void* stream);
 
-/* fobj_selinv_eval -- steps a1..a8 and a7 together: f_obj as fobj_eval for
- * one pass of ntheta (1..B; B when the instances' models differ) thetas,
+/* fobj_selinv_eval -- f_obj and the marginal variances together: f_obj as
+ * fobj_eval for one pass of ntheta (1..B; B when the instances' models differ) thetas,
  * and diag(Q_c^{-1}) of every instance as bta_selinv (diag_out_dev: the
  * instances' N values in order).  The solve and quadratic forms run on a
  * second, library-owned stream concurrently with the selected inversion
@@ -315,11 +359,58 @@ dl_status dl_ws_mean(dl_ws* ws, double* out_dev, void* stream);
 /* Copy one assembled (or factored) block to out_dev, column-major, for
  * inspection: kind 0 = diagonal block D_t (b x b, lower triangle), 1 =
  * sub-diagonal block B_t (b x b, rows t+1, cols t), 2 = arrow block R_t
- * (a x b), 3 = tip (a x a, lower triangle), 4 = right-hand side (N).  After
- * a DL_WS_TWOSIDED factorisation kind 1 at t >= mid holds the factor's
- * coupling of block t to block t-1 (its successor in that order). */
-dl_status dl_ws_get_block(dl_ws* ws, dl_which which, int32_t kind, int32_t t,
+ * (a x b), 3 = tip (a x a, lower triangle), 4 = right-hand side (N, Q_c
+ * only).  After a DL_WS_TWOSIDED factorisation kind 1 at t >= mid holds the
+ * factor's coupling of block t to block t-1 (its successor in that order).
+ * Single-instance workspaces; Q_p blocks other than the tip need
+ * DL_WS_KEEP_QP (DL_ESTATE otherwise).  Synchronises the stream. */
+dl_status dl_ws_get_block(dl_ws* W, dl_which which, int32_t kind, int32_t t,
                           double* out_dev, void* stream);
+
+/* The reverse of dl_ws_get_block: overwrite one block of an assembled (not
+ * yet factored) matrix with in_dev (column-major, unpadded sizes as above;
+ * for diagonal blocks and the tip only the lower triangle is used), so that
+ * bta_factor / bta_solve / bta_selinv run on a caller-supplied BTA matrix
+ * (the padding keeps its identity).  DL_WS_TWOSIDED workspaces read each
+ * sub-diagonal block also as its own transpose, so they need symmetric
+ * B_t.  DL_ESTATE unless the matrix was assembled since its last
+ * factorisation (or for Q_p blocks without DL_WS_KEEP_QP).  Synchronises the
+ * stream. */
+dl_status dl_ws_set_block(dl_ws* W, dl_which which, int32_t kind, int32_t t,
+                          const double* in_dev, void* stream);
+
+/* Model order <-> BTA order (Section IV-B, permutation).  Model order is the
+ * response-major order of Eq. 11: latent variable (response j, time t,
+ * node s) at j*nt*ns + t*ns + s, then the fixed effects (j, r) at
+ * nt*nv*ns + j*nr + r; BTA order is the one described at the top of this
+ * file.  dl_permute: bta_dev[k] = model_dev[perm(k)]; dl_unpermute: the
+ * inverse.  nvec vectors of N doubles each, contiguous; source and
+ * destination must not be the same buffer (DL_EINVAL).  Asynchronous. */
+dl_status dl_permute(const dl_model* model, const double* model_dev, double* bta_dev,
+                     int32_t nvec, void* stream);
+dl_status dl_unpermute(const dl_model* model, const double* bta_dev, double* model_dev,
+                       int32_t nvec, void* stream);
+
+/* ---- device memory budget ------------------------------------------------
+ * dl_ws_estimate_bytes: device bytes that dl_ws_create_batch(models,
+ * nmodels, flags) allocates for its buffers, computed on the host without
+ * touching the device (dl_ws_bytes reports the same count after creation;
+ * the launch descriptors, a few MB, and the split-k partial tiles of
+ * DL_WS_SPLITK or of a later dl_autotune are not included).
+ * dl_ws_create_budget: dl_ws_create_batch, or DL_ENOMEM without allocating
+ * anything when that estimate exceeds hbm_budget bytes.
+ * dl_plan_waves: splits a batch that does not fit into waves that do: each
+ * instance k gets a wave index wave_of_host[k] in 0 .. *nwaves_host - 1
+ * (first fit, largest instance first), so that every wave's estimate plus
+ * DL_WAVE_RESERVE bytes stays within hbm_budget; DL_ENOMEM when one
+ * instance alone does not fit.  Host only. */
+#define DL_WAVE_RESERVE ((size_t)256 << 20)
+dl_status dl_ws_estimate_bytes(const dl_model* const* models, int32_t nmodels,
+                               int32_t flags, size_t* bytes_host);
+dl_status dl_ws_create_budget(const dl_model* const* models, int32_t nmodels,
+                              int32_t flags, size_t hbm_budget, dl_ws** out);
+dl_status dl_plan_waves(const dl_model* const* models, int32_t nmodels, int32_t flags,
+                        size_t hbm_budget, int32_t* wave_of_host, int32_t* nwaves_host);
 
 /* ---- dense FP64 block kernels (the building blocks of bta_factor) ------- */
 

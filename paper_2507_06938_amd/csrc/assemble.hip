@@ -524,6 +524,11 @@ __global__ void k_combine(const CombineJob* __restrict__ jobs) {
   if (info_out) {
     info_out[0] = info2[0];
     info_out[1] = info2[1];
+    // a refined mean whose residual missed the tolerance (the pivots were
+    // fine): reported, f is kept
+    if (info2[1] == 0 && C.tol2 && C.rnorm &&
+        !(C.rnorm[0] <= C.tol2[0] * C.rnorm[1]))
+      info_out[1] = DL_INFO_NOTCONV;
   }
 }
 

@@ -173,15 +173,21 @@ hipError_t launch_panel_updates(const PanelTask* tasks_dev, int ntask, int grid,
                                 hipStream_t s);
 
 // ---- small batched element-wise jobs ------------------------------------------
+// MJ_AXPY_UNCONV: dst += src unless norms[0] <= tol2[0] * norms[1] (a
+// residual already within the squared relative tolerance: the iterate
+// stays as it is, bit for bit);
+// MJ_COPY2D_TO_F32: FP64 src into an FP32 dst.
 enum : int { MJ_FILL = 0, MJ_COPY = 1, MJ_ZERO_I64 = 2, MJ_DIAG = 3,
              MJ_COPY2D = 4, MJ_ZERO_UPPER_TILES = 5, MJ_COPY2D_F32 = 6,
-             MJ_AXPY = 7 };
+             MJ_AXPY = 7, MJ_AXPY_UNCONV = 8, MJ_COPY2D_TO_F32 = 9 };
 struct MiscJob {
   int32_t kind, rows, cols, pad_;
   double* dst;
   const double* src;
   int64_t n, lds, ldd;
   double v;
+  const double* norms;
+  const double* tol2;
 };
 hipError_t launch_misc(const MiscJob* jobs_dev, int count, hipStream_t s);
 

@@ -486,6 +486,19 @@ __global__ __launch_bounds__(256) void k_misc(const MiscJob* __restrict__ jobs) 
     case MJ_AXPY:
       for (int64_t i = i0; i < J.n; i += stride) J.dst[i] += J.src[i];
       break;
+    case MJ_AXPY_UNCONV:
+      if (!(J.norms[0] <= J.tol2[0] * J.norms[1]))
+        for (int64_t i = i0; i < J.n; i += stride) J.dst[i] += J.src[i];
+      break;
+    case MJ_COPY2D_TO_F32: {
+      float* dst32 = (float*)J.dst;
+      const int64_t tot = (int64_t)J.rows * J.cols;
+      for (int64_t i = i0; i < tot; i += stride) {
+        const int64_t r = i % J.rows, c = i / J.rows;
+        dst32[r + c * J.ldd] = (float)J.src[r + c * J.lds];
+      }
+      break;
+    }
     case MJ_ZERO_UPPER_TILES: {
       const int64_t tot = (int64_t)J.rows * J.rows;
       for (int64_t i = i0; i < tot; i += stride) {

@@ -448,10 +448,22 @@ struct dl_ws {
   std::vector<int32_t> newton_steps;
   bool warm = false;             // DL_WS_WARM_START
   std::vector<char> has_mode;    // instance holds a converged mode in xcur
+  // refinement of the mean: residual norms of every instance ([B x 2]:
+  // |rhs - Q_c x|^2, |rhs|^2), the squared relative tolerance in use (one
+  // device double and its host copy) and a host buffer for the norms
+  double* rnorm_all = nullptr;
+  double* tol2_dev = nullptr;
+  double tol2_host = 0.0;
+  std::vector<double> rnorm_host;
+  MiscJob* d_io = nullptr;  // one descriptor for dl_ws_get_block / set_block
   Descs H;
   DevDescs Dd;
   std::vector<Launch> table;
-  Plan theta_p, asm_p[3], fac_p[3], solve_p, refine_p, selinv_p, post_p, eval_p;
+  // refinement plans: init (x <- mu), res (residual of x and its norms), corr
+  // (solve with the factor, x += correction unless converged), fin (mu <- x
+  // and the final residual), resid (the final residual of mu alone)
+  Plan theta_p, asm_p[3], fac_p[3], solve_p, selinv_p, post_p, eval_p;
+  Plan ref_init_p, ref_res_p, ref_corr_p, ref_fin_p, resid_p;
   bool assembled[2] = {false, false}, factored[2] = {false, false};
   bool solved = false;
   int max_shmem = 0;
@@ -1091,24 +1103,18 @@ static Step res_step(uint64_t key, Inst& I, const double* v, double* out) {
   return s;
 }
 
-static void seq_refine(dl_ws* W, Inst& I, int nt_max, int steps, std::vector<Step>& q) {
-  const uint64_t span = 2 * (uint64_t)nt_max + 8;
-  if (steps > 0)
-    q.push_back(misc_step(K(0, 0), DL_CAT_SOLVE, MJ_COPY, I.mu_acc, I.mu, I.m.Np));
-  for (int r = 0; r < steps; ++r) {
-    const uint64_t base = 1 + (uint64_t)r * span;
-    q.push_back(res_step(K(base, 0), I, I.mu_acc, I.x));
-    std::vector<Step> core;
-    seq_solve(W, I, nt_max, core);
-    for (auto& st : core) st.key += K(base + 1, 0);
-    q.insert(q.end(), core.begin(), core.end());
-    q.push_back(misc_step(K(base + span - 1, 0), DL_CAT_SOLVE, MJ_AXPY, I.mu_acc, I.mu,
-                          I.m.Np));
-  }
-  const uint64_t tail = 1 + (uint64_t)steps * span;
-  if (steps > 0)
-    q.push_back(misc_step(K(tail, 0), DL_CAT_SOLVE, MJ_COPY, I.mu, I.mu_acc, I.m.Np));
-  q.push_back(res_step(K(tail, 1), I, I.mu, I.x));
+// The pieces of one refinement: init copies mu to the iterate mu_acc; res
+// forms x = rhs - Q_c mu_acc and its norms; corr solves with the factor
+// (x -> mu) and adds mu to mu_acc unless the residual was already within
+// the tolerance (the iterate then stays as it is, bit for bit); fin copies
+// mu_acc back to mu and forms its residual; resid forms the residual of mu.
+static void seq_refine_corr(dl_ws* W, Inst& I, int nt_max, std::vector<Step>& q) {
+  seq_solve(W, I, nt_max, q);
+  Step ax = misc_step(K(2 * (uint64_t)nt_max + 8, 0), DL_CAT_SOLVE, MJ_AXPY_UNCONV, I.mu_acc,
+                      I.mu, I.m.Np);
+  ax.misc.norms = I.rnorm;
+  ax.misc.tol2 = W->tol2_dev;
+  q.push_back(ax);
 }
 
 // mu^T Q_p mu, (y - A mu)^T D (y - A mu) and f_obj, per instance.
@@ -1135,6 +1141,7 @@ static void seq_post(dl_ws* W, Inst& I, int k, std::vector<Step>& q) {
   c.comb.parts = (dl_fobj_parts*)(W->parts_all + 8 * (int64_t)k);
   c.comb.info_out = W->info_all + 2 * (int64_t)k;
   c.comb.rnorm = I.rnorm;
+  c.comb.tol2 = (I.mixed && !I.poisson) ? W->tol2_dev : nullptr;
   q.push_back(c);
 }
 
@@ -1178,12 +1185,21 @@ static dl_status build_plans(dl_ws* W) {
     merge(seqs, H, W->table, W->solve_p);
   }
   {
-    std::vector<std::vector<Step>> seqs;
+    std::vector<std::vector<Step>> init, res, corr, fin, resid;
     for (auto& I : W->inst) {
-      seqs.emplace_back();
-      seq_refine(W, I, nt_max, I.mixed ? DL_REFINE_STEPS : 0, seqs.back());
+      init.push_back({misc_step(K(0, 0), DL_CAT_SOLVE, MJ_COPY, I.mu_acc, I.mu, I.m.Np)});
+      res.push_back({res_step(K(0, 0), I, I.mu_acc, I.x)});
+      corr.emplace_back();
+      seq_refine_corr(W, I, nt_max, corr.back());
+      fin.push_back({misc_step(K(0, 0), DL_CAT_SOLVE, MJ_COPY, I.mu, I.mu_acc, I.m.Np),
+                     res_step(K(0, 1), I, I.mu, I.x)});
+      resid.push_back({res_step(K(0, 0), I, I.mu, I.x)});
     }
-    merge(seqs, H, W->table, W->refine_p);
+    merge(init, H, W->table, W->ref_init_p);
+    merge(res, H, W->table, W->ref_res_p);
+    merge(corr, H, W->table, W->ref_corr_p);
+    merge(fin, H, W->table, W->ref_fin_p);
+    merge(resid, H, W->table, W->resid_p);
   }
   {
     std::vector<std::vector<Step>> seqs;
@@ -1205,7 +1221,18 @@ static dl_status build_plans(dl_ws* W) {
   append(W->eval_p, W->asm_p[2]);
   append(W->eval_p, W->fac_p[2]);
   append(W->eval_p, W->solve_p);
-  append(W->eval_p, W->refine_p);
+  if (W->mixed) {
+    // a captured graph runs a fixed number of correction steps (instances
+    // that meet the tolerance earlier stay as they are)
+    append(W->eval_p, W->ref_init_p);
+    for (int r = 0; r < DL_REFINE_STEPS_GRAPH; ++r) {
+      append(W->eval_p, W->ref_res_p);
+      append(W->eval_p, W->ref_corr_p);
+    }
+    append(W->eval_p, W->ref_fin_p);
+  } else {
+    append(W->eval_p, W->resid_p);
+  }
   append(W->eval_p, W->post_p);
   // split-k partial tiles: the largest need of any launch, for either tile
   int64_t pmax = 0;
@@ -1277,6 +1304,155 @@ static void ws_free(dl_ws* W) {
   delete W;
 }
 
+// Storage layout of instance I (host fields only) for the workspace flags.
+static void inst_layout(const dl_ws* W, Inst& I, const dl_model* model, bool two_sided) {
+  I.model = model;
+  I.m = model->d;
+  I.dim = I.m.dim_theta;
+  const ModelDev& m = I.m;
+  I.qp_ring = !W->keep_qp;
+  I.ldbr = m.bp + m.ap;
+  I.mixed = W->mixed;
+  I.eb = I.mixed ? 4 : 8;
+  // two chains need at least one block each besides the root
+  I.two = two_sided && m.nt >= 4;
+  I.mid = I.two ? (m.nt + 1) / 2 : m.nt - 1;
+  I.poisson = W->poisson;
+}
+
+// The device buffers of instance I (laid out by inst_layout): A(bytes, &ptr)
+// allocates them, or only counts them when the workspace is being sized.
+template <typename Alloc>
+static void inst_buffers(const dl_ws* W, Inst& I, Alloc&& A) {
+  const ModelDev& m = I.m;
+  const int bp = m.bp, ap = m.ap;
+  const int64_t bb = (int64_t)bp * bp;
+  const int xs = I.two ? 1 : 0;  // extra spare slot of chain B
+  const size_t eb = I.eb;
+  if (I.qp_ring) {
+    A(sizeof(double) * (I.two ? 5 : 2) * bb, (void**)&I.Dp);
+    A(eb * (I.two ? 7 : 3) * bb, (void**)&I.Bp);
+  } else {
+    A(sizeof(double) * m.nt * bb, (void**)&I.Dp);
+    A(eb * (m.nt + 1 + xs) * bb, (void**)&I.Bp);
+  }
+  A(sizeof(double) * m.nt * bb, (void**)&I.Dc);
+  A(eb * (m.nt + 1 + xs) * I.ldbr * bp, (void**)&I.BRc);
+  A(sizeof(double) * m.Np, (void**)&I.mu_acc);
+  A(sizeof(double) * (m.m_total + 1), (void**)&I.av);
+  A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.rpart);
+  const size_t tip = sizeof(double) * (ap > 0 ? ap * ap : 1);
+  A(tip, (void**)&I.Pp);
+  A(tip, (void**)&I.Pc);
+  A(tip, (void**)&I.GPc);
+  A(tip, (void**)&I.GPp);
+  // per diagonal-block factorisation: the side ring and the folded
+  // inverse's accumulators (2 + nbk (nbk - 1) / 2 tiles of 64 x 64), or
+  // the recursive inverse's bp x (bp / 2 + 64) temporary (the larger)
+  const int64_t nbk = bp / 64;
+  const size_t ftemp = sizeof(double) * std::max<int64_t>(
+      4096 * (2 + nbk * (nbk - 1) / 2), (int64_t)bp * (nbk / 2 + 1) * 64);
+  for (int w = 0; w < 2; ++w) {
+    A(ftemp, (void**)&I.ttemp[w]);
+    A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
+  }
+  A(sizeof(double) * (I.dim + 1), (void**)&I.theta);
+  A(sizeof(double) * C_SIZE, (void**)&I.coef);
+  A(sizeof(double) * 2, (void**)&I.logdet2);
+  A(sizeof(int64_t) * 2, (void**)&I.info2);
+  A(sizeof(double) * 2, (void**)&I.quad2);
+  A(sizeof(double) * 2 * SUM_BLOCKS, (void**)&I.sumpart);
+  A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.qpart);
+  A(sizeof(double) * m.Np, (void**)&I.rhs);
+  A(sizeof(double) * m.Np, (void**)&I.x);
+  A(sizeof(double) * m.Np, (void**)&I.mu);
+  A(sizeof(double) * I.ldbr, (void**)&I.u);
+  A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
+  if (I.poisson) {
+    A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_d);
+    A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_z);
+    A(sizeof(double) * m.Np, (void**)&I.xcur);
+    A(sizeof(double) * m.Np, (void**)&I.xN);
+    A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.tpart);
+  }
+  if (I.two) {
+    A(tip, (void**)&I.PcB);
+    for (int w = 0; w < 2; ++w) A(ftemp, (void**)&I.ttempB[w]);
+    A(sizeof(double) * I.ldbr, (void**)&I.uB);
+    A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpartB);
+    A(sizeof(double) * (ap > 0 ? ap : 1), (void**)&I.xPB);
+  }
+  if (W->sel) {
+    // [W_t; V_t] = [B_t; R_t] G_t of every time step (formed up front)
+    A((size_t)I.eb * m.nt * I.ldbr * bp, (void**)&I.WV);
+    A(sizeof(double) * I.ldbr * bp, (void**)&I.Y);
+    A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[0]);
+    A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[1]);
+    A(sizeof(double) * m.Np, (void**)&I.selout);
+    if (I.two) {
+      A(sizeof(double) * I.ldbr * bp, (void**)&I.YB);
+      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[0]);
+      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[1]);
+    }
+  }
+}
+
+// The workspace-wide buffers of a batch of nmodels instances.
+template <typename Alloc>
+static void ws_buffers(dl_ws* W, int nmodels, int dim_total, Alloc&& A) {
+  A(sizeof(double) * (dim_total + 1), (void**)&W->theta_all);
+  A(sizeof(double) * nmodels, (void**)&W->f_all);
+  A(sizeof(double) * 8 * nmodels, (void**)&W->parts_all);
+  A(sizeof(int64_t) * 2 * nmodels, (void**)&W->info_all);
+  A(sizeof(double) * 2 * nmodels, (void**)&W->rnorm_all);
+  A(sizeof(double), (void**)&W->tol2_dev);
+  A(sizeof(MiscJob), (void**)&W->d_io);
+  if (W->poisson) {
+    A(sizeof(double) * nmodels, (void**)&W->alpha_all);
+    A(sizeof(double) * 4 * nmodels, (void**)&W->out4_all);
+  }
+}
+
+// Flags of a workspace (host fields only).
+static void ws_flags(dl_ws* W, int32_t flags) {
+  W->flags = flags;
+  W->sel = (flags & DL_WS_SELINV) != 0;
+  W->keep_qp = (flags & DL_WS_KEEP_QP) != 0;
+  W->mixed = (flags & DL_WS_MIXED) != 0;
+  W->use_graph = (flags & DL_WS_GRAPH) != 0;
+  W->splitk = (flags & DL_WS_SPLITK) != 0;
+  W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
+  W->warm = (flags & DL_WS_WARM_START) != 0;
+}
+
+// Bytes of the buffers of each instance and of the workspace-wide ones,
+// without allocating (the launch descriptors built at creation and the
+// split-k partial tiles of DL_WS_SPLITK or of a later dl_autotune are not
+// included).
+static dl_status ws_sizes(const dl_model* const* models, int32_t nmodels, int32_t flags,
+                          std::vector<size_t>* per_inst, size_t* shared) {
+  if (!models || nmodels <= 0) return DL_EINVAL;
+  dl_ws W;
+  ws_flags(&W, flags);
+  W.poisson = models[0] && models[0]->d.likelihood == DL_LIK_POISSON;
+  per_inst->assign(nmodels, 0);
+  int dim_total = 0;
+  for (int k = 0; k < nmodels; ++k) {
+    if (!models[k]) return DL_EINVAL;
+    if ((models[k]->d.likelihood == DL_LIK_POISSON) != W.poisson) return DL_EINVAL;
+    Inst I;
+    inst_layout(&W, I, models[k], (flags & DL_WS_TWOSIDED) != 0);
+    dim_total += I.dim;
+    size_t bytes = 0;
+    inst_buffers(&W, I, [&](size_t b, void** p) { bytes += b; *p = nullptr; });
+    (*per_inst)[k] = bytes;
+  }
+  size_t sh = 0;
+  ws_buffers(&W, nmodels, dim_total, [&](size_t b, void** p) { sh += b; *p = nullptr; });
+  *shared = sh;
+  return DL_OK;
+}
+
 extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
                                         int32_t nmodels, int32_t flags,
                                         dl_ws** out) {
@@ -1285,13 +1461,7 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     if (!models[k]) return DL_EINVAL;
   dl_ws* W = new (std::nothrow) dl_ws();
   if (!W) return DL_ENOMEM;
-  W->flags = flags;
-  W->sel = (flags & DL_WS_SELINV) != 0;
-  W->keep_qp = (flags & DL_WS_KEEP_QP) != 0;
-  W->mixed = (flags & DL_WS_MIXED) != 0;
-  W->use_graph = (flags & DL_WS_GRAPH) != 0;
-  W->splitk = (flags & DL_WS_SPLITK) != 0;
-  W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
+  ws_flags(W, flags);
   const bool two_sided = (flags & DL_WS_TWOSIDED) != 0;
   // one likelihood per workspace
   W->poisson = models[0]->d.likelihood == DL_LIK_POISSON;
@@ -1301,7 +1471,6 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
       return DL_EINVAL;
     }
   W->newton_steps.assign(nmodels, 0);
-  W->warm = (flags & DL_WS_WARM_START) != 0;
   W->has_mode.assign(nmodels, 0);
   W->inst.resize(nmodels);
   dl_status st = DL_OK;
@@ -1311,116 +1480,39 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
   int dim_total = 0;
   for (int k = 0; k < nmodels; ++k) {
     Inst& I = W->inst[k];
-    I.model = models[k];
-    I.m = models[k]->d;
-    I.dim = I.m.dim_theta;
+    inst_layout(W, I, models[k], two_sided);
     dim_total += I.dim;
-    const ModelDev& m = I.m;
-    const int bp = m.bp, ap = m.ap;
-    const int64_t bb = (int64_t)bp * bp;
-    W->max_shmem = std::max(W->max_shmem, 2 * bp + ap);
-    I.qp_ring = !W->keep_qp;
-    I.ldbr = bp + ap;
-    I.mixed = W->mixed;
-    I.eb = I.mixed ? 4 : 8;
-    // two chains need at least one block each besides the root
-    I.two = two_sided && m.nt >= 4;
-    I.mid = I.two ? (m.nt + 1) / 2 : m.nt - 1;
-    const int xs = I.two ? 1 : 0;  // extra spare slot of chain B
-    const size_t eb = I.eb;
-    if (I.qp_ring) {
-      A(sizeof(double) * (I.two ? 5 : 2) * bb, (void**)&I.Dp);
-      A(eb * (I.two ? 7 : 3) * bb, (void**)&I.Bp);
-    } else {
-      A(sizeof(double) * m.nt * bb, (void**)&I.Dp);
-      A(eb * (m.nt + 1 + xs) * bb, (void**)&I.Bp);
-    }
-    A(sizeof(double) * m.nt * bb, (void**)&I.Dc);
-    A(eb * (m.nt + 1 + xs) * I.ldbr * bp, (void**)&I.BRc);
-    A(sizeof(double) * m.Np, (void**)&I.mu_acc);
-    A(sizeof(double) * (m.m_total + 1), (void**)&I.av);
-    A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.rpart);
-    A(sizeof(double) * 2, (void**)&I.rnorm);
-    const size_t tip = sizeof(double) * (ap > 0 ? ap * ap : 1);
-    A(tip, (void**)&I.Pp);
-    A(tip, (void**)&I.Pc);
-    A(tip, (void**)&I.GPc);
-    A(tip, (void**)&I.GPp);
-    // per diagonal-block factorisation: the side ring and the folded
-    // inverse's accumulators (2 + nbk (nbk - 1) / 2 tiles of 64 x 64), or
-    // the recursive inverse's bp x (bp / 2 + 64) temporary (the larger)
-    const int64_t nbk = bp / 64;
-    const size_t ftemp = sizeof(double) * std::max<int64_t>(
-        4096 * (2 + nbk * (nbk - 1) / 2), (int64_t)bp * (nbk / 2 + 1) * 64);
-    for (int w = 0; w < 2; ++w) {
-      A(ftemp, (void**)&I.ttemp[w]);
-      A(sizeof(double) * m.Np, (void**)&I.logdiag[w]);
-    }
-    A(sizeof(double) * (I.dim + 1), (void**)&I.theta);
-    A(sizeof(double) * C_SIZE, (void**)&I.coef);
-    A(sizeof(double) * 2, (void**)&I.logdet2);
-    A(sizeof(int64_t) * 2, (void**)&I.info2);
-    A(sizeof(double) * 2, (void**)&I.quad2);
-    A(sizeof(double) * 2 * SUM_BLOCKS, (void**)&I.sumpart);
-    A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.qpart);
-    A(sizeof(double) * m.Np, (void**)&I.rhs);
-    A(sizeof(double) * m.Np, (void**)&I.x);
-    A(sizeof(double) * m.Np, (void**)&I.mu);
-    A(sizeof(double) * I.ldbr, (void**)&I.u);
-    A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpart);
-    I.poisson = W->poisson;
-    if (I.poisson) {
-      A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_d);
-      A(sizeof(double) * (m.m_total + 1), (void**)&I.obs_z);
-      A(sizeof(double) * m.Np, (void**)&I.xcur);
-      A(sizeof(double) * m.Np, (void**)&I.xN);
-      A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.tpart);
-      if (st == DL_OK &&
-          (hipMemset(I.obs_d, 0, sizeof(double) * (m.m_total + 1)) != hipSuccess ||
-           hipMemset(I.obs_z, 0, sizeof(double) * (m.m_total + 1)) != hipSuccess))
-        st = DL_EHIP;
-    }
-    if (I.two) {
-      A(tip, (void**)&I.PcB);
-      for (int w = 0; w < 2; ++w) A(ftemp, (void**)&I.ttempB[w]);
-      A(sizeof(double) * I.ldbr, (void**)&I.uB);
-      A(sizeof(double) * GEMV_KS * I.ldbr, (void**)&I.gpartB);
-      A(sizeof(double) * (ap > 0 ? ap : 1), (void**)&I.xPB);
-    }
-    if (W->sel) {
-      // [W_t; V_t] = [B_t; R_t] G_t of every time step (formed up front)
-      A((size_t)I.eb * m.nt * I.ldbr * bp, (void**)&I.WV);
-      A(sizeof(double) * I.ldbr * bp, (void**)&I.Y);
-      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[0]);
-      A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XC[1]);
-      A(sizeof(double) * m.Np, (void**)&I.selout);
-      if (I.two) {
-        A(sizeof(double) * I.ldbr * bp, (void**)&I.YB);
-        A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[0]);
-        A(sizeof(double) * I.ldbr * I.ldbr, (void**)&I.XCB[1]);
-      }
-    }
+    W->max_shmem = std::max(W->max_shmem, 2 * I.m.bp + I.m.ap);
+    inst_buffers(W, I, A);
+    if (I.poisson && st == DL_OK &&
+        (hipMemset(I.obs_d, 0, sizeof(double) * (I.m.m_total + 1)) != hipSuccess ||
+         hipMemset(I.obs_z, 0, sizeof(double) * (I.m.m_total + 1)) != hipSuccess))
+      st = DL_EHIP;
   }
   W->dim_total = dim_total;
-  A(sizeof(double) * (dim_total + 1), (void**)&W->theta_all);
-  A(sizeof(double) * nmodels, (void**)&W->f_all);
-  A(sizeof(double) * 8 * nmodels, (void**)&W->parts_all);
-  A(sizeof(int64_t) * 2 * nmodels, (void**)&W->info_all);
-  if (W->poisson) {
-    A(sizeof(double) * nmodels, (void**)&W->alpha_all);
-    A(sizeof(double) * 4 * nmodels, (void**)&W->out4_all);
-  }
+  ws_buffers(W, nmodels, dim_total, A);
   if (st != DL_OK) {
     ws_free(W);
     return st;
   }
-  // instance theta buffers are views of the packed array
+  // instance theta buffers are views of the packed array, residual norms
+  // views of theirs
   {
     int off = 0;
-    for (auto& I : W->inst) {
+    for (size_t k = 0; k < W->inst.size(); ++k) {
+      Inst& I = W->inst[k];
       I.theta = W->theta_all + off;
       off += I.dim;
+      I.rnorm = W->rnorm_all + 2 * k;
     }
+  }
+  W->rnorm_host.assign(2 * (size_t)nmodels, 0.0);
+  W->tol2_host = DL_REFINE_TOL * DL_REFINE_TOL;
+  if (hipMemcpy(W->tol2_dev, &W->tol2_host, sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(W->rnorm_all, 0, sizeof(double) * 2 * nmodels) != hipSuccess) {
+    ws_free(W);
+    return DL_EHIP;
   }
   if (W->poisson)
     for (int k = 0; k < nmodels; ++k) {
@@ -1437,6 +1529,58 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
     return st;
   }
   *out = W;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_estimate_bytes(const dl_model* const* models, int32_t nmodels,
+                                          int32_t flags, size_t* bytes_host) {
+  if (!bytes_host) return DL_EINVAL;
+  std::vector<size_t> per;
+  size_t shared = 0;
+  const dl_status st = ws_sizes(models, nmodels, flags, &per, &shared);
+  if (st != DL_OK) return st;
+  size_t tot = shared;
+  for (size_t b : per) tot += b;
+  *bytes_host = tot;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_create_budget(const dl_model* const* models, int32_t nmodels,
+                                         int32_t flags, size_t hbm_budget, dl_ws** out) {
+  if (!out) return DL_EINVAL;
+  size_t need = 0;
+  const dl_status st = dl_ws_estimate_bytes(models, nmodels, flags, &need);
+  if (st != DL_OK) return st;
+  if (need > hbm_budget) return DL_ENOMEM;
+  return dl_ws_create_batch(models, nmodels, flags, out);
+}
+
+extern "C" dl_status dl_plan_waves(const dl_model* const* models, int32_t nmodels,
+                                   int32_t flags, size_t hbm_budget, int32_t* wave_of_host,
+                                   int32_t* nwaves_host) {
+  if (!wave_of_host || !nwaves_host) return DL_EINVAL;
+  std::vector<size_t> per;
+  size_t shared = 0;
+  dl_status st = ws_sizes(models, nmodels, flags, &per, &shared);
+  if (st != DL_OK) return st;
+  // first fit, largest instance first; each wave also holds the
+  // workspace-wide buffers of the whole batch (an upper bound) and
+  // DL_WAVE_RESERVE bytes for its launch descriptors
+  const size_t fixed = shared + (size_t)DL_WAVE_RESERVE;
+  std::vector<int> order(nmodels);
+  for (int k = 0; k < nmodels; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return per[a] > per[b]; });
+  std::vector<size_t> used;
+  for (int k : order) {
+    if (per[k] + fixed > hbm_budget) return DL_ENOMEM;
+    int w = 0;
+    while (w < (int)used.size() && used[w] + per[k] > hbm_budget) ++w;
+    if (w == (int)used.size()) used.push_back(fixed);
+    used[w] += per[k];
+    wave_of_host[k] = w;
+  }
+  *nwaves_host = (int32_t)used.size();
   return DL_OK;
 }
 
@@ -1458,6 +1602,67 @@ static dl_status copy_theta_in(dl_ws* W, const double* theta_dev, int n_inst,
   for (int k = 0; k < n_inst; ++k) dims += W->inst[k].dim;
   DL_HIP_CHECK(hipMemcpyAsync(W->theta_all, theta_dev, sizeof(double) * dims,
                               hipMemcpyDeviceToDevice, s));
+  return DL_OK;
+}
+
+// ---- iterative refinement of the mean -----------------------------------------------------
+
+__global__ void k_set_double(double* p, double v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+// Make tol the relative tolerance the refinement kernels read (stream
+// order; the value travels as a kernel argument).
+static dl_status set_refine_tol(dl_ws* W, double tol, hipStream_t s) {
+  const double t2 = tol * tol;
+  if (t2 == W->tol2_host) return DL_OK;
+  W->tol2_host = t2;
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, W->tol2_dev, t2);
+  DL_HIP_CHECK(hipGetLastError());
+  return DL_OK;
+}
+
+// Read every instance's residual norms (synchronises s); true when all are
+// within the tolerance.
+static dl_status refine_all_converged(dl_ws* W, hipStream_t s, bool* conv) {
+  const size_t B = W->inst.size();
+  DL_HIP_CHECK(hipMemcpyAsync(W->rnorm_host.data(), W->rnorm_all, sizeof(double) * 2 * B,
+                              hipMemcpyDeviceToHost, s));
+  DL_HIP_CHECK(hipStreamSynchronize(s));
+  bool all = true;
+  for (size_t k = 0; k < B; ++k)
+    all = all && W->rnorm_host[2 * k] <= W->tol2_host * W->rnorm_host[2 * k + 1];
+  *conv = all;
+  return DL_OK;
+}
+
+// Refine mu (the solve of the workspace's right-hand sides) with at most
+// max_steps corrections, stopping once every instance meets tol (the host
+// reads the norms after each residual); then the final residual of mu.
+// *conv (may be null) receives whether every final residual meets tol
+// (read only when max_steps > 0).
+static dl_status refine_eager(dl_ws* W, hipStream_t s, int max_steps, double tol, bool* conv) {
+  dl_status st = set_refine_tol(W, tol, s);
+  if (st != DL_OK) return st;
+  if (max_steps <= 0) {
+    DL_HIP_CHECK(run(W, W->resid_p, s));
+    if (conv) *conv = true;
+    return DL_OK;
+  }
+  DL_HIP_CHECK(run(W, W->ref_init_p, s));
+  for (int r = 0; r < max_steps; ++r) {
+    DL_HIP_CHECK(run(W, W->ref_res_p, s));
+    bool all = false;
+    if ((st = refine_all_converged(W, s, &all)) != DL_OK) return st;
+    if (all) break;
+    DL_HIP_CHECK(run(W, W->ref_corr_p, s));
+  }
+  DL_HIP_CHECK(run(W, W->ref_fin_p, s));
+  if (conv) {
+    bool all = false;
+    if ((st = refine_all_converged(W, s, &all)) != DL_OK) return st;
+    *conv = all;
+  }
   return DL_OK;
 }
 
@@ -1500,29 +1705,50 @@ extern "C" dl_status bta_factor(dl_ws* W, dl_which which, double* logdet_dev,
   return DL_OK;
 }
 
-extern "C" dl_status bta_solve(dl_ws* W, double* rhs_inout_dev, void* stream) {
+extern "C" dl_status bta_solve(dl_ws* W, double* rhs_inout_dev, int32_t nrhs,
+                               int32_t refine_max, double refine_tol, void* stream) {
   if (!W) return DL_EINVAL;
+  if (rhs_inout_dev ? nrhs < 1 : (nrhs != 0 && nrhs != 1)) return DL_EINVAL;
+  if (refine_max > 100 || (refine_max >= 0 && !(refine_tol >= 0.0))) return DL_EINVAL;
   if (!W->factored[1]) return DL_ESTATE;
   hipStream_t s = (hipStream_t)stream;
-  if (rhs_inout_dev) {
-    // the plan copies rhs -> x first, so stage the caller's vectors in rhs
-    int64_t off = 0;
-    for (auto& I : W->inst) {
-      DL_HIP_CHECK(launch_unpack(I.m, rhs_inout_dev + off, I.rhs, s));
-      off += I.m.N;
+  // refine_max < 0: the workspace's default (mixed precision: to
+  // DL_REFINE_TOL in at most DL_REFINE_MAX corrections; FP64: none)
+  const int steps = refine_max < 0 ? (W->mixed ? DL_REFINE_MAX : 0) : refine_max;
+  const double tol = refine_max < 0 ? DL_REFINE_TOL : refine_tol;
+  bool all = true;
+  dl_status st = DL_OK;
+  if (!rhs_inout_dev) {
+    DL_HIP_CHECK(run(W, W->solve_p, s));
+    bool conv = true;
+    if ((st = refine_eager(W, s, steps, tol, &conv)) != DL_OK) return st;
+    all = conv;
+  } else {
+    int64_t ntot = 0;
+    for (auto& I : W->inst) ntot += I.m.N;
+    for (int c = 0; c < nrhs; ++c) {
+      double* col = rhs_inout_dev + (int64_t)c * ntot;
+      // the plan copies rhs -> x first, so stage the caller's vectors in rhs
+      int64_t off = 0;
+      for (auto& I : W->inst) {
+        DL_HIP_CHECK(launch_unpack(I.m, col + off, I.rhs, s));
+        off += I.m.N;
+      }
+      DL_HIP_CHECK(run(W, W->solve_p, s));
+      bool conv = true;
+      if (steps > 0 && (st = refine_eager(W, s, steps, tol, &conv)) != DL_OK) return st;
+      all = all && conv;
+      off = 0;
+      for (auto& I : W->inst) {
+        DL_HIP_CHECK(launch_pack(I.m, I.mu, col + off, s));
+        off += I.m.N;
+      }
     }
   }
-  DL_HIP_CHECK(run(W, W->solve_p, s));
-  if (!rhs_inout_dev) DL_HIP_CHECK(run(W, W->refine_p, s));
-  if (rhs_inout_dev) {
-    int64_t off = 0;
-    for (auto& I : W->inst) {
-      DL_HIP_CHECK(launch_pack(I.m, I.mu, rhs_inout_dev + off, s));
-      off += I.m.N;
-    }
-  }
+  // evaluations after this call use the default tolerance again
+  if ((st = set_refine_tol(W, DL_REFINE_TOL, s)) != DL_OK) return st;
   W->solved = true;
-  return DL_OK;
+  return all ? DL_OK : DL_ENOTCONV;
 }
 
 extern "C" dl_status bta_selinv(dl_ws* W, double* diag_out_dev, void* stream) {
@@ -1606,7 +1832,9 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
     }
     DL_HIP_CHECK(run(W, W->solve_p, s));
     // mixed precision: refine x_N in FP64 against the sparse Q_c(x)
-    if (W->mixed) DL_HIP_CHECK(run(W, W->refine_p, s));
+    if (W->mixed) {
+      if ((st = refine_eager(W, s, DL_REFINE_MAX, DL_REFINE_TOL, nullptr)) != DL_OK) return st;
+    }
     for (auto& I : W->inst)
       DL_HIP_CHECK(hipMemcpyAsync(I.xN, I.mu, sizeof(double) * I.m.Np,
                                   hipMemcpyDeviceToDevice, s));
@@ -1656,7 +1884,8 @@ static dl_status laplace_pass(dl_ws* W, int nk, hipStream_t s) {
   for (auto& I : W->inst)
     DL_HIP_CHECK(hipMemcpyAsync(I.mu, I.xcur, sizeof(double) * I.m.Np,
                                 hipMemcpyDeviceToDevice, s));
-  DL_HIP_CHECK(run(W, W->refine_p, s));
+  if ((st = refine_eager(W, s, W->mixed ? DL_REFINE_MAX : 0, DL_REFINE_TOL, nullptr)) != DL_OK)
+    return st;
   static const double kBad = 1.0;
   for (int k = 0; k < B; ++k) {
     if (state[k] == -1)
@@ -1676,8 +1905,16 @@ extern "C" dl_status dl_ws_newton_steps(const dl_ws* W, int32_t* steps_host) {
 }
 
 static dl_status run_eval(dl_ws* W, hipStream_t s) {
+  dl_status st = set_refine_tol(W, DL_REFINE_TOL, s);
+  if (st != DL_OK) return st;
   if (!W->use_graph) {
-    DL_HIP_CHECK(run(W, W->eval_p, s));
+    DL_HIP_CHECK(run(W, W->asm_p[2], s));
+    DL_HIP_CHECK(run(W, W->fac_p[2], s));
+    DL_HIP_CHECK(run(W, W->solve_p, s));
+    if ((st = refine_eager(W, s, W->mixed ? DL_REFINE_MAX : 0, DL_REFINE_TOL, nullptr)) !=
+        DL_OK)
+      return st;
+    DL_HIP_CHECK(run(W, W->post_p, s));
     return DL_OK;
   }
   if (!W->graph_exec) {
@@ -1763,20 +2000,26 @@ extern "C" dl_status fobj_selinv_eval(dl_ws* W, const double* theta_dev, int32_t
     if ((st = laplace_pass(W, ntheta, s)) != DL_OK) return st;
     DL_HIP_CHECK(hipEventRecord(W->ev_join, s));
   } else {
+    if ((st = set_refine_tol(W, DL_REFINE_TOL, s)) != DL_OK) return st;
     DL_HIP_CHECK(run(W, W->asm_p[2], s));
     DL_HIP_CHECK(run(W, W->fac_p[2], s));
     DL_HIP_CHECK(hipEventRecord(W->ev_fork, s));
     DL_HIP_CHECK(hipStreamWaitEvent(W->aux_stream, W->ev_fork, 0));
-    DL_HIP_CHECK(run(W, W->solve_p, W->aux_stream));
-    DL_HIP_CHECK(run(W, W->refine_p, W->aux_stream));
-    DL_HIP_CHECK(run(W, W->post_p, W->aux_stream));
-    DL_HIP_CHECK(hipEventRecord(W->ev_join, W->aux_stream));
   }
+  // the selected inversion is enqueued before the solve side, whose
+  // refinement may wait on the host for its residual norms
   DL_HIP_CHECK(run(W, W->selinv_p, s));
   int64_t off = 0;
   for (auto& I : W->inst) {
     DL_HIP_CHECK(launch_pack(I.m, I.selout, diag_out_dev + off, s));
     off += I.m.N;
+  }
+  if (!W->poisson) {
+    DL_HIP_CHECK(run(W, W->solve_p, W->aux_stream));
+    st = refine_eager(W, W->aux_stream, W->mixed ? DL_REFINE_MAX : 0, DL_REFINE_TOL, nullptr);
+    if (st != DL_OK) return st;
+    DL_HIP_CHECK(run(W, W->post_p, W->aux_stream));
+    DL_HIP_CHECK(hipEventRecord(W->ev_join, W->aux_stream));
   }
   DL_HIP_CHECK(hipStreamWaitEvent(s, W->ev_join, 0));
   if (fobj_dev)
@@ -1794,56 +2037,98 @@ extern "C" dl_status fobj_selinv_eval(dl_ws* W, const double* theta_dev, int32_t
   return DL_OK;
 }
 
-extern "C" dl_status dl_ws_get_block(dl_ws* W, dl_which which, int32_t kind,
-                                     int32_t t, double* out_dev, void* stream) {
-  if (!W || !out_dev || (which != DL_QP && which != DL_QC)) return DL_EINVAL;
-  if (W->inst.size() != 1) return DL_EINVAL;
+// Descriptor of one block copy between the workspace and a caller buffer
+// (column-major, unpadded): to_ws = false reads the block into `user`,
+// true writes `user` into the block.  kind 0 = D_t, 1 = B_t (rows t+1,
+// cols t), 2 = R_t, 3 = tip.
+static dl_status block_job(dl_ws* W, dl_which which, int32_t kind, int32_t t, bool to_ws,
+                           double* user, MiscJob* J) {
   Inst& I = W->inst[0];
   const ModelDev& m = I.m;
-  hipStream_t s = (hipStream_t)stream;
   const int bp = m.bp;
   const bool p = which == DL_QP;
-  if (p && I.qp_ring && kind != 3 && kind != 4) return DL_ESTATE;
-  std::vector<MiscJob> jobs(1);
-  MiscJob& J = jobs[0];
-  J.kind = MJ_COPY2D;
-  J.dst = out_dev;
-  if (kind == 4) {
-    DL_HIP_CHECK(launch_pack(m, I.rhs, out_dev, s));
-    return DL_OK;
-  }
+  if (p && I.qp_ring) return DL_ESTATE;
+  double* ws = nullptr;
+  int64_t ldw = 0;
+  int rows = 0, cols = 0;
+  bool f32 = false;
   if (kind == 3) {
     if (m.a == 0) return DL_EINVAL;
-    J.src = p ? I.Pp : I.Pc; J.lds = m.ap; J.ldd = m.a; J.rows = m.a; J.cols = m.a;
+    ws = p ? I.Pp : I.Pc; ldw = m.ap; rows = m.a; cols = m.a;
   } else {
     if (t < 0 || t >= m.nt) return DL_EINVAL;
     const bool fact = W->factored[p ? 0 : 1];
     const int sl = (!p && fact) ? I.slot_final[t] : t;
     const int64_t ldbr = p ? bp : I.ldbr;
-    const double* BRt = eoff(p ? I.Bp : I.BRc, (int64_t)sl * ldbr * bp, I.eb);
+    double* BRt = eoff(p ? I.Bp : I.BRc, (int64_t)sl * ldbr * bp, I.eb);
     if (kind == 0) {
-      J.src = (p ? I.Dp : I.Dc) + (int64_t)t * bp * bp; J.lds = bp;
-      J.ldd = m.b; J.rows = m.b; J.cols = m.b;
+      ws = (p ? I.Dp : I.Dc) + (int64_t)t * bp * bp; ldw = bp; rows = m.b; cols = m.b;
     } else if (kind == 1) {
       if (t + 1 >= m.nt) return DL_EINVAL;
-      J.src = BRt; J.lds = ldbr; J.ldd = m.b; J.rows = m.b; J.cols = m.b;
-      if (I.mixed) J.kind = MJ_COPY2D_F32;
+      ws = BRt; ldw = ldbr; rows = m.b; cols = m.b; f32 = I.mixed;
     } else if (kind == 2) {
       if (p || m.a == 0) return DL_EINVAL;
-      J.src = eoff((void*)BRt, bp, I.eb); J.lds = ldbr; J.ldd = m.a; J.rows = m.a; J.cols = m.b;
-      if (I.mixed) J.kind = MJ_COPY2D_F32;
+      ws = eoff((void*)BRt, bp, I.eb); ldw = ldbr; rows = m.a; cols = m.b; f32 = I.mixed;
     } else {
       return DL_EINVAL;
     }
   }
-  // one-off descriptor copy (inspection path, synchronous)
-  void* d = nullptr;
-  DL_HIP_CHECK(hipMalloc(&d, sizeof(MiscJob)));
-  hipError_t e = hipMemcpyAsync(d, jobs.data(), sizeof(MiscJob), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_misc((const MiscJob*)d, 1, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d);
-  return e == hipSuccess ? DL_OK : DL_EHIP;
+  *J = MiscJob{};
+  J->rows = rows;
+  J->cols = cols;
+  if (to_ws) {
+    J->kind = f32 ? MJ_COPY2D_TO_F32 : MJ_COPY2D;
+    J->dst = ws; J->ldd = ldw; J->src = user; J->lds = rows;
+  } else {
+    J->kind = f32 ? MJ_COPY2D_F32 : MJ_COPY2D;
+    J->dst = user; J->ldd = rows; J->src = ws; J->lds = ldw;
+  }
+  return DL_OK;
+}
+
+// One block copy through the workspace's descriptor slot (synchronous).
+static dl_status block_copy(dl_ws* W, const MiscJob& J, hipStream_t s) {
+  DL_HIP_CHECK(hipMemcpyAsync(W->d_io, &J, sizeof(MiscJob), hipMemcpyHostToDevice, s));
+  DL_HIP_CHECK(launch_misc(W->d_io, 1, s));
+  DL_HIP_CHECK(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+extern "C" dl_status dl_ws_get_block(dl_ws* W, dl_which which, int32_t kind,
+                                     int32_t t, double* out_dev, void* stream) {
+  if (!W || !out_dev || (which != DL_QP && which != DL_QC)) return DL_EINVAL;
+  if (W->inst.size() != 1) return DL_EINVAL;
+  Inst& I = W->inst[0];
+  hipStream_t s = (hipStream_t)stream;
+  if (kind == 4) {
+    if (which == DL_QP) return DL_EINVAL;
+    DL_HIP_CHECK(launch_pack(I.m, I.rhs, out_dev, s));
+    return DL_OK;
+  }
+  MiscJob J;
+  const dl_status st = block_job(W, which, kind, t, false, out_dev, &J);
+  if (st != DL_OK) return st;
+  return block_copy(W, J, s);
+}
+
+extern "C" dl_status dl_ws_set_block(dl_ws* W, dl_which which, int32_t kind, int32_t t,
+                                     const double* in_dev, void* stream) {
+  if (!W || !in_dev || (which != DL_QP && which != DL_QC)) return DL_EINVAL;
+  if (W->inst.size() != 1) return DL_EINVAL;
+  const int w = which == DL_QP ? 0 : 1;
+  if (!W->assembled[w]) return DL_ESTATE;
+  Inst& I = W->inst[0];
+  hipStream_t s = (hipStream_t)stream;
+  if (kind == 4) {
+    if (which == DL_QP) return DL_EINVAL;
+    DL_HIP_CHECK(launch_unpack(I.m, in_dev, I.rhs, s));
+    DL_HIP_CHECK(hipStreamSynchronize(s));
+    return DL_OK;
+  }
+  MiscJob J;
+  const dl_status st = block_job(W, which, kind, t, true, const_cast<double*>(in_dev), &J);
+  if (st != DL_OK) return st;
+  return block_copy(W, J, s);
 }
 
 // ---- profiling ----------------------------------------------------------------------------

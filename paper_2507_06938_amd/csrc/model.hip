@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -232,3 +233,57 @@ extern "C" dl_status dl_model_dims(const dl_model* M, int64_t* n, int64_t* b,
   return DL_OK;
 }
 
+
+// ---- model order <-> BTA order ------------------------------------------------------------
+//
+// The time-major permutation (Section IV-B, permutation): the latent
+// variable (response j, time t, node s) sits at j*nt*ns + t*ns + s in the
+// model (response-major) order of Eq. 11 and at t*b + j*ns + s in the BTA
+// order, b = nv*ns; the fixed effects (j, r) stay last at the same offset
+// in both.  The map is computed from these formulas, nothing is stored.
+namespace {
+__device__ __forceinline__ int64_t model_index(int64_t k, int64_t nt, int64_t ns, int64_t b) {
+  if (k >= nt * b) return k;
+  const int64_t t = k / b, rem = k - t * b;
+  const int64_t j = rem / ns, sp = rem - j * ns;
+  return j * nt * ns + t * ns + sp;
+}
+
+__global__ __launch_bounds__(256) void k_permute(const double* __restrict__ src,
+                                                 double* __restrict__ dst, int64_t N,
+                                                 int64_t nt, int64_t ns, int64_t b,
+                                                 int32_t nvec, int32_t to_bta) {
+  const int64_t tot = N * (int64_t)nvec;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t v = i / N, k = i - v * N;
+    const int64_t mk = model_index(k, nt, ns, b);
+    if (to_bta)
+      dst[v * N + k] = src[v * N + mk];
+    else
+      dst[v * N + mk] = src[v * N + k];
+  }
+}
+
+dl_status permute(const dl_model* M, const double* src, double* dst, int32_t nvec,
+                  int to_bta, void* stream) {
+  if (!M || !src || !dst || nvec < 0 || src == dst) return DL_EINVAL;
+  if (nvec == 0) return DL_OK;
+  const dl::ModelDev& m = M->d;
+  const int64_t tot = m.N * (int64_t)nvec;
+  const int64_t blocks = std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     src, dst, m.N, (int64_t)m.nt, (int64_t)m.ns, (int64_t)m.b, nvec, to_bta);
+  return hipGetLastError() == hipSuccess ? DL_OK : DL_EHIP;
+}
+}  // namespace
+
+extern "C" dl_status dl_permute(const dl_model* M, const double* model_dev, double* bta_dev,
+                                int32_t nvec, void* stream) {
+  return permute(M, model_dev, bta_dev, nvec, 1, stream);
+}
+
+extern "C" dl_status dl_unpermute(const dl_model* M, const double* bta_dev, double* model_dev,
+                                  int32_t nvec, void* stream) {
+  return permute(M, bta_dev, model_dev, nvec, 0, stream);
+}

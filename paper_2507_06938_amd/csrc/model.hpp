@@ -112,6 +112,9 @@ struct CombineJob {
   dl_fobj_parts* parts;
   int64_t* info_out;
   const double* rnorm;  // [|rhs - Q_c mu|^2, |rhs|^2] (may be null)
+  const double* tol2;   // squared tolerance of the refined mean: a larger
+                        // relative residual sets info_out[1] to
+                        // DL_INFO_NOTCONV (null: no check)
 };
 
 constexpr int QF_BLOCKS = 256;
@@ -143,7 +146,7 @@ struct ResJob {
 hipError_t launch_residual(const ResJob* jobs, int count, hipStream_t s);
 hipError_t launch_combine(const CombineJob* jobs, int count, hipStream_t s);
 
-// Inner Newton iteration of a Poisson likelihood (Section II-B): from the
+// Inner Newton iteration of a Poisson likelihood (Section II-A, conditional Gaussian distribution): from the
 // iterate x (padded BTA order) every observation row gets eta = (A x)_row,
 // d = exp(eta) and z = y - d + d eta (the gradient plus D eta).
 struct LapJob {

@@ -23,6 +23,13 @@ DL_WS_SPLITK = 16
 DL_WS_TWOSIDED = 32
 DL_WS_FOLD_INV = 64
 DL_WS_WARM_START = 128
+# refinement of the mean (see include/dalia.h)
+DL_REFINE_TOL = 1e-12
+DL_REFINE_MAX = 10
+DL_REFINE_STEPS_GRAPH = 3
+DL_INFO_NOTCONV = -1
+DL_ENOTCONV = 6
+DL_WAVE_RESERVE = 256 << 20
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
@@ -82,7 +89,15 @@ def lib():
             "dl_ws_bytes": (C.c_size_t, [vp]),
             "bta_assemble": (i32, [vp, vp, i32, vp]),
             "bta_factor": (i32, [vp, i32, vp, vp, vp]),
-            "bta_solve": (i32, [vp, vp, vp]),
+            "bta_solve": (i32, [vp, vp, i32, i32, dbl, vp]),
+            "dl_ws_set_block": (i32, [vp, i32, i32, i32, vp, vp]),
+            "dl_permute": (i32, [vp, vp, vp, i32, vp]),
+            "dl_unpermute": (i32, [vp, vp, vp, i32, vp]),
+            "dl_ws_estimate_bytes": (i32, [C.POINTER(vp), i32, i32, C.POINTER(C.c_size_t)]),
+            "dl_ws_create_budget": (i32, [C.POINTER(vp), i32, i32, C.c_size_t,
+                                          C.POINTER(vp)]),
+            "dl_plan_waves": (i32, [C.POINTER(vp), i32, i32, C.c_size_t, C.POINTER(i32),
+                                    C.POINTER(i32)]),
             "bta_selinv": (i32, [vp, vp, vp]),
             "fobj_eval": (i32, [vp, vp, i32, vp, vp, vp, vp]),
             "dl_ws_mean": (i32, [vp, vp, vp]),
@@ -183,6 +198,23 @@ class Model:
         self.n, self.b, self.a, self.N, self.bp = [v.value for v in vals]
         self.dim_theta = theta_dim(nv, likelihood)
 
+    def permute(self, x: torch.Tensor) -> torch.Tensor:
+        """Model order -> BTA order of N-vectors (x: (N,) or (nvec, N))."""
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        nvec = 1 if x.dim() == 1 else x.shape[0]
+        _check("dl_permute", lib().dl_permute(self.h, _ptr(x), _ptr(out), nvec, _stream()))
+        return out
+
+    def unpermute(self, x: torch.Tensor) -> torch.Tensor:
+        """BTA order -> model order of N-vectors (x: (N,) or (nvec, N))."""
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        nvec = 1 if x.dim() == 1 else x.shape[0]
+        _check("dl_unpermute", lib().dl_unpermute(self.h, _ptr(x), _ptr(out), nvec,
+                                                  _stream()))
+        return out
+
     @classmethod
     def from_workload(cls, wl) -> "Model":
         resp = [(r.t, r.nodes, r.w, r.X, r.y) for r in wl.responses]
@@ -197,29 +229,74 @@ class Model:
             self.h = None
 
 
+def ws_flags(selinv: bool = False, keep_qp: bool = False, graph: bool = False,
+             mixed: bool = False, splitk: bool = False, two_sided: bool = False,
+             fold_inverse: bool = False, warm_start: bool = False) -> int:
+    """The DL_WS_* flag word of a workspace."""
+    return ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
+            | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
+            | (DL_WS_SPLITK if splitk else 0)
+            | (DL_WS_TWOSIDED if two_sided else 0)
+            | (DL_WS_FOLD_INV if fold_inverse else 0)
+            | (DL_WS_WARM_START if warm_start else 0))
+
+
+def _model_array(models):
+    if isinstance(models, Model):
+        models = [models]
+    return (C.c_void_p * len(models))(*[m.h for m in models]), len(models)
+
+
+def estimate_bytes(models, **flags) -> int:
+    """Device bytes a workspace of `models` with these flags allocates
+    (computed on the host; see dl_ws_estimate_bytes)."""
+    arr, n = _model_array(models)
+    out = C.c_size_t()
+    _check("dl_ws_estimate_bytes", lib().dl_ws_estimate_bytes(arr, n, ws_flags(**flags),
+                                                              C.byref(out)))
+    return int(out.value)
+
+
+def plan_waves(models, hbm_budget: int, **flags) -> list:
+    """Split a batch of models into waves whose workspaces fit hbm_budget
+    bytes (dl_plan_waves); returns a list of lists of instance indices."""
+    arr, n = _model_array(models)
+    wave_of = (C.c_int32 * n)()
+    nw = C.c_int32()
+    _check("dl_plan_waves", lib().dl_plan_waves(arr, n, ws_flags(**flags), int(hbm_budget),
+                                                wave_of, C.byref(nw)))
+    waves = [[] for _ in range(nw.value)]
+    for k in range(n):
+        waves[wave_of[k]].append(k)
+    return waves
+
+
 class Workspace:
     """Dense BTA workspace of Q_p and Q_c for one model, or for a batch of
     instances (a list of models, repeated entries allowed) evaluated
-    together.  Per-instance vectors are packed in instance order."""
+    together.  Per-instance vectors are packed in instance order.  With
+    hbm_budget (bytes) the workspace is created only if its estimated size
+    fits (DaliaError with code DL_ENOMEM otherwise, nothing allocated)."""
 
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
                  graph: bool = False, mixed: bool = False, splitk: bool = False,
                  two_sided: bool = False, fold_inverse: bool = False,
-                 warm_start: bool = False):
+                 warm_start: bool = False, hbm_budget: Optional[int] = None):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
         self.model = self.models[0]
-        flags = ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
-                 | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
-                 | (DL_WS_SPLITK if splitk else 0)
-                 | (DL_WS_TWOSIDED if two_sided else 0)
-                 | (DL_WS_FOLD_INV if fold_inverse else 0)
-                 | (DL_WS_WARM_START if warm_start else 0))
+        flags = ws_flags(selinv, keep_qp, graph, mixed, splitk, two_sided, fold_inverse,
+                         warm_start)
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
-        _check("dl_ws_create_batch",
-               lib().dl_ws_create_batch(arr, len(self.models), flags, C.byref(h)))
+        if hbm_budget is None:
+            _check("dl_ws_create_batch",
+                   lib().dl_ws_create_batch(arr, len(self.models), flags, C.byref(h)))
+        else:
+            _check("dl_ws_create_budget",
+                   lib().dl_ws_create_budget(arr, len(self.models), flags, int(hbm_budget),
+                                             C.byref(h)))
         self.h = h
         self.B = len(self.models)
         self.N_total = sum(m.N for m in self.models)
@@ -246,12 +323,26 @@ class Workspace:
                                               _stream()))
         return ld, info
 
-    def solve(self, rhs: Optional[torch.Tensor] = None):
+    def solve(self, rhs: Optional[torch.Tensor] = None, refine_max: int = -1,
+              refine_tol: float = DL_REFINE_TOL, return_converged: bool = False):
+        """Solve with the factor of Q_c: the assembled A^T D y (rhs None;
+        returns the mean) or, in place, rhs of shape (N_total,) or
+        (nrhs, N_total).  refine_max < 0: the workspace's default FP64
+        refinement; otherwise at most refine_max corrections to refine_tol.
+        With return_converged, also whether every solve met refine_tol."""
         if rhs is None:
-            _check("bta_solve", lib().bta_solve(self.h, None, _stream()))
-            return self.mean()
-        _check("bta_solve", lib().bta_solve(self.h, _ptr(rhs), _stream()))
-        return rhs
+            code = lib().bta_solve(self.h, None, 1, int(refine_max), float(refine_tol),
+                                   _stream())
+            out = self.mean()
+        else:
+            assert rhs.shape[-1] == self.N_total and rhs.is_contiguous()
+            nrhs = 1 if rhs.dim() == 1 else rhs.shape[0]
+            code = lib().bta_solve(self.h, _ptr(rhs), nrhs, int(refine_max),
+                                   float(refine_tol), _stream())
+            out = rhs
+        if code != DL_ENOTCONV:
+            _check("bta_solve", code)
+        return (out, code == 0) if return_converged else out
 
     def mean(self) -> torch.Tensor:
         out = torch.empty(self.N_total, dtype=torch.float64, device=self.dev)
@@ -381,6 +472,16 @@ class Workspace:
                                                         _ptr(out), _stream()))
         # column-major storage -> logical matrix
         return out.T if out.dim() == 2 else out
+
+    def set_block(self, which: int, kind: int, t: int, M: torch.Tensor):
+        """Overwrite one block of the assembled matrix (see get_block for
+        kind); M is the logical matrix (or the N-vector for kind 4)."""
+        if M.dim() == 2:
+            M = M.T.contiguous()  # column-major storage
+        else:
+            M = M.contiguous()
+        _check("dl_ws_set_block", lib().dl_ws_set_block(self.h, which, kind, t, _ptr(M),
+                                                        _stream()))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -1,5 +1,5 @@
 """Hessian of f at the mode and the Gaussian approximation of the
-hyperparameter marginals (Sec. II-C), on the batched GPU evaluator.
+hyperparameter marginals (Sec. III, marginal posteriors of the hyperparameters), on the batched GPU evaluator.
 
 The second-order central differences with step h on the internal theta --
     H_ii = (f(x + h e_i) - 2 f(x) + f(x - h e_i)) / h^2,

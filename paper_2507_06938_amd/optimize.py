@@ -30,7 +30,7 @@ from __future__ import annotations
 import dataclasses
 import math
 import time
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 import torch
@@ -53,8 +53,9 @@ class Evaluator:
     line searches."""
 
     def __init__(self, model: "D.Model", batch: int, graph: bool = True, ntrial: int = 4,
-                 warm_start: Optional[bool] = None):
+                 warm_start: Optional[bool] = None, mixed: bool = False):
         self.model = model
+        self.mixed = mixed
         self.B = batch
         self.ntrial = ntrial
         # warm_start (Poisson likelihood; the default for it): each instance's
@@ -62,8 +63,10 @@ class Evaluator:
         # the nearby points of consecutive gradients and line searches reuse
         if warm_start is None:
             warm_start = getattr(model, "likelihood", "gaussian") == "poisson"
-        self.ws = D.Workspace([model] * batch, graph=graph, warm_start=warm_start)
-        self.ws_ls = D.Workspace([model] * ntrial, graph=graph, warm_start=warm_start)
+        self.ws = D.Workspace([model] * batch, graph=graph, warm_start=warm_start,
+                              mixed=mixed)
+        self.ws_ls = D.Workspace([model] * ntrial, graph=graph, warm_start=warm_start,
+                                 mixed=mixed)
         self.dim = model.dim_theta
         self.count = 0
         self.archive_x: List[np.ndarray] = []
@@ -150,22 +153,29 @@ def _exact_step(ev, x, F, g, H, max_step):
 
 def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
             f_target: Optional[float] = None, target_rtol: float = 1e-6,
-            max_step: float = 1.0) -> Trace:
+            max_step: float = 1.0, f_check: Optional[Callable[[np.ndarray], float]] = None,
+            count: Optional[Callable[[], int]] = None, kind: str = "fd") -> Trace:
+    """f_check (optional): the value the target test uses at each iterate
+    instead of ev's (an FP64 evaluation when ev is mixed precision); count:
+    the evaluation counter the trace records (default ev.count)."""
     t0 = time.perf_counter()
     tr = Trace()
     x = np.asarray(theta0, np.float64).copy()
     F, g = fd_gradient(ev, x, h)
     H = np.eye(x.shape[0])
     first = True
+    count = count or (lambda: ev.count)
 
-    def log(kind):
-        tr.theta.append(x.copy()); tr.f.append(F); tr.exact_evals.append(ev.count)
-        tr.wall.append(time.perf_counter() - t0); tr.kind.append(kind)
+    def log(k):
+        tr.theta.append(x.copy()); tr.f.append(F); tr.exact_evals.append(count())
+        tr.wall.append(time.perf_counter() - t0); tr.kind.append(k)
 
     log("start")
     for _ in range(max_iter):
-        if f_target is not None and abs(F - f_target) <= target_rtol * abs(f_target):
-            break
+        if f_target is not None:
+            Fc = f_check(x) if f_check is not None else F
+            if abs(Fc - f_target) <= target_rtol * abs(f_target):
+                break
         if np.max(np.abs(g)) <= gtol:
             break
         a, xn, Fn, H = _exact_step(ev, x, F, g, H, max_step)
@@ -176,10 +186,40 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
         first = False
         rel = abs(Fn2 - F) / max(1.0, abs(F))
         x, F, g = xn, Fn2, gn
-        log("fd")
+        log(kind)
         if f_target is None and rel <= ftol:
             break
     return tr
+
+
+def mixed_fd_bfgs(ev: Evaluator, ev64: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4,
+                  max_iter=100, f_target: Optional[float] = None,
+                  target_rtol: float = 1e-6, max_step: float = 1.0) -> Trace:
+    """FD-BFGS on the mixed-precision evaluator `ev`, then FD-BFGS on the
+    FP64 evaluator `ev64` from the point where the mixed search stops (a
+    failed line search or ftol/gtol on its values: the floor its FP32
+    rounding puts under the finite differences).  With f_target the target
+    is tested on FP64 values (one ev64 evaluation per mixed iterate).  The
+    trace's f are the evaluator's own values (mixed in the first phase,
+    kind 'mixed'; FP64 in the second, kind 'fd'); exact_evals counts both
+    evaluators."""
+    total = lambda: ev.count + ev64.count
+    check = (lambda x: float(ev64(x[None])[0])) if f_target is not None else None
+    t1 = fd_bfgs(ev, theta0, h=h, ftol=ftol, gtol=gtol, max_iter=max_iter,
+                 f_target=f_target, target_rtol=target_rtol, max_step=max_step,
+                 f_check=check, count=total, kind="mixed")
+    x1 = t1.theta[-1]
+    if f_target is not None and abs(check(x1) - f_target) <= target_rtol * abs(f_target):
+        return t1
+    t2 = fd_bfgs(ev64, x1, h=h, ftol=ftol, gtol=gtol, max_iter=max_iter,
+                 f_target=f_target, target_rtol=target_rtol, max_step=max_step,
+                 count=total)
+    off = t1.wall[-1]
+    for i in range(len(t2.f)):
+        t1.theta.append(t2.theta[i]); t1.f.append(t2.f[i])
+        t1.exact_evals.append(t2.exact_evals[i]); t1.wall.append(off + t2.wall[i])
+        t1.kind.append("fp64-start" if i == 0 else t2.kind[i])
+    return t1
 
 
 class Surrogate:

@@ -62,3 +62,24 @@ def test_surrogate_bfgs_reaches_oracle_optimum(problem):
     assert abs(tr.f[-1] - fs) <= REL * abs(fs)
     # every accepted step was decided by exact values: F never increases
     assert all(b <= a + 1e-12 * abs(a) for a, b in zip(tr.f, tr.f[1:]))
+
+
+def test_mixed_fd_bfgs_reaches_oracle_optimum(problem):
+    """Mixed precision (FP32 off-diagonal blocks, FP64 diagonal blocks and
+    refined mean) drives the search; FP64 evaluations test the target and
+    finish from where the mixed finite differences stall.  The end point's
+    FP64 value must reach the oracle's optimum."""
+    from paper_2507_06938_amd import dalia as D
+    from paper_2507_06938_amd import optimize as O
+    wl, theta0, xs, fs = problem
+    model = D.Model.from_workload(wl)
+    ev = O.Evaluator(model, batch=2 * wl.dim_theta + 1, mixed=True)
+    ev64 = O.Evaluator(model, batch=2 * wl.dim_theta + 1)
+    tr = O.mixed_fd_bfgs(ev, ev64, theta0, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300,
+                         f_target=fs, target_rtol=REL)
+    F64 = float(ev64(tr.theta[-1][None])[0])
+    kinds = {k: tr.kind.count(k) for k in set(tr.kind)}
+    print(f"oracle F*={fs:.12f}  mixed-driven F(FP64)={F64:.12f} steps={kinds} "
+          f"mixed evals={ev.count} fp64 evals={ev64.count}", flush=True)
+    assert abs(F64 - fs) <= REL * abs(fs)
+    assert ev.count > 0 and tr.kind.count("mixed") >= 1

@@ -1,4 +1,4 @@
-"""Poisson likelihood (non-Gaussian, Section II-B): the inner mode by damped
+"""Poisson likelihood (non-Gaussian; Section II-A, conditional Gaussian distribution): the inner mode by damped
 Newton on the GPU and f_obj by the Laplace approximation at it, against the
 oracle's independent implementation (oracle/laplace.py) on the same seeded
 count workloads.
