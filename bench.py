@@ -201,6 +201,37 @@ def gemm_roofline(prof, steps):
     }
 
 
+def check_timed_step(g, p, info, var, mu):
+    """The timed step's f_obj, log-determinants, quadratic forms, mean and
+    marginal variances against the stored oracle values `g` (None: no stored
+    values), with the parity tolerances of the tests: log-determinants
+    1e-10 relative, f 1e-10 (|log|Q_p|| + |log|Q_c||), quadratic forms 1e-9
+    relative, mean 1e-9 max|mu|, variances 1e-9 relative."""
+    import numpy as np
+    if g is None:
+        return None
+    scale = abs(g["logdet_p"]) + abs(g["logdet_c"])
+    mu_s = mu[np.asarray(g["mu_index_bta"])]
+    mu_want = np.asarray(g["mu"])
+    v_s = var[np.asarray(g["var_index_bta"])]
+    v_want = np.asarray(g["var"])
+    e = {"logdet_p_rel": abs(p[1] - g["logdet_p"]) / abs(g["logdet_p"]),
+         "logdet_c_rel": abs(p[2] - g["logdet_c"]) / abs(g["logdet_c"]),
+         "f_abs": abs(p[0] - g["f"]),
+         "f_rel_scale": abs(p[0] - g["f"]) / scale,
+         "quad_p_rel": abs(p[3] - g["quad_p"]) / abs(g["quad_p"]),
+         "quad_obs_rel": abs(p[4] - g["quad_obs"]) / abs(g["quad_obs"]),
+         "mu_rel_max": float(np.max(np.abs(mu_s - mu_want)) / np.max(np.abs(mu_want))),
+         "var_rel_max": float(np.max(np.abs(v_s - v_want) / v_want)),
+         "mu_positions": int(mu_s.size), "var_positions": int(v_s.size)}
+    e["ok"] = bool(info.tolist() == [[0, 0]] and e["logdet_p_rel"] <= 1e-10
+                   and e["logdet_c_rel"] <= 1e-10 and e["f_rel_scale"] <= 1e-10
+                   and e["quad_p_rel"] <= 1e-9 and e["quad_obs_rel"] <= 1e-9
+                   and e["mu_rel_max"] <= 1e-9 and e["var_rel_max"] <= 1e-9
+                   and bool(np.all(np.isfinite(var))) and bool(np.all(var > 0)))
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +311,10 @@ def main():
     t1 = time.perf_counter()
     prof = ws.profile_end()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    # the last timed step's own outputs (nothing has run since), checked
+    # against the stored oracle values below
+    timed_out = (parts.cpu().numpy()[0].copy(), info.cpu().numpy().copy(),
+                 var.cpu().numpy().copy(), ws.mean().cpu().numpy())
     value = args.steps / (t1 - t0)
     roofline = gemm_roofline(prof, 1)
     roofline["steps_bracketed"] = 1
@@ -326,6 +361,7 @@ def main():
                 "logdet_c": abs(p[2] - g["logdet_c"]) / abs(g["logdet_c"]),
                 "f_abs": abs(p[0] - g["f"])}
     err = errors(pr)
+    check = check_timed_step(g, *timed_out)
 
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
@@ -343,6 +379,7 @@ def main():
         "bta_cholesky_tflops": F / (fac_ms * 1e-3) / 1e12,
         "bta_cholesky_ms": fac_ms,
         "logdet_rel_err_vs_fp64_oracle": err,
+        "timed_step_vs_oracle": check,
         "roofline": roofline,
         "cpu_baseline": None,
     }
@@ -357,6 +394,10 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt, model=args.model)
     print(json.dumps(out), flush=True)
+    if check is not None and not check["ok"]:
+        print("the timed step's outputs are outside the parity tolerances",
+              file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -1,11 +1,14 @@
 """Mixed precision: FP32 off-diagonal blocks and FP32 matrix-core products,
 FP64 diagonal blocks, log-determinants and iterative refinement of the mean.
 
-It is an approximation of the FP64 evaluation: log-determinant, f_obj and
-variance errors against the FP64 path are measured and written to
-gpurun_out/mixed_errors.json (sanity bounds only), while the refined mean
-must meet the FP64 residual bound |A^T D y - Q_c mu| <= 1e-12 |A^T D y|
-and agree with the FP64 mean to 1e-9 relative."""
+It is an approximation of the FP64 method, so its errors are measured
+against the oracle -- the dense FP64 oracle for the small cases, the values
+stored by tests/golden/make_golden.py (RCM + banded LAPACK Cholesky) at
+production size -- and printed as one `MIXED_ERR` line per case (the table
+kept with the profiles comes from these lines).  Pass/fail: the refined
+mean meets the FP64 residual bound |A^T D y - Q_c mu| <= 1e-12 |A^T D y|
+and the FP64 parity bound on mu (1e-9 of max|mu|); the log-determinant,
+f_obj and variance errors only have sanity bounds."""
 import json
 import os
 
@@ -13,10 +16,13 @@ import numpy as np
 import pytest
 
 import workloads as W
+from oracle import fobj as OF
+from oracle import model as OM
+from oracle.linalg import DenseSPD
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-OUT = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -28,55 +34,64 @@ def D():
     return dalia
 
 
-CASES = {
+SMALL = {
     "c0": W.config0,
     "tri_small": lambda: W.scaled("tri", 6, 5, 3, 2, 60, seed=4),
-    "c1_univariate_45x45_nt100": W.config1,
-    "c2_trivariate_30x30_nt48": W.config2,
     "diffusion_tri_small": lambda: W.scaled("dtri", 6, 5, 3, 2, 60, seed=4,
                                             model="diffusion"),
-    "c1_univariate_45x45_nt100_diffusion": lambda: W.config1(model="diffusion"),
+}
+FULL = {
+    "c1": W.config1,
+    "c2": W.config2,
+    "c1_diffusion": lambda: W.config1(model="diffusion"),
 }
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_mixed_against_fp64(D, name):
-    wl = CASES[name]()
+def reference(name):
+    """Oracle values: logdets, f, and (index, value) samples of mu and of
+    the marginal variances in BTA order."""
+    if name in SMALL:
+        wl = SMALL[name]()
+        ref = OF.fobj_parts(wl, wl.theta, return_factors=True)
+        perm = OM.bta_permutation(wl.nv, wl.ns, wl.nt, wl.nr)
+        idx = np.arange(wl.N)
+        return wl, dict(logdet_p=ref["logdet_p"], logdet_c=ref["logdet_c"], f=ref["f"],
+                        mu_index_bta=idx, mu=ref["mu"][perm], var_index_bta=idx,
+                        var=DenseSPD(ref["Qc"]).inv_diag()[perm])
+    g = json.load(open(os.path.join(GOLD, f"{name}_golden.json")))
+    return FULL[name](), g
+
+
+@pytest.mark.parametrize("name", list(SMALL) + list(FULL))
+def test_mixed_against_oracle(D, name):
+    wl, g = reference(name)
     model = D.Model.from_workload(wl)
-    res = {}
-    outs = {}
-    for tag, mixed in (("fp64", False), ("mixed", True)):
-        ws = D.Workspace(model, selinv=True, mixed=mixed)
-        f, parts, info = ws.fobj(wl.theta)
-        mu = ws.mean()
-        var = ws.selinv()
-        torch.cuda.synchronize()
-        outs[tag] = (parts.cpu().numpy()[0], mu.cpu().numpy(), var.cpu().numpy(),
-                     info.cpu().numpy())
-        del ws
-    p64, mu64, v64, i64 = outs["fp64"]
-    pmx, mumx, vmx, imx = outs["mixed"]
-    assert i64.tolist() == [[0, 0]] and imx.tolist() == [[0, 0]]
+    ws = D.Workspace(model, selinv=True, mixed=True, two_sided=True, fold_inverse=True)
+    print(f"{name} N={wl.N}", flush=True)
+    f, parts, info, var = ws.fobj_selinv(wl.theta)
+    torch.cuda.synchronize()
+    mu = ws.mean().cpu().numpy()
+    p = parts.cpu().numpy()[0]
+    v = var.cpu().numpy()
+    assert info.cpu().tolist() == [[0, 0]]
+    mi, vi = np.asarray(g["mu_index_bta"]), np.asarray(g["var_index_bta"])
+    mu_want, v_want = np.asarray(g["mu"]), np.asarray(g["var"])
     err = dict(
-        logdet_p_rel=abs(pmx[1] - p64[1]) / abs(p64[1]),
-        logdet_c_rel=abs(pmx[2] - p64[2]) / abs(p64[2]),
-        f_abs=abs(pmx[0] - p64[0]),
-        f_rel_to_logdets=abs(pmx[0] - p64[0]) / (abs(p64[1]) + abs(p64[2])),
-        mu_rel=float(np.max(np.abs(mumx - mu64)) / np.max(np.abs(mu64))),
-        var_rel_max=float(np.max(np.abs(vmx - v64) / v64)),
-        var_rel_median=float(np.median(np.abs(vmx - v64) / v64)),
-        residual_mixed=float(pmx[7]),
-        residual_fp64=float(p64[7]),
+        logdet_p_rel=abs(p[1] - g["logdet_p"]) / abs(g["logdet_p"]),
+        logdet_c_rel=abs(p[2] - g["logdet_c"]) / abs(g["logdet_c"]),
+        f_abs=abs(p[0] - g["f"]),
+        f_rel_to_logdets=abs(p[0] - g["f"]) / (abs(g["logdet_p"]) + abs(g["logdet_c"])),
+        mu_rel=float(np.max(np.abs(mu[mi] - mu_want)) / np.max(np.abs(mu_want))),
+        var_rel_max=float(np.max(np.abs(v[vi] - v_want) / v_want)),
+        var_rel_median=float(np.median(np.abs(v[vi] - v_want) / v_want)),
+        refined_rel_residual=float(p[7]),
+        positions=int(vi.size),
     )
-    os.makedirs(OUT, exist_ok=True)
-    path = os.path.join(OUT, "mixed_errors.json")
-    allr = json.load(open(path)) if os.path.exists(path) else {}
-    allr[name] = err
-    json.dump(allr, open(path, "w"), indent=1)
-    print(name, err)
+    print("MIXED_ERR", name, json.dumps(err), flush=True)
     # pass/fail: the refined mean meets the FP64 bounds
-    assert err["residual_mixed"] <= 1e-12, err
+    assert err["refined_rel_residual"] <= 1e-12, err
     assert err["mu_rel"] <= 1e-9, err
-    # sanity bounds on the approximation (reported values are the result)
+    # sanity bounds on the approximation (the reported values are the result)
     assert err["logdet_c_rel"] <= 1e-4 and err["logdet_p_rel"] <= 1e-4, err
     assert err["var_rel_max"] <= 1e-2, err
+    assert np.all(np.isfinite(v)) and np.all(v > 0)

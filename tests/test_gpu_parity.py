@@ -164,3 +164,23 @@ def test_non_spd_theta_gives_minus_inf(D):
     f, parts, info = ws.fobj(th)
     torch.cuda.synchronize()
     assert f.item() == -math.inf
+
+
+@pytest.mark.parametrize("sd", [0.3, 2.5])
+def test_theta_prior_sd_and_mean(D, sd):
+    """A prior on theta with sd != 1 and a mean away from the evaluation
+    point: log p(theta) (the Gaussian density, constant included) and f_obj
+    against the oracle, univariate and trivariate."""
+    for wl in (W.config0(), W.scaled("tri_sd", 5, 4, 3, 2, 40, seed=4)):
+        wl.theta_prior_sd = sd
+        wl.theta_prior_mean = wl.theta + 0.2 * np.cos(np.arange(wl.dim_theta))
+        ref = OF.fobj_parts(wl, wl.theta)
+        model = D.Model.from_workload(wl)
+        ws = D.Workspace(model)
+        f, parts, info = ws.fobj(wl.theta)
+        torch.cuda.synchronize()
+        p = parts.cpu().numpy()[0]
+        assert info.cpu().tolist() == [[0, 0]]
+        assert abs(p[5] - ref["log_prior"]) <= 1e-12 * max(1.0, abs(ref["log_prior"]))
+        scale = abs(ref["logdet_p"]) + abs(ref["logdet_c"])
+        assert abs(f.item() - ref["f"]) <= 1e-10 * scale
