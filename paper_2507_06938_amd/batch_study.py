@@ -4,9 +4,10 @@ mix, each as batched, graph-replayed workspaces in FP64 and mixed precision.
 
     python -m paper_2507_06938_amd.batch_study [--skip-uneven] [--skip-fd]
 
-The uneven mix needs more device memory than one GPU holds at once, so it is
-packed (largest first) into waves of at most --mem-gb of workspace each; a
-wave is one workspace of uneven instances evaluated together.  Prints one
+The uneven mix needs more device memory than one GPU holds at once, so the
+library's planner (dl_plan_waves: first fit, largest first) splits it into
+waves of at most --mem-gb of workspace each; a wave is one workspace of
+uneven instances evaluated together.  Prints one
 JSON document: evals/s of every configuration, the sequential single-
 instance rate for comparison, device bytes, and whether every evaluation
 reported positive-definite factors.
@@ -18,16 +19,6 @@ import json
 import os
 import sys
 import time
-
-
-def _ws_bytes_estimate(wl, mixed):
-    """Device bytes of an f_obj workspace (dense Q_c blocks dominate)."""
-    bp = (wl.b + 63) // 64 * 64
-    ap = 64 if wl.a > 0 else 0
-    eb = 4 if mixed else 8
-    qc = wl.nt * bp * bp * 8 + (wl.nt + 1) * (bp + ap) * bp * eb
-    ring = 2 * bp * bp * 8 + 3 * bp * bp * eb
-    return int(1.05 * (qc + ring)) + (64 << 20)
 
 
 def main(argv=None):
@@ -101,18 +92,9 @@ def main(argv=None):
         models = [D.Model.from_workload(w) for w in wls]
         res = {"instances": 64}
         for mixed in (False, True):
-            cap = args.mem_gb * 1e9
-            order = sorted(range(64), key=lambda k: -_ws_bytes_estimate(wls[k], mixed))
-            waves, cur, used = [], [], 0
-            for k in order:
-                b = _ws_bytes_estimate(wls[k], mixed)
-                if cur and used + b > cap:
-                    waves.append(cur)
-                    cur, used = [], 0
-                cur.append(k)
-                used += b
-            if cur:
-                waves.append(cur)
+            # the library's planner: first fit, largest first, within the budget
+            waves = D.plan_waves(models, int(args.mem_gb * 1e9), graph=True, mixed=mixed,
+                                 two_sided=args.order == "two-sided")
             total_t, ok, gb = 0.0, True, []
             for wave in waves:
                 ws = D.Workspace([models[k] for k in wave], graph=True, mixed=mixed,
