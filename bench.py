@@ -255,6 +255,10 @@ def main():
                     help="elimination order: time steps forward only, or the "
                          "two halves of the time domain concurrently toward "
                          "a middle block (two time-domain partitions)")
+    ap.add_argument("--diag-factor", choices=("panel", "dag"), default="panel",
+                    help="diagonal blocks factored by one launch per 64-column "
+                         "panel, or by one persistent tile-task launch per "
+                         "elimination step")
     ap.add_argument("--tiles", default=os.path.join(
         ROOT, "paper_2507_06938_amd", "tiles_gfx950.txt"),
         help="autotuner cache ('' disables tuning: default tiles)")
@@ -275,7 +279,8 @@ def main():
     wl = W.config1(model=args.model)
     model = D.Model.from_workload(wl)
     two_sided = args.order == "two-sided"
-    ws = D.Workspace(model, selinv=True, two_sided=two_sided, fold_inverse=True)
+    dag = args.diag_factor == "dag"
+    ws = D.Workspace(model, selinv=True, two_sided=two_sided, fold_inverse=not dag, dag=dag)
     tiles = ws.autotune(args.tiles) if args.tiles else None
     dev = torch.device("cuda")
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev)
@@ -373,7 +378,8 @@ def main():
                    "nb": wl.a, "m": wl.m, "b": wl.b, "N": wl.N,
                    "step": "fobj_eval + bta_selinv (all marginal variances)",
                    "order": args.order,
-                   "block_inverse": "inside the panel launches",
+                   "block_inverse": ("inside the persistent tile-task launches" if dag
+                                     else "inside the panel launches"),
                    "gemm_tiles": tiles},
         "fobj_only_evals_per_s": 1000.0 / fobj_ms,
         "bta_cholesky_tflops": F / (fac_ms * 1e-3) / 1e12,

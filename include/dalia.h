@@ -206,7 +206,21 @@ enum {
                          nearby thetas (line searches, difference stencils)
                          it takes fewer steps; the mode is unique, so results
                          differ from a cold start by rounding only, but they
-                         depend on the call history                        */
+                         depend on the call history                        */,
+  DL_WS_DAG = 256     /* factor each step's diagonal blocks in one persistent
+                         launch (a tile-task graph, Sec. III-A's Cholesky
+                         of the diagonal block with its inverse formed
+                         alongside): workgroups take 64 x 64 tile tasks --
+                         tile factor, panel solve, trailing update, inverse
+                         accumulation and inverse row -- in a fixed order and
+                         wait on per-tile readiness counters, so the next
+                         tile factor starts as soon as its tile is final
+                         instead of after a whole panel launch.  Holds the
+                         inverse like DL_WS_FOLD_INV; needs one bp x bp
+                         block of doubles per matrix and elimination chain
+                         for the L tiles.
+                         Results differ from the panel path by rounding
+                         only                                               */
 };
 /* FP64 iterative refinement of the mean (DL_WS_MIXED workspaces; any
  * workspace through bta_solve on request): x <- x + c, where c solves
@@ -224,6 +238,9 @@ enum {
 #define DL_REFINE_MAX 10
 #define DL_REFINE_STEPS_GRAPH 3
 #define DL_INFO_NOTCONV (-1)
+/* info value of a factorisation whose persistent launch (DL_WS_DAG) gave up
+ * waiting for a tile (it never should; f is then -inf). */
+#define DL_INFO_TIMEOUT (-2)
 
 /* Allocate the dense BTA workspace for Q_p and Q_c of `model`.  All device
  * memory of the evaluation path is allocated here. */
@@ -539,7 +556,8 @@ enum {
   DL_KERNEL_ASSEMBLE = 3,    /* assembly                                 */
   DL_KERNEL_OTHER = 4,
   DL_KERNEL_PANEL = 5,       /* fused trailing update + next tile factor */
-  DL_KERNEL_GEMM_REDUCE = 6  /* sum of the pieces of split-k products    */
+  DL_KERNEL_GEMM_REDUCE = 6, /* sum of the pieces of split-k products    */
+  DL_KERNEL_DAG = 7          /* persistent diagonal-block factorisation  */
 };
 dl_status dl_ws_profile_begin(dl_ws* ws, int32_t category_mask,
                               int32_t max_launches);

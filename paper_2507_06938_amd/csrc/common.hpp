@@ -172,6 +172,33 @@ int finalize_panels(PanelTask* t, int n);
 hipError_t launch_panel_updates(const PanelTask* tasks_dev, int ntask, int grid,
                                 hipStream_t s);
 
+// ---- persistent tile-task factorisation of diagonal blocks --------------------
+// One launch factors several diagonal blocks (A = L L^T, G = L^{-1} formed
+// alongside) by working through the task list of dag.hpp: each workgroup
+// takes the next task word (in list order), waits until the counters it
+// depends on are set, runs the task on 64 x 64 tiles and sets its counter.
+// On return each block holds G in its lower triangle, logdiag[i] = log L_ii
+// and *info the first bad pivot (as the panel path), or DL_INFO_TIMEOUT when
+// a wait gave up (it never should: the list order cannot deadlock).
+struct DagBlock {
+  double* A;          // the block (bp x bp, ld)
+  int64_t ld;
+  double* L;          // tiles L(i, k), i > k, same layout and ld as A
+  double* stage;      // inverse accumulators: tile (r, c) at ((r (r-1)) / 2 + c) * 4096, ld 64
+  double* logdiag;    // 64 * nbk entries
+  int64_t* info;
+  int64_t row0;       // BTA row of the block's first row
+  int32_t* ctr;       // nbk * nbk readiness counters: zero before the launch;
+                      // the launch's last workgroup zeroes them again
+  int32_t nbk, pad_;
+};
+// head[0]: next task, head[1]: finished workgroups, head[2]: set when a wait
+// gave up (then every later wait gives up at once, so the launch ends
+// quickly); all zero before the launch and reset by its last workgroup.
+// workers: the grid size.
+hipError_t launch_dag_chol(const uint64_t* tasks, int ntask, const DagBlock* blocks,
+                           int nblocks, int32_t* head, int workers, hipStream_t s);
+
 // ---- small batched element-wise jobs ------------------------------------------
 // MJ_AXPY_UNCONV: dst += src unless norms[0] <= tol2[0] * norms[1] (a
 // residual already within the squared relative tolerance: the iterate

@@ -2,6 +2,9 @@
 // fills, deterministic log-sum reductions.
 #include "common.hpp"
 
+#define DL_DAG_FN __host__ __device__ inline
+#include "dag.hpp"
+
 namespace dl {
 
 namespace {
@@ -17,6 +20,32 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
+}
+
+// Device-coherent accesses (agent-scope relaxed atomics: sc1 loads and
+// stores that bypass the per-XCD caches): the persistent factorisation
+// exchanges tiles between workgroups on different XCDs with these.
+// (global address space: keeps them off the generic load path)
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double cload(const double* p) {
+  return __hip_atomic_load((const gdouble*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore(double* p, double v) {
+  __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// p must point to global memory
+__device__ __forceinline__ double global_load(const double* p) { return *(const gdouble*)p; }
+// COH: a device-coherent load of global memory; otherwise a plain load
+// through a generic pointer (the tile factor also reads LDS tiles this way)
+template <bool COH>
+__device__ __forceinline__ double gload(const double* p) {
+  if constexpr (COH) return cload(p);
+  else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void gstore(double* p, double v) {
+  if constexpr (COH) cstore(p, v);
+  else *p = v;
 }
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps
@@ -79,7 +108,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ X, int64_t
 // TILE_LDS doubles (Lc[k*LDL + i] = L(i, k), Gk[k*LDL + c] = G(k, c)).
 // Outputs as described for PotrfTileArgs (A/lda: where mode 0 writes L and
 // mode 1 writes G).
-template <int CW>
+template <int CW, bool COH = false>
 __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, double* Lc,
                                            double* Gk, int* sbad, double* A, int64_t lda,
                                            double* Ginv, double* logdiag, int64_t* info,
@@ -92,7 +121,7 @@ __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, doubl
   double r[CW], g[CW];
 #pragma unroll
   for (int q = 0; q < CW; ++q) {
-    r[q] = src[(int64_t)i + (int64_t)(CW * wv + q) * lds];
+    r[q] = gload<COH>(&src[(int64_t)i + (int64_t)(CW * wv + q) * lds]);
     g[q] = (CW * wv + q == i) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -163,7 +192,7 @@ __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, doubl
   if (dst) {
     for (int idx = threadIdx.x; idx < NB * NB; idx += NT) {
       const int rr = idx & 63, cc = idx >> 6;
-      dst[rr + cc * ldd] = (rr >= cc) ? Gk[rr * LDL + cc] : 0.0;
+      gstore<COH>(&dst[rr + cc * ldd], (rr >= cc) ? Gk[rr * LDL + cc] : 0.0);
     }
   }
 }
@@ -200,18 +229,20 @@ hipError_t launch_potrf_tiles(const PotrfTileArgs* args, int count,
 // products each (see PanelTask).
 
 // S[k*LDL + r] = X(r, k) for the 64 x 64 tile X (ld), coalesced along r.
+template <bool COH = false>
 __device__ __forceinline__ void stage_cols(const double* __restrict__ X, int64_t ld, double* S) {
   for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT) {
     const int r = idx & 63, k = idx >> 6;
-    S[k * LDL + r] = X[r + (int64_t)k * ld];
+    S[k * LDL + r] = gload<COH>(&X[r + (int64_t)k * ld]);
   }
 }
 
 // S[k*LDL + r] = X(k, r) (the transpose), coalesced along k.
+template <bool COH = false>
 __device__ __forceinline__ void stage_rows(const double* __restrict__ X, int64_t ld, double* S) {
   for (int idx = threadIdx.x; idx < NB * NB; idx += POTRF_NT) {
     const int k = idx & 63, r = idx >> 6;
-    S[k * LDL + r] = X[k + (int64_t)r * ld];
+    S[k * LDL + r] = gload<COH>(&X[k + (int64_t)r * ld]);
   }
 }
 
@@ -445,6 +476,234 @@ hipError_t launch_panel_updates(const PanelTask* tasks, int ntask, int grid,
                                 hipStream_t s) {
   if (ntask <= 0 || grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_panel_update, dim3(grid), dim3(POTRF_NT), 0, s, tasks, ntask);
+  return hipGetLastError();
+}
+
+// ---- persistent tile-task factorisation of diagonal blocks ----------------------------
+//
+// Workgroups of 16 waves take task words from the launch's list in order
+// (one atomic add on head[0] each), wait until the counters the task depends
+// on are set (one lane polls, 0.5 s limit), run the task on 64 x 64 tiles
+// staged in two LDS tiles and set the task's counter.  The tile operations
+// are those of the panel path: the same staging, the same MFMA products
+// (mfma1_k64), the same tile factor (potrf_body).
+//
+// Hand-over between workgroups, which may sit on different XCDs (each with
+// its own L2), without cache write-back or invalidation: every value a task
+// writes for another task (A, G, L and accumulator tiles) is stored
+// device-coherently (sc1), and every value that another task may have
+// rewritten during the launch (A, G and accumulator tiles) is loaded
+// device-coherently.  L tiles are written once per launch, after which
+// nobody writes them, and nobody reads them before, so they are read through
+// the caches (each is read by many update tasks).  A task's stores are
+// complete (s_waitcnt) in every lane before the barrier after which its
+// counter is set; the counters themselves are relaxed device-scope atomics.
+
+namespace {
+constexpr long long kDagWaitTicks = 50000000;  // 0.5 s of the 100 MHz constant clock
+constexpr int DPER = NB * NB / POTRF_NT;        // elements of a tile per lane
+
+typedef __attribute__((address_space(1))) int32_t gint;
+__device__ __forceinline__ int dag_load(const int32_t* p) {
+  return __hip_atomic_load((const gint*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dag_store(int32_t* p, int v) {
+  __hip_atomic_store((gint*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// true once *p >= value; false after the time limit, or at once when the
+// launch has given up (*abort set by a wait that timed out)
+__device__ bool dag_wait(const int32_t* p, int value, int32_t* abort) {
+  if (dag_load(p) >= value) return true;
+  const long long t0 = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (dag_load(p) >= value) return true;
+    if (dag_load(abort) != 0) return false;
+    if (wall_clock64() - t0 > kDagWaitTicks) {
+      dag_store(abort, 1);
+      return false;
+    }
+  }
+}
+
+// The lane's DPER elements of the 64 x 64 tile X (global, ld): element idx =
+// threadIdx.x + e * POTRF_NT is X(idx & 63, idx >> 6).  All loads are issued
+// before any is used.
+template <bool COH>
+__device__ __forceinline__ void tile_regs(const double* __restrict__ X, int64_t ld,
+                                          double (&v)[DPER]) {
+#pragma unroll
+  for (int e = 0; e < DPER; ++e) {
+    const int idx = threadIdx.x + e * POTRF_NT;
+    const double* p = &X[(idx & 63) + (int64_t)(idx >> 6) * ld];
+    v[e] = COH ? cload(p) : global_load(p);
+  }
+}
+// as stage_cols: S[k*LDL + r] = X(r, k)
+__device__ __forceinline__ void regs_to_cols(const double (&v)[DPER], double* S) {
+#pragma unroll
+  for (int e = 0; e < DPER; ++e) {
+    const int idx = threadIdx.x + e * POTRF_NT;
+    S[(idx >> 6) * LDL + (idx & 63)] = v[e];
+  }
+}
+// as stage_rows: S[k*LDL + r] = X(k, r)
+__device__ __forceinline__ void regs_to_rows(const double (&v)[DPER], double* S) {
+#pragma unroll
+  for (int e = 0; e < DPER; ++e) {
+    const int idx = threadIdx.x + e * POTRF_NT;
+    S[(idx & 63) * LDL + (idx >> 6)] = v[e];
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(POTRF_NT) void k_dag_chol(const uint64_t* __restrict__ tasks,
+                                                       int ntask,
+                                                       const DagBlock* __restrict__ blocks,
+                                                       int nblocks, int32_t* head) {
+  __shared__ __align__(16) double pool[2 * TILE_LDS];
+  __shared__ int s_task, s_bad, s_last;
+  double* S0 = pool;
+  double* S1 = pool + TILE_LDS;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int p0 = 16 * (wv >> 2), q0 = 16 * (wv & 3);  // this wave's 16 x 16 block
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(head, 1);
+    __syncthreads();
+    const int ti = s_task;
+    if (ti >= ntask) break;
+    int bi = 0;
+    const dag::Task t = dag::unpack(tasks[ti], &bi);
+    const DagBlock B = blocks[bi];
+    const int64_t ld = B.ld;
+    auto tile = [&](double* base, int r, int c) {
+      return base + (int64_t)r * NB + (int64_t)c * NB * ld;
+    };
+    if (threadIdx.x == 0) {
+      dag::Wait w[4], set;
+      const int nw = dag::waits_of(B.nbk, t, w, &set);
+      bool ok = true;
+      for (int e = 0; e < nw; ++e) ok = dag_wait(B.ctr + w[e].ctr, w[e].value, head + 2) && ok;
+      if (!ok)
+        atomicCAS((unsigned long long*)B.info, 0ull, (unsigned long long)(int64_t)DL_INFO_TIMEOUT);
+    }
+    __syncthreads();
+    switch (t.type) {
+      case dag::T_F: {
+        double* Akk = tile(B.A, t.k, t.k);
+        potrf_body<POTRF_CW, true>(Akk, ld, S0, S1, &s_bad, Akk, ld, nullptr,
+                                   B.logdiag + (int64_t)t.k * NB, B.info,
+                                   B.row0 + (int64_t)t.k * NB, 1);
+        break;
+      }
+      case dag::T_S: {
+        // L(i, k) = A(i, k) G_kk^T: S1[q][r] = G(r, q), S0[c][m] = A(m, c)
+        double vg[DPER], va[DPER];
+        tile_regs<true>(tile(B.A, t.k, t.k), ld, vg);
+        tile_regs<true>(tile(B.A, t.i, t.k), ld, va);
+        regs_to_cols(vg, S1);
+        regs_to_cols(va, S0);
+        __syncthreads();
+        v4d a0 = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L(m = q0 + lr, c = p0 + lk + 4r)
+        double* Lo = tile(B.L, t.i, t.k);
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) cstore(&Lo[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld], a0[rg]);
+        break;
+      }
+      case dag::T_U: {
+        // A(i, k) -= L(i, j) L(k, j)^T
+        const bool diag = t.i == t.k;
+        double vp[DPER], vq[DPER], cpre[4];
+        tile_regs<false>(tile(B.L, t.i, t.j), ld, vp);
+        if (!diag) tile_regs<false>(tile(B.L, t.k, t.j), ld, vq);
+        double* C = tile(B.A, t.i, t.k);
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) cpre[rg] = cload(&C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld]);
+        regs_to_cols(vp, S0);
+        if (!diag) regs_to_cols(vq, S1);
+        __syncthreads();
+        v4d u0 = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(diag ? S0 : S1, p0, S0, q0, u0);  // update(m = q0 + lr, n = p0 + lk + 4r)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+          cstore(&C[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld], cpre[rg] - u0[rg]);
+        break;
+      }
+      case dag::T_A:
+      case dag::T_R: {
+        // A(r, c, m): S(r, c) (+)= L(r, m) G(m, c);
+        // R(j, c):    t = S(j, c) + L(j, j-1) G(j-1, c), G(j, c) = -G_jj t
+        const bool row = t.type == dag::T_R;
+        const int r = t.i, c = t.k, m = row ? t.i - 1 : t.j;
+        double* Sd = B.stage + ((int64_t)r * (r - 1) / 2 + c) * (NB * NB);
+        const bool acc = row ? (r - 1 > c) : (m > c);
+        double prev[4] = {0.0, 0.0, 0.0, 0.0};
+        if (acc) {
+#pragma unroll
+          for (int rg = 0; rg < 4; ++rg) prev[rg] = cload(&Sd[(q0 + lr) + (p0 + lk + 4 * rg) * NB]);
+        }
+        double vy[DPER], vx[DPER], vg[DPER];
+        tile_regs<false>(tile(B.L, r, m), ld, vy);  // Y = L(r, m)
+        tile_regs<true>(tile(B.A, m, c), ld, vx);   // X = G(m, c)
+        if (row) tile_regs<true>(tile(B.A, r, r), ld, vg);  // G_jj, for the second product
+        regs_to_cols(vy, S0);
+        regs_to_rows(vx, S1);
+        __syncthreads();
+        v4d tv = {prev[0], prev[1], prev[2], prev[3]};
+        mfma1_k64(S1, p0, S0, q0, tv);  // (Y X)(q0 + lr, p0 + lk + 4r)
+        if (!row) {
+#pragma unroll
+          for (int rg = 0; rg < 4; ++rg) cstore(&Sd[(q0 + lr) + (p0 + lk + 4 * rg) * NB], tv[rg]);
+          break;
+        }
+        __syncthreads();  // S0, S1 are read no more
+        regs_to_cols(vg, S0);  // G_jj
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) S1[(q0 + lr) * LDL + p0 + lk + 4 * rg] = tv[rg];
+        __syncthreads();
+        v4d g = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(S1, p0, S0, q0, g, q0 + 16);  // G_jj is lower triangular
+        double* dst = tile(B.A, r, c);
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) cstore(&dst[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld], -g[rg]);
+        break;
+      }
+    }
+    // every lane's stores complete before the counter is set
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      dag::Wait w[4], set;
+      (void)dag::waits_of(B.nbk, t, w, &set);
+      dag_store(B.ctr + set.ctr, set.value);
+    }
+  }
+  // the last workgroup out (every task is then complete) zeroes the
+  // counters and the head for the next launch
+  if (threadIdx.x == 0) s_last = atomicAdd(head + 1, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (s_last) {
+    for (int b = 0; b < nblocks; ++b) {
+      const int64_t nc = dag::counters_per_block(blocks[b].nbk);
+      for (int64_t i = threadIdx.x; i < nc; i += POTRF_NT) dag_store(blocks[b].ctr + i, 0);
+    }
+    if (threadIdx.x == 0) {
+      dag_store(head, 0);
+      dag_store(head + 1, 0);
+      dag_store(head + 2, 0);
+    }
+  }
+}
+
+hipError_t launch_dag_chol(const uint64_t* tasks, int ntask, const DagBlock* blocks,
+                           int nblocks, int32_t* head, int workers, hipStream_t s) {
+  if (ntask <= 0 || nblocks <= 0 || workers <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dag_chol, dim3(workers), dim3(POTRF_NT), 0, s, tasks, ntask, blocks,
+                     nblocks, head);
   return hipGetLastError();
 }
 

@@ -25,13 +25,14 @@
 #include "engine.hpp"
 #include "selinv.hpp"
 #include "solve.hpp"
+#include "dag.hpp"
 
 namespace dl {
 
 enum OpKind : int {
   OP_GEMM, OP_POTRF, OP_MISC, OP_GEMV_N, OP_GEMV_T, OP_SUM, OP_FINISH,
   OP_ASM_COLS, OP_ASM_TIPS, OP_THETA, OP_QUAD, OP_COMBINE, OP_GEMM32, OP_RES,
-  OP_PANEL, OP_NKIND
+  OP_PANEL, OP_DAG, OP_NKIND
 };
 
 // One step of one sequence (before merging).
@@ -43,6 +44,7 @@ struct Step {
   std::vector<GemmTask> gemm;
   PotrfTileArgs potrf{};
   PanelTask panel{};
+  DagBlock dagb{};
   MiscJob misc{};
   GemvN gn{};
   GemvT gt{};
@@ -90,6 +92,9 @@ struct Descs {
   std::vector<GemmTask> gemm;
   std::vector<PotrfTileArgs> potrf;
   std::vector<PanelTask> panel;
+  std::vector<DagBlock> dagb;   // blocks of the persistent factorisation launches
+  std::vector<uint64_t> dagt;   // their task words (one list per launch)
+  int dag_launches = 0;
   std::vector<MiscJob> misc;
   std::vector<GemvN> gn;
   std::vector<GemvT> gt;
@@ -106,6 +111,8 @@ struct DevDescs {
   GemmTask* gemm = nullptr;
   PotrfTileArgs* potrf = nullptr;
   PanelTask* panel = nullptr;
+  DagBlock* dagb = nullptr;
+  uint64_t* dagt = nullptr;
   MiscJob* misc = nullptr;
   GemvN* gn = nullptr;
   GemvT* gt = nullptr;
@@ -169,6 +176,23 @@ static void merge(const std::vector<std::vector<Step>>& seqs, Descs& D,
         for (const Step* st : g) D.panel.push_back(st->panel);
         L.count = (int)D.panel.size() - L.off;
         L.gx = finalize_panels(D.panel.data() + L.off, L.count);
+        break;
+      }
+      case OP_DAG: {
+        // one persistent launch over the blocks of the merged steps: their
+        // tasks in one list (dag.hpp)
+        L.off = (int)D.dagb.size();
+        std::vector<int> nbks;
+        for (const Step* st : g) {
+          D.dagb.push_back(st->dagb);
+          nbks.push_back(st->dagb.nbk);
+        }
+        L.count = (int)D.dagb.size() - L.off;
+        const std::vector<uint64_t> tl = dag::launch_list(nbks, true);
+        L.gy = (int)D.dagt.size();
+        D.dagt.insert(D.dagt.end(), tl.begin(), tl.end());
+        L.gx = (int)tl.size();
+        L.gz = D.dag_launches++;
         break;
       }
       case OP_MISC: PUSH(misc, misc)
@@ -257,8 +281,31 @@ static Step misc_step(uint64_t key, int cat, int kind, double* dst,
 // (j, 2) step j and the closing launch (j = nbk - 1), (nbk - 1, 3) the copy.
 static void seq_potrf(std::vector<Step>& q, uint64_t major, double* A, int64_t ld,
                       int n, double* logdiag, int64_t* info, int64_t row0,
-                      int breal, double* tmp, bool count_inv, bool fold) {
+                      int breal, double* tmp, bool count_inv, bool fold,
+                      double* lbuf = nullptr, int32_t* dctr = nullptr) {
   const int nbk = n / 64;
+  if (lbuf) {
+    // the whole factorisation and inverse in one persistent launch (shared
+    // with the other blocks of the same key)
+    Step s;
+    s.key = K(major, 1, 0, 2);
+    s.kind = OP_DAG;
+    s.cat = DL_CAT_PANEL_SYRK;
+    const double b3 = (double)breal * breal * breal / 3.0;
+    s.flops = b3 + (count_inv ? b3 : 0.0);
+    DagBlock& d = s.dagb;
+    d.A = A;
+    d.ld = ld;
+    d.L = lbuf;
+    d.stage = tmp;
+    d.logdiag = logdiag;
+    d.info = info;
+    d.row0 = row0;
+    d.ctr = dctr;
+    d.nbk = nbk;
+    q.push_back(s);
+    return;
+  }
   auto width = [&](int j) { return (double)std::max(0, std::min(64, breal - j * 64)); };
   auto below = [&](int j) { return (double)std::max(0, breal - (j + 1) * 64); };
   double* gside = tmp;
@@ -400,6 +447,10 @@ struct Inst {
   bool two = false;
   int mid = 0;
   double *PcB = nullptr, *ttempB[2] = {nullptr, nullptr};
+  // persistent diagonal-block factorisation (DL_WS_DAG): the L tiles and the
+  // readiness counters of the block each chain factors, per matrix
+  double *lbuf[2] = {nullptr, nullptr}, *lbufB[2] = {nullptr, nullptr};
+  int32_t *dctr[2] = {nullptr, nullptr}, *dctrB[2] = {nullptr, nullptr};
   double *uB = nullptr, *gpartB = nullptr, *xPB = nullptr;
   double *YB = nullptr, *XCB[2] = {nullptr, nullptr};
   double *theta = nullptr, *coef = nullptr, *logdiag[2] = {nullptr, nullptr};
@@ -431,6 +482,9 @@ struct dl_ws {
   bool sel = false, keep_qp = false, mixed = false;
   bool splitk = false;
   bool fold_inv = false;  // inverses inside the panel launches (DL_WS_FOLD_INV)
+  bool dag = false;       // one persistent launch per diagonal block (DL_WS_DAG)
+  int32_t* dag_heads = nullptr;  // [4 x launches] task head, finished workgroups, abort
+  int dag_workers = 0;           // grid of the persistent launches
   double* partials = nullptr;  // split-k partial tiles (shared by all launches)
   int64_t partials_cap = 0;    // doubles allocated at `partials`
   int dim_total = 0;
@@ -535,6 +589,7 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
     if (L.kind == OP_GEMM || L.kind == OP_GEMM32) kk = DL_KERNEL_GEMM;
     else if (L.kind == OP_POTRF) kk = DL_KERNEL_POTRF_TILE;
     else if (L.kind == OP_PANEL) kk = DL_KERNEL_PANEL;
+    else if (L.kind == OP_DAG) kk = DL_KERNEL_DAG;
     else if (L.kind == OP_GEMV_N || L.kind == OP_GEMV_T) kk = DL_KERNEL_GEMV;
     else if (L.kind == OP_ASM_COLS) kk = DL_KERNEL_ASSEMBLE;
     const int pk = prof_begin(W, L.cat, kk, s);
@@ -558,6 +613,11 @@ static hipError_t run_launch(dl_ws* W, const Launch& L, hipStream_t s) {
       case OP_RES: e = launch_residual(d.res + L.off, L.count, s); break;
       case OP_POTRF: e = launch_potrf_tiles(d.potrf + L.off, L.count, s); break;
       case OP_PANEL: e = launch_panel_updates(d.panel + L.off, L.count, L.gx, s); break;
+      case OP_DAG:
+        e = launch_dag_chol(d.dagt + L.gy, L.gx, d.dagb + L.off, L.count,
+                            W->dag_heads + 4 * (int64_t)L.gz,
+                            std::min(L.gx, W->dag_workers), s);
+        break;
       case OP_MISC: e = launch_misc(d.misc + L.off, L.count, s); break;
       case OP_GEMV_N: e = launch_gemv_n(d.gn + L.off, L.count, L.gx, s); break;
       case OP_GEMV_T: e = launch_gemv_t(d.gt + L.off, L.count, L.gx, s); break;
@@ -744,9 +804,11 @@ static void seq_factor(dl_ws* W, Inst& I, int w, int nt_max, std::vector<Step>& 
     }
     // factor and inverse of the diagonal block
     double* tmp = chain == 1 ? I.ttempB[w] : I.ttemp[w];
+    double* lb = W->dag ? (chain == 1 ? I.lbufB[w] : I.lbuf[w]) : nullptr;
+    int32_t* dc = W->dag ? (chain == 1 ? I.dctrB[w] : I.dctr[w]) : nullptr;
     seq_potrf(q, major, Dt(t), bp, bp, logdiag + (int64_t)t * bp, info,
-              (int64_t)t * m.b, m.b, tmp, count_inv, W->fold_inv);
-    if (!W->fold_inv) seq_trtri(q, major, Dt(t), bp, bp, tmp, count_inv ? m.b : 0, xf);
+              (int64_t)t * m.b, m.b, tmp, count_inv, W->fold_inv, lb, dc);
+    if (!W->fold_inv && !W->dag) seq_trtri(q, major, Dt(t), bp, bp, tmp, count_inv ? m.b : 0, xf);
     const int M = (root ? 0 : bp) + apr;
     if (M <= 0) return;
     const double b = m.b, ar = apr ? m.a : 0;
@@ -1263,6 +1325,19 @@ static dl_status build_plans(dl_ws* W) {
   up(H.gemm, W->Dd.gemm);
   up(H.potrf, W->Dd.potrf);
   up(H.panel, W->Dd.panel);
+  up(H.dagb, W->Dd.dagb);
+  up(H.dagt, W->Dd.dagt);
+  if (st == DL_OK && H.dag_launches > 0) {
+    const size_t hb = sizeof(int32_t) * 4 * (size_t)H.dag_launches;
+    st = dev_alloc(W->allocs, hb, (void**)&W->dag_heads, &W->bytes);
+    if (st == DL_OK && hipMemset(W->dag_heads, 0, hb) != hipSuccess) st = DL_EHIP;
+    int dev = 0, cus = 0;
+    if (st == DL_OK && (hipGetDevice(&dev) != hipSuccess ||
+                        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                              dev) != hipSuccess))
+      st = DL_EHIP;
+    W->dag_workers = 2 * std::max(cus, 1);
+  }
   up(H.misc, W->Dd.misc);
   up(H.gn, W->Dd.gn);
   up(H.gt, W->Dd.gt);
@@ -1375,6 +1450,17 @@ static void inst_buffers(const dl_ws* W, Inst& I, Alloc&& A) {
     A(sizeof(double) * m.Np, (void**)&I.xN);
     A(sizeof(double) * 2 * QF_BLOCKS, (void**)&I.tpart);
   }
+  if (W->dag) {
+    const size_t nc = sizeof(int32_t) * (size_t)dag::counters_per_block((int)nbk);
+    for (int w = 0; w < 2; ++w) {
+      A(sizeof(double) * bb, (void**)&I.lbuf[w]);
+      A(nc, (void**)&I.dctr[w]);
+      if (I.two) {
+        A(sizeof(double) * bb, (void**)&I.lbufB[w]);
+        A(nc, (void**)&I.dctrB[w]);
+      }
+    }
+  }
   if (I.two) {
     A(tip, (void**)&I.PcB);
     for (int w = 0; w < 2; ++w) A(ftemp, (void**)&I.ttempB[w]);
@@ -1423,6 +1509,7 @@ static void ws_flags(dl_ws* W, int32_t flags) {
   W->splitk = (flags & DL_WS_SPLITK) != 0;
   W->fold_inv = (flags & DL_WS_FOLD_INV) != 0;
   W->warm = (flags & DL_WS_WARM_START) != 0;
+  W->dag = (flags & DL_WS_DAG) != 0;
 }
 
 // Bytes of the buffers of each instance and of the workspace-wide ones,
@@ -1488,6 +1575,13 @@ extern "C" dl_status dl_ws_create_batch(const dl_model* const* models,
         (hipMemset(I.obs_d, 0, sizeof(double) * (I.m.m_total + 1)) != hipSuccess ||
          hipMemset(I.obs_z, 0, sizeof(double) * (I.m.m_total + 1)) != hipSuccess))
       st = DL_EHIP;
+    if (W->dag && st == DL_OK) {
+      const size_t nc = sizeof(int32_t) * (size_t)dag::counters_per_block(I.m.bp / 64);
+      for (int w = 0; w < 2 && st == DL_OK; ++w)
+        for (int32_t* c : {I.dctr[w], I.dctrB[w]})
+          if (c && hipMemset(c, 0, nc) != hipSuccess) st = DL_EHIP;
+    }
+
   }
   W->dim_total = dim_total;
   ws_buffers(W, nmodels, dim_total, A);

@@ -23,6 +23,8 @@ DL_WS_SPLITK = 16
 DL_WS_TWOSIDED = 32
 DL_WS_FOLD_INV = 64
 DL_WS_WARM_START = 128
+DL_WS_DAG = 256
+DL_INFO_TIMEOUT = -2
 # refinement of the mean (see include/dalia.h)
 DL_REFINE_TOL = 1e-12
 DL_REFINE_MAX = 10
@@ -33,7 +35,7 @@ DL_WAVE_RESERVE = 256 << 20
 CATEGORIES = ("potrf_tile", "panel_trsm", "panel_syrk", "trtri", "trsm",
               "update", "solve", "selinv", "assemble", "other")
 KERNELS = ("k_gemm_tasks", "k_potrf_tile", "gemv", "k_assemble", "other",
-           "k_panel_update", "k_gemm_reduce")
+           "k_panel_update", "k_gemm_reduce", "k_dag_chol")
 STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed",
           3: "not positive definite", 4: "HIP runtime error",
           5: "call order violated", 6: "refinement did not converge"}
@@ -231,14 +233,15 @@ class Model:
 
 def ws_flags(selinv: bool = False, keep_qp: bool = False, graph: bool = False,
              mixed: bool = False, splitk: bool = False, two_sided: bool = False,
-             fold_inverse: bool = False, warm_start: bool = False) -> int:
+             fold_inverse: bool = False, warm_start: bool = False, dag: bool = False) -> int:
     """The DL_WS_* flag word of a workspace."""
     return ((DL_WS_SELINV if selinv else 0) | (DL_WS_KEEP_QP if keep_qp else 0)
             | (DL_WS_GRAPH if graph else 0) | (DL_WS_MIXED if mixed else 0)
             | (DL_WS_SPLITK if splitk else 0)
             | (DL_WS_TWOSIDED if two_sided else 0)
             | (DL_WS_FOLD_INV if fold_inverse else 0)
-            | (DL_WS_WARM_START if warm_start else 0))
+            | (DL_WS_WARM_START if warm_start else 0)
+            | (DL_WS_DAG if dag else 0))
 
 
 def _model_array(models):
@@ -281,13 +284,14 @@ class Workspace:
     def __init__(self, models, selinv: bool = False, keep_qp: bool = False,
                  graph: bool = False, mixed: bool = False, splitk: bool = False,
                  two_sided: bool = False, fold_inverse: bool = False,
-                 warm_start: bool = False, hbm_budget: Optional[int] = None):
+                 warm_start: bool = False, hbm_budget: Optional[int] = None,
+                 dag: bool = False):
         if isinstance(models, Model):
             models = [models]
         self.models = list(models)
         self.model = self.models[0]
         flags = ws_flags(selinv, keep_qp, graph, mixed, splitk, two_sided, fold_inverse,
-                         warm_start)
+                         warm_start, dag)
         h = C.c_void_p()
         arr = (C.c_void_p * len(self.models))(*[m.h for m in self.models])
         if hbm_budget is None:
