@@ -53,40 +53,64 @@ def fac_flops(n, b, a):
             + (n - 1) * (2 * b ** 3 + 2 * a * b * b) + a ** 3 / 3)
 
 
-def cpu_baseline(nt_sample: int = 20, var_samples: int = 8,
-                 model: str = "separable"):
-    """The CPU oracle on a bounded sample of the same workload: the same
-    generator and mesh with nt_sample time steps (2,000 observations per
-    step), scaled linearly in nt (banded Cholesky cost is linear in N for a
-    fixed bandwidth), plus var_samples unit-vector variance solves scaled to
-    all N diagonal entries."""
+# HBM bytes per algorithmic FLOP of the FP64 tile GEMM on the launch shapes
+# of each category, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of the GEMM
+# microbenchmark (64-wide tiles, counters scaled by a plain device copy;
+# profiles/gemm_block_products_traffic.md):
+#   trsm    [B;R] G^T, 2112 x 2048 x 2048, k < col + 64: 610.6 + 34.6 MB / 8.858 GFLOP
+#   update  SYRK lower 2048^2, K 2048:                  174.6 + 16.8 MB / 8.590 GFLOP
+#   selinv  per recursion step: W = [B;R] G (as trsm), Y = -X W (NN 2112 x 2048 x 2112,
+#           432.6 + 34.6 MB / 18.27 GFLOP), X_tt -= Y^T W (as update), G^T G (lower,
+#           k >= row, 224.5 + 16.8 MB / 5.727 GFLOP): 1.545 GB / 41.45 GFLOP
+#   other   NN 2048^3: 307.1 + 33.6 MB / 17.18 GFLOP
+GEMM_BYTES_PER_FLOP = {"trsm": 645.2e6 / 8.858e9, "update": 191.4e6 / 8.590e9,
+                       "selinv": 1.545e9 / 41.45e9, "other": 340.7e6 / 17.18e9}
+
+
+def cpu_model():
+    """The host CPU's model name and logical CPU count."""
+    name = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline(var_samples: int = 8, model: str = "separable"):
+    """The CPU oracle on the benchmark's own workload: one full-size f_obj
+    (RCM + LAPACK banded Cholesky of Q_p and Q_c, the solve for mu, Eq. 8),
+    measured, plus var_samples unit-vector solves with the factor of Q_c for
+    single marginal variances, scaled to all N diagonal entries (the oracle
+    has no selected inversion)."""
     import numpy as np
     from threadpoolctl import threadpool_info
     import workloads as W
     from oracle import fobj as OF
-    wl = W.make_univariate("c1_sample", 45, nt_sample, 4, 2000 * nt_sample,
-                           seed=0, model=model)
+    wl = W.config1(model=model)
     t0 = time.perf_counter()
     p = OF.fobj_parts(wl, wl.theta, method="banded", return_factors=True)
     t1 = time.perf_counter()
     idx = np.random.default_rng(0).choice(wl.N, var_samples, replace=False)
     p["Fc"].inv_diag(idx, chunk=1)
     t2 = time.perf_counter()
-    scale = 100.0 / nt_sample
-    t_fobj = (t1 - t0) * scale
-    N_full = 100 * 2025 + 4
-    t_var = (t2 - t1) / var_samples * N_full * scale
+    t_fobj = t1 - t0
+    t_var = (t2 - t1) / var_samples * wl.N
     threads = max((i.get("num_threads", 1) for i in threadpool_info()),
                   default=1)
+    name, ncpu = cpu_model()
     return {
         "value": 1.0 / (t_fobj + t_var), "unit": "evals/s", "cores": threads,
-        "kind": "oracle",
-        "fobj_only_evals_per_s": 1.0 / t_fobj,
-        "sample": (f"oracle (RCM + LAPACK banded Cholesky) f_obj of the same "
-                   f"generator at nt={nt_sample} ({t1 - t0:.1f} s) scaled x"
-                   f"{scale:g} to nt=100, plus {var_samples} unit-vector "
-                   f"variance solves ({t2 - t1:.1f} s) scaled to all N="
-                   f"{N_full} diagonal entries"),
+        "kind": "oracle", "cpu_model": name, "logical_cpus": ncpu,
+        "fobj_only_evals_per_s": 1.0 / t_fobj, "fobj_seconds_measured": t_fobj,
+        "f": p["f"],
+        "sample": (f"oracle (RCM + LAPACK banded Cholesky) f_obj of {wl.name} at full "
+                   f"size, measured once ({t_fobj:.1f} s); all N={wl.N} marginal "
+                   f"variances extrapolated from {var_samples} unit-vector solves "
+                   f"({t2 - t1:.2f} s) with the same factor"),
     }
 
 
@@ -174,11 +198,21 @@ def mixed(D, wl, model, errors, tiles, two_sided=False):
     f, parts, info = ws.fobj(th)
     torch.cuda.synchronize()
     p = parts.cpu().numpy()[0]
+    # where one evaluation's time goes: summed launch durations (HIP events
+    # around each launch) by operation category and by kernel
+    split = {}
+    for by_kernel in (False, True):
+        ws.profile_begin(D.CATEGORIES, max_launches=40000, by_kernel=by_kernel)
+        ws.fobj(th)
+        torch.cuda.synchronize()
+        split["by_kernel" if by_kernel else "by_category"] = {
+            k: round(v["ms"], 3) for k, v in ws.profile_end().items()}
     del ws
     torch.cuda.empty_cache()
     return {"evals_per_s": 1000.0 / ms, "ms": ms,
             "err_vs_fp64_oracle": errors(p),
-            "refined_mean_rel_residual": float(p[7])}
+            "refined_mean_rel_residual": float(p[7]),
+            "launch_ms": split}
 
 
 def gemm_roofline(prof, steps):
@@ -238,7 +272,6 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-nt", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FD-batch and mixed-precision measurements")
     ap.add_argument("--roofline-only", action="store_true",
@@ -255,6 +288,9 @@ def main():
                     help="elimination order: time steps forward only, or the "
                          "two halves of the time domain concurrently toward "
                          "a middle block (two time-domain partitions)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only run the CPU oracle leg (full-size f_obj on the host, "
+                         "no GPU) and print it")
     ap.add_argument("--diag-factor", choices=("panel", "dag"), default="panel",
                     help="diagonal blocks factored by one launch per 64-column "
                          "panel, or by one persistent tile-task launch per "
@@ -268,6 +304,10 @@ def main():
               "evaluation path is built for a single GPU and does not shard "
               "over several.", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_only:
+        print(json.dumps(cpu_baseline(model=args.model)), flush=True)
+        return
 
     import torch
     from paper_2507_06938_amd import dalia as D
@@ -320,6 +360,19 @@ def main():
     # against the stored oracle values below
     timed_out = (parts.cpu().numpy()[0].copy(), info.cpu().numpy().copy(),
                  var.cpu().numpy().copy(), ws.mean().cpu().numpy())
+    # untimed steps, one per category, recording the GEMM kernel's
+    # algorithmic FLOPs in that category, for the modeled HBM traffic of the
+    # dominant kernel
+    fl = {}
+    for c in gemm_cats:
+        ws.profile_begin((c,), max_launches=40000, by_kernel=True)
+        step()
+        torch.cuda.synchronize()
+        fl[c] = ws.profile_end().get("k_gemm_tasks", {}).get("flops", 0.0)
+    model_bytes = (fl["trsm"] * GEMM_BYTES_PER_FLOP["trsm"]
+                   + fl["update"] * GEMM_BYTES_PER_FLOP["update"]
+                   + fl["selinv"] * GEMM_BYTES_PER_FLOP["selinv"]
+                   + (fl["panel_trsm"] + fl["trtri"]) * GEMM_BYTES_PER_FLOP["other"])
     value = args.steps / (t1 - t0)
     roofline = gemm_roofline(prof, 1)
     roofline["steps_bracketed"] = 1
@@ -367,6 +420,15 @@ def main():
                 "f_abs": abs(p[0] - g["f"])}
     err = errors(pr)
     check = check_timed_step(g, *timed_out)
+    launches = max(1, roofline["launches"])
+    roofline["traffic"] = model_bytes / launches
+    roofline["traffic_source"] = (
+        "modeled, not counted on this process: HBM bytes per algorithmic FLOP measured by "
+        "rocprofv3 FETCH_SIZE/WRITE_SIZE on the GEMM microbenchmark's launch shapes of each "
+        "category (profiles/gemm_block_products_traffic.md), times this step's algorithmic "
+        "FLOPs per category, per k_gemm_tasks launch")
+    roofline["traffic_over_algorithmic_flops_bytes"] = {
+        c: GEMM_BYTES_PER_FLOP[c] for c in GEMM_BYTES_PER_FLOP}
 
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
@@ -398,7 +460,9 @@ def main():
         if args.model == "separable":
             out["poisson_likelihood"] = poisson(D, W, args.tiles, two_sided)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_nt, model=args.model)
+        print("GPU legs done; timing the CPU oracle on the full-size workload",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(model=args.model)
     print(json.dumps(out), flush=True)
     if check is not None and not check["ok"]:
         print("the timed step's outputs are outside the parity tolerances",

@@ -3,6 +3,7 @@ surrogate-guided variant, from seeded starts theta_0 = theta* + 0.25 z.
 
     python -m paper_2507_06938_amd.opt_study --nx 12 --nt 12 --runs 16
     python -m paper_2507_06938_amd.opt_study --config2 --runs 3
+    python -m paper_2507_06938_amd.opt_study --config2 --ref-in ref.json --methods mixed
 
 ``--config2`` takes the production trivariate model (30 x 30 mesh, nt = 48,
 b = 2700, 31-point gradients) instead of the generator at --nx/--nt, and
@@ -12,7 +13,11 @@ b = 2700, 31-point gradients) instead of the generator at --nx/--nt, and
 theta* and F* = -f_obj(theta*) come from a reference FD-BFGS run started at
 the generator's theta and driven to a small gradient.  Each method then runs
 from every start until |F - F*| <= rtol |F*| (or its iteration cap), and the
-study reports exact f_obj evaluations and wall time per run.  Every f_obj
+study reports exact f_obj evaluations and wall time per run.  Methods: ``fd``
+(FD-BFGS on FP64 evaluations), ``surrogate`` (surrogate-guided BFGS) and
+``mixed`` (FD-BFGS on mixed-precision evaluations -- FP32 off-diagonal blocks,
+FP64 diagonal blocks and refined mean -- finished on FP64 ones; the target is
+always tested on FP64 values).  Every f_obj
 value comes from the batched GPU evaluator; the surrogate network is trained
 by the library's MLP kernels.  Prints one JSON document.
 """
@@ -65,7 +70,16 @@ def main(argv=None):
                     help="index of the first seeded start (starts are drawn in order)")
     ap.add_argument("--progress-evals", type=int, default=500,
                     help="print a progress line every this many exact evaluations")
+    ap.add_argument("--methods", default="fd,surrogate",
+                    help="comma-separated subset of fd, surrogate, mixed")
+    ap.add_argument("--fp64-batch", type=int, default=8,
+                    help="instances of the FP64 evaluator when only the mixed method "
+                         "runs and theta* is read from --ref-in (its target checks and "
+                         "finishing gradients then go through it in chunks)")
     args = ap.parse_args(argv)
+    methods = [m.strip() for m in args.methods.split(",") if m.strip()]
+    if not methods or any(m not in ("fd", "surrogate", "mixed") for m in methods):
+        ap.error("--methods takes a comma-separated subset of fd, surrogate, mixed")
 
     if args.config2:
         wl = W.config2(seed=args.seed, likelihood=args.likelihood)
@@ -87,11 +101,17 @@ def main(argv=None):
             v = super().__call__(thetas)
             if self.count - self.mark >= args.progress_evals:
                 self.mark = self.count
-                print(f"  exact evaluations {self.count}, best F {min(self.archive_f):.10f}",
+                best = min(self.archive_f) if self.archive_f else float("nan")
+                print(f"  exact evaluations {self.count}, best F {best:.10f}",
                       file=sys.stderr, flush=True)
             return v
 
-    ev = Logged(model, B, graph=True)
+    # the FP64 evaluator runs the reference and the fd / surrogate methods at
+    # full gradient batch; for the mixed method alone it only checks targets
+    # and finishes, at a smaller batch (the two workspaces share HBM)
+    full64 = "fd" in methods or "surrogate" in methods or not args.ref_in
+    ev = Logged(model, B if full64 else min(B, args.fp64_batch), graph=True)
+    evm = Logged(model, B, graph=True, mixed=True) if "mixed" in methods else None
 
     # reference optimum
     if args.ref_in:
@@ -115,10 +135,13 @@ def main(argv=None):
                            "F_star": float(F_star), "reference": ref_info}, fh)
 
     def fresh():
-        ev.count = 0
-        ev.mark = 0
-        ev.archive_x.clear()
-        ev.archive_f.clear()
+        for e in (ev, evm):
+            if e is None:
+                continue
+            e.count = 0
+            e.mark = 0
+            e.archive_x.clear()
+            e.archive_f.clear()
 
     runs = []
     rng = np.random.default_rng(12345 + args.seed)
@@ -126,31 +149,52 @@ def main(argv=None):
               for _ in range(args.first_run + args.runs)][args.first_run:]
     for k, th0 in enumerate(starts, start=args.first_run):
         row = {"run": k}
-        fresh()
-        t0 = time.perf_counter()
-        tr = O.fd_bfgs(ev, th0, h=1e-3, ftol=0.0, gtol=0.0, max_iter=args.max_iter,
-                       f_target=F_star, target_rtol=args.rtol)
-        torch.cuda.synchronize()
-        row["fd"] = {"exact_evals": tr.exact_evals[-1], "wall_s": time.perf_counter() - t0,
-                     "F": float(tr.f[-1]),
-                     "iters": len(tr.f) - 1,
-                     "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
-                     "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
-        fresh()
-        sur = O.Surrogate(d, hidden=(256, 256, 256),
-                          max_batch=(args.max_iter + 2) * 3 * B, seed=k)
-        t0 = time.perf_counter()
-        tr = O.surrogate_bfgs(ev, th0, sur, h=1e-3, ftol=0.0, gtol=0.0,
-                              max_iter=args.max_iter, f_target=F_star,
-                              target_rtol=args.rtol, train_steps=args.train_steps)
-        torch.cuda.synchronize()
-        row["surrogate"] = {"exact_evals": tr.exact_evals[-1], "F": float(tr.f[-1]),
-                            "wall_s": time.perf_counter() - t0,
+        if "fd" in methods:
+            fresh()
+            t0 = time.perf_counter()
+            tr = O.fd_bfgs(ev, th0, h=1e-3, ftol=0.0, gtol=0.0, max_iter=args.max_iter,
+                           f_target=F_star, target_rtol=args.rtol)
+            torch.cuda.synchronize()
+            row["fd"] = {"exact_evals": tr.exact_evals[-1],
+                         "wall_s": time.perf_counter() - t0,
+                         "F": float(tr.f[-1]),
+                         "iters": len(tr.f) - 1,
+                         "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
+                         "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
+        if "surrogate" in methods:
+            fresh()
+            sur = O.Surrogate(d, hidden=(256, 256, 256),
+                              max_batch=(args.max_iter + 2) * 3 * B, seed=k)
+            t0 = time.perf_counter()
+            tr = O.surrogate_bfgs(ev, th0, sur, h=1e-3, ftol=0.0, gtol=0.0,
+                                  max_iter=args.max_iter, f_target=F_star,
+                                  target_rtol=args.rtol, train_steps=args.train_steps)
+            torch.cuda.synchronize()
+            row["surrogate"] = {
+                "exact_evals": tr.exact_evals[-1], "F": float(tr.f[-1]),
+                "wall_s": time.perf_counter() - t0,
+                "iters": len(tr.f) - 1,
+                "surrogate_steps": tr.kind.count("surrogate"),
+                "fd_steps": tr.kind.count("fd"),
+                "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
+                "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
+        if "mixed" in methods:
+            fresh()
+            t0 = time.perf_counter()
+            tr = O.mixed_fd_bfgs(evm, ev, th0, h=1e-3, ftol=0.0, gtol=0.0,
+                                 max_iter=args.max_iter, f_target=F_star,
+                                 target_rtol=args.rtol)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            F64 = float(ev(np.asarray(tr.theta[-1])[None])[0])
+            row["mixed"] = {"exact_evals": evm.count + ev.count - 1,
+                            "mixed_evals": evm.count, "fp64_evals": ev.count - 1,
+                            "wall_s": wall, "F_fp64": F64,
                             "iters": len(tr.f) - 1,
-                            "surrogate_steps": tr.kind.count("surrogate"),
-                            "fd_steps": tr.kind.count("fd"),
-                            "reached": bool(abs(tr.f[-1] - F_star) <= args.rtol * abs(F_star)),
-                            "rel_gap": float(abs(tr.f[-1] - F_star) / abs(F_star))}
+                            "mixed_steps": tr.kind.count("mixed"),
+                            "fp64_steps": tr.kind.count("fd"),
+                            "reached": bool(abs(F64 - F_star) <= args.rtol * abs(F_star)),
+                            "rel_gap": float(abs(F64 - F_star) / abs(F_star))}
         runs.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
 
@@ -163,8 +207,11 @@ def main(argv=None):
     out = {"workload": wl.name, "N": wl.N, "b": wl.b, "dim_theta": d, "batch": B,
            "F_star": float(F_star), "theta_star": list(map(float, theta_star)),
            "reference": ref_info,
-           "rtol": args.rtol, "start_scale": args.scale,
-           "fd_bfgs": summ("fd"), "surrogate_bfgs": summ("surrogate"), "runs": runs}
+           "rtol": args.rtol, "start_scale": args.scale, "runs": runs}
+    for m, key in (("fd", "fd_bfgs"), ("surrogate", "surrogate_bfgs"),
+                   ("mixed", "mixed_fd_bfgs")):
+        if m in methods:
+            out[key] = summ(m)
     print(json.dumps(out), flush=True)
 
 

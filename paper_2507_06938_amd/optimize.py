@@ -45,6 +45,7 @@ class Trace:
     exact_evals: List[int] = dataclasses.field(default_factory=list)
     wall: List[float] = dataclasses.field(default_factory=list)
     kind: List[str] = dataclasses.field(default_factory=list)
+    H: Optional[np.ndarray] = None  # final inverse-Hessian estimate (BFGS drivers)
 
 
 class Evaluator:
@@ -154,16 +155,22 @@ def _exact_step(ev, x, F, g, H, max_step):
 def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
             f_target: Optional[float] = None, target_rtol: float = 1e-6,
             max_step: float = 1.0, f_check: Optional[Callable[[np.ndarray], float]] = None,
-            count: Optional[Callable[[], int]] = None, kind: str = "fd") -> Trace:
+            count: Optional[Callable[[], int]] = None, kind: str = "fd",
+            H0: Optional[np.ndarray] = None, check_band: float = math.inf,
+            min_progress: float = 0.0) -> Trace:
     """f_check (optional): the value the target test uses at each iterate
-    instead of ev's (an FP64 evaluation when ev is mixed precision); count:
-    the evaluation counter the trace records (default ev.count)."""
+    instead of ev's (an FP64 evaluation when ev is mixed precision), called
+    only where ev's value lies within target_rtol |f_target| + check_band of
+    the target; count: the evaluation counter the trace records (default
+    ev.count); H0: the starting inverse-Hessian estimate (default I, scaled
+    at the first update), returned updated as the trace's H; min_progress:
+    stop once an iteration lowers F by less than this."""
     t0 = time.perf_counter()
     tr = Trace()
     x = np.asarray(theta0, np.float64).copy()
     F, g = fd_gradient(ev, x, h)
-    H = np.eye(x.shape[0])
-    first = True
+    H = np.eye(x.shape[0]) if H0 is None else np.array(H0, np.float64)
+    first = H0 is None
     count = count or (lambda: ev.count)
 
     def log(k):
@@ -173,8 +180,14 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
     log("start")
     for _ in range(max_iter):
         if f_target is not None:
-            Fc = f_check(x) if f_check is not None else F
-            if abs(Fc - f_target) <= target_rtol * abs(f_target):
+            tol = target_rtol * abs(f_target)
+            if f_check is None:
+                Fc = F
+            elif abs(F - f_target) <= tol + check_band:
+                Fc = f_check(x)
+            else:
+                Fc = math.inf
+            if abs(Fc - f_target) <= tol:
                 break
         if np.max(np.abs(g)) <= gtol:
             break
@@ -185,40 +198,63 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
         H = _bfgs_update(H, xn - x, gn - g, first)
         first = False
         rel = abs(Fn2 - F) / max(1.0, abs(F))
+        gain = F - Fn2
         x, F, g = xn, Fn2, gn
         log(kind)
         if f_target is None and rel <= ftol:
             break
+        if gain < min_progress:
+            break
+    tr.H = H
     return tr
 
 
 def mixed_fd_bfgs(ev: Evaluator, ev64: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4,
                   max_iter=100, f_target: Optional[float] = None,
-                  target_rtol: float = 1e-6, max_step: float = 1.0) -> Trace:
+                  target_rtol: float = 1e-6, max_step: float = 1.0,
+                  h_mixed: Optional[float] = None, check_band: float = 1e-5,
+                  stall_rtol: float = 1e-6) -> Trace:
     """FD-BFGS on the mixed-precision evaluator `ev`, then FD-BFGS on the
     FP64 evaluator `ev64` from the point where the mixed search stops (a
     failed line search or ftol/gtol on its values: the floor its FP32
-    rounding puts under the finite differences).  With f_target the target
-    is tested on FP64 values (one ev64 evaluation per mixed iterate).  The
-    trace's f are the evaluator's own values (mixed in the first phase,
-    kind 'mixed'; FP64 in the second, kind 'fd'); exact_evals counts both
+    rounding puts under the finite differences), starting from the mixed
+    phase's inverse-Hessian estimate.
+
+    The mixed phase differences with h_mixed (default 30 h): the FP32
+    rounding of the off-diagonal blocks perturbs f by an amount that does not
+    vary smoothly with theta, so central differences over h would be mostly
+    that noise; over 30 h the noise term shrinks 30-fold while the
+    truncation error stays small far from the optimum, which is where the
+    mixed phase works.  With f_target the target is tested on FP64 values,
+    one ev64 evaluation per mixed iterate whose mixed value is within
+    target_rtol |f_target| + check_band |f_target| of the target.  The mixed
+    phase also stops once an iteration gains less than stall_rtol |F| (gains
+    below the FP32 perturbation are not to be trusted).  The
+    trace's f are the evaluator's own values (mixed in the first phase, kind
+    'mixed'; FP64 in the second, kind 'fd'); exact_evals counts both
     evaluators."""
     total = lambda: ev.count + ev64.count
     check = (lambda x: float(ev64(x[None])[0])) if f_target is not None else None
-    t1 = fd_bfgs(ev, theta0, h=h, ftol=ftol, gtol=gtol, max_iter=max_iter,
+    hm = 30.0 * h if h_mixed is None else h_mixed
+    band = check_band * abs(f_target) if f_target is not None else math.inf
+    t1 = fd_bfgs(ev, theta0, h=hm, ftol=ftol, gtol=gtol, max_iter=max_iter,
                  f_target=f_target, target_rtol=target_rtol, max_step=max_step,
-                 f_check=check, count=total, kind="mixed")
+                 f_check=check, count=total, kind="mixed", check_band=band,
+                 min_progress=stall_rtol * abs(f_target if f_target is not None
+                                                else ev(np.asarray(theta0)[None])[0]))
     x1 = t1.theta[-1]
     if f_target is not None and abs(check(x1) - f_target) <= target_rtol * abs(f_target):
         return t1
+    H1 = t1.H if len(t1.f) > 1 else None  # no accepted mixed step: no curvature yet
     t2 = fd_bfgs(ev64, x1, h=h, ftol=ftol, gtol=gtol, max_iter=max_iter,
                  f_target=f_target, target_rtol=target_rtol, max_step=max_step,
-                 count=total)
+                 count=total, H0=H1)
     off = t1.wall[-1]
     for i in range(len(t2.f)):
         t1.theta.append(t2.theta[i]); t1.f.append(t2.f[i])
         t1.exact_evals.append(t2.exact_evals[i]); t1.wall.append(off + t2.wall[i])
         t1.kind.append("fp64-start" if i == 0 else t2.kind[i])
+    t1.H = t2.H
     return t1
 
 
