@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--cpu-only", action="store_true",
                     help="only run the CPU oracle leg (full-size f_obj on the host, "
                          "no GPU) and print it")
-    ap.add_argument("--diag-factor", choices=("panel", "dag"), default="panel",
+    ap.add_argument("--diag-factor", choices=("panel", "dag"), default="dag",
                     help="diagonal blocks factored by one launch per 64-column "
                          "panel, or by one persistent tile-task launch per "
                          "elimination step")
@@ -339,8 +339,8 @@ def main():
     torch.cuda.synchronize()
 
     # timed region; in its last step the FP64 MFMA GEMM kernel's launches
-    # are bracketed by HIP events on the stream they run on (the fused panel
-    # launches, a separate kernel, are not).  The steps are identical;
+    # are bracketed by HIP events on the stream they run on (the diagonal
+    # blocks' launches, other kernels, are not).  The steps are identical;
     # bracketing every step would add about 14 ms of event packets per step
     # to the timed region.  The event pool is created before timing.
     gemm_cats = ("panel_trsm", "trtri", "trsm", "update", "selinv")

@@ -13,8 +13,15 @@
 //   U(i, k, j)  A(i, k) -= L(i, j) L(k, j)^T   (j < k <= i)
 //   A(r, c, m)  accumulate S(r, c) += L(r, m) G(m, c)   (c <= m <= r - 2)
 //   R(j, c)     G(j, c) = -G_jj (S(j, c) + L(j, j-1) G(j-1, c))   (c < j)
+//   C(k)        the chain from tile k to tile k+1 in one task: S(k+1, k),
+//               then U(k+1, k+1, k) and F(k+1) on the tiles it holds
 // G(j, c) goes into A(j, c) (read by nobody once S(j, c) has run), so on
-// completion the block holds G in its lower triangle.
+// completion the block holds G in its lower triangle.  In the chained form
+// (the one launches use) C(k) stands for S(k+1, k), U(k+1, k+1, k) and
+// F(k+1): the factorisation's critical path -- each tile factor, the solve of
+// the tile below it and that tile's last update -- then runs as one task per
+// tile without handing tiles between workgroups, and C(k) publishes L(k+1, k)
+// as soon as it is stored, before its update and factor.
 //
 // Readiness is tracked by one counter per tile and one per accumulator:
 //   v(r, c): number of updates applied (0 .. c); c + 1 once L(r, c) (or G_cc
@@ -47,11 +54,12 @@
 namespace dl {
 namespace dag {
 
-enum : int { T_F = 0, T_S = 1, T_U = 2, T_A = 3, T_R = 4 };
+enum : int { T_F = 0, T_S = 1, T_U = 2, T_A = 3, T_R = 4, T_C = 5 };
 
 struct Task {
   int type;
-  int i, k, j;  // F: (k, k, k); S: (i, k, k); U: (i, k, j); A: (r, c, m); R: (j, c, c)
+  int i, k, j;  // F: (k, k, k); S: (i, k, k); U: (i, k, j); A: (r, c, m); R: (j, c, c);
+                // C: (k + 1, k, k)
 };
 
 // Counter indices within a block: tiles first, then accumulators.
@@ -67,7 +75,8 @@ struct Wait {
   int value;
 };
 
-// The waits of task t (at most 4) and the counter it sets (and the value).
+// The waits of task t (at most 4) and the counter it sets (and the value)
+// when it completes.
 DL_DAG_FN int waits_of(int nbk, const Task& t, Wait* w, Wait* sets) {
   int n = 0;
   auto gfinal = [&](int m, int c) {  // G(m, c) final
@@ -103,21 +112,40 @@ DL_DAG_FN int waits_of(int nbk, const Task& t, Wait* w, Wait* sets) {
       gfinal(t.i - 1, t.k);
       *sets = {tile_ctr(t.i, t.k), t.k + 2};
       break;
+    case T_C:  // k = t.k: the waits of S(k+1, k), and the earlier updates of tile k+1
+      w[n++] = {tile_ctr(t.k + 1, t.k), t.k};
+      w[n++] = {tile_ctr(t.k, t.k), t.k + 1};
+      w[n++] = {tile_ctr(t.k + 1, t.k + 1), t.k};
+      *sets = {tile_ctr(t.k + 1, t.k + 1), t.k + 2};  // G(k+1, k+1) final
+      break;
   }
   return n;
 }
 
+// The counter a task sets before it completes, if any: C(k) sets
+// v(k+1, k) = k + 1 once L(k+1, k) is stored.  (Its final counter skips
+// v(k+1, k+1) = k + 1, which only its own update would have set.)
+DL_DAG_FN bool mid_set(const Task& t, Wait* s) {
+  if (t.type != T_C) return false;
+  *s = {tile_ctr(t.k + 1, t.k), t.k + 1};
+  return true;
+}
+
 // All tasks of one block in phase order (step j: F(j), S(., j), R(j, .),
-// U(., ., j), A(., ., j)), which is a valid order.
-inline std::vector<Task> phase_order(int nbk, bool inverse) {
+// U(., ., j), A(., ., j)), which is a valid order.  Chained: F(0), and in
+// step j, C(j) in place of S(j+1, j) (it also stands for U(j+1, j+1, j) and
+// F(j+1)).
+inline std::vector<Task> phase_order(int nbk, bool inverse, bool chain = true) {
   std::vector<Task> q;
   for (int j = 0; j < nbk; ++j) {
-    q.push_back({T_F, j, j, j});
-    for (int i = j + 1; i < nbk; ++i) q.push_back({T_S, i, j, j});
+    if (!chain || j == 0) q.push_back({T_F, j, j, j});
+    for (int i = j + 1; i < nbk; ++i)
+      q.push_back(chain && i == j + 1 ? Task{T_C, j + 1, j, j} : Task{T_S, i, j, j});
     if (inverse)
       for (int c = 0; c < j; ++c) q.push_back({T_R, j, c, c});
     for (int k = j + 1; k < nbk; ++k)
-      for (int i = k; i < nbk; ++i) q.push_back({T_U, i, k, j});
+      for (int i = k; i < nbk; ++i)
+        if (!(chain && i == j + 1 && k == j + 1)) q.push_back({T_U, i, k, j});
     if (inverse)
       for (int c = 0; c <= j; ++c)
         for (int r = j + 2; r < nbk; ++r) q.push_back({T_A, r, c, j});
@@ -130,18 +158,22 @@ inline std::vector<Task> phase_order(int nbk, bool inverse) {
 // the tasks and, in `level` and `slack`, each one's earliest start level and
 // the difference between its latest and earliest start levels.
 inline std::vector<Task> schedule(int nbk, bool inverse, std::vector<int>* level = nullptr,
-                                  std::vector<int>* slack = nullptr) {
-  std::vector<Task> q = phase_order(nbk, inverse);
+                                  std::vector<int>* slack = nullptr, bool chain = true) {
+  std::vector<Task> q = phase_order(nbk, inverse, chain);
   const size_t n = q.size();
   const int64_t nc = counters_per_block(nbk);
-  // producer of (counter, value): index into q; counters only step by one
+  // producer of (counter, value): index into q
   std::vector<std::vector<int>> prod(nc);
-  for (size_t t = 0; t < n; ++t) {
-    Wait w[4], s;
-    waits_of(nbk, q[t], w, &s);
+  auto produce = [&](const Wait& s, int t) {
     std::vector<int>& p = prod[s.ctr];
     if ((int)p.size() < s.value + 1) p.resize(s.value + 1, -1);
-    p[s.value] = (int)t;
+    p[s.value] = t;
+  };
+  for (size_t t = 0; t < n; ++t) {
+    Wait w[4], s, m;
+    waits_of(nbk, q[t], w, &s);
+    produce(s, (int)t);
+    if (mid_set(q[t], &m)) produce(m, (int)t);
   }
   std::vector<int> asap(n, 0), alap(n, 0);
   std::vector<std::vector<int>> succ(n);
@@ -150,7 +182,12 @@ inline std::vector<Task> schedule(int nbk, bool inverse, std::vector<int>* level
     const int nw = waits_of(nbk, q[t], w, &s);
     for (int e = 0; e < nw; ++e) {
       if (w[e].value == 0) continue;
-      const int p = prod[w[e].ctr][w[e].value];
+      // the task that brings the counter to the value (or past it: C(k)
+      // steps v(k+1, k+1) by two)
+      const std::vector<int>& pv = prod[w[e].ctr];
+      int v = w[e].value;
+      while (pv[v] < 0) ++v;
+      const int p = pv[v];
       asap[t] = std::max(asap[t], asap[p] + 1);
       succ[p].push_back((int)t);
     }
@@ -194,7 +231,8 @@ DL_DAG_FN Task unpack(uint64_t w, int* block) {
 // The task list of one launch over several blocks: all blocks' tasks
 // sorted by latest start level, then earliest start level, then block, then
 // phase order.
-inline std::vector<uint64_t> launch_list(const std::vector<int>& nbks, bool inverse) {
+inline std::vector<uint64_t> launch_list(const std::vector<int>& nbks, bool inverse,
+                                         bool chain = true) {
   struct Item {
     int alap, asap, block;
     size_t pos;
@@ -203,7 +241,7 @@ inline std::vector<uint64_t> launch_list(const std::vector<int>& nbks, bool inve
   std::vector<Item> all;
   for (size_t b = 0; b < nbks.size(); ++b) {
     std::vector<int> lv, sl;
-    std::vector<Task> s = schedule(nbks[b], inverse, &lv, &sl);
+    std::vector<Task> s = schedule(nbks[b], inverse, &lv, &sl, chain);
     for (size_t p = 0; p < s.size(); ++p) all.push_back({lv[p] + sl[p], lv[p], (int)b, p, s[p]});
   }
   std::stable_sort(all.begin(), all.end(), [](const Item& a, const Item& b) {

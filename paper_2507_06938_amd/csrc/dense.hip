@@ -108,7 +108,9 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ X, int64_t
 // TILE_LDS doubles (Lc[k*LDL + i] = L(i, k), Gk[k*LDL + c] = G(k, c)).
 // Outputs as described for PotrfTileArgs (A/lda: where mode 0 writes L and
 // mode 1 writes G).
-template <int CW, bool COH = false>
+// COH: G (and L) are stored device-coherent; COH_SRC: src is global memory
+// read device-coherent (false: a plain load, for LDS or same-workgroup data).
+template <int CW, bool COH = false, bool COH_SRC = COH>
 __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, double* Lc,
                                            double* Gk, int* sbad, double* A, int64_t lda,
                                            double* Ginv, double* logdiag, int64_t* info,
@@ -121,7 +123,7 @@ __device__ __forceinline__ void potrf_body(const double* src, int64_t lds, doubl
   double r[CW], g[CW];
 #pragma unroll
   for (int q = 0; q < CW; ++q) {
-    r[q] = gload<COH>(&src[(int64_t)i + (int64_t)(CW * wv + q) * lds]);
+    r[q] = gload<COH_SRC>(&src[(int64_t)i + (int64_t)(CW * wv + q) * lds]);
     g[q] = (CW * wv + q == i) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -562,10 +564,11 @@ __global__ __launch_bounds__(POTRF_NT) void k_dag_chol(const uint64_t* __restric
                                                        int ntask,
                                                        const DagBlock* __restrict__ blocks,
                                                        int nblocks, int32_t* head) {
-  __shared__ __align__(16) double pool[2 * TILE_LDS];
+  __shared__ __align__(16) double pool[3 * TILE_LDS];
   __shared__ int s_task, s_bad, s_last;
   double* S0 = pool;
   double* S1 = pool + TILE_LDS;
+  double* S2 = pool + 2 * TILE_LDS;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = l >> 4;
@@ -597,6 +600,45 @@ __global__ __launch_bounds__(POTRF_NT) void k_dag_chol(const uint64_t* __restric
         potrf_body<POTRF_CW, true>(Akk, ld, S0, S1, &s_bad, Akk, ld, nullptr,
                                    B.logdiag + (int64_t)t.k * NB, B.info,
                                    B.row0 + (int64_t)t.k * NB, 1);
+        break;
+      }
+      case dag::T_C: {
+        // S(k+1, k), then U(k+1, k+1, k) and F(k+1) on the tiles in LDS
+        const int k = t.k, k1 = t.k + 1;
+        double vg[DPER], va[DPER], dpre[4];
+        tile_regs<true>(tile(B.A, k, k), ld, vg);    // G_kk
+        tile_regs<true>(tile(B.A, k1, k), ld, va);   // A(k+1, k)
+        double* Ad = tile(B.A, k1, k1);               // A(k+1, k+1), final but for U(., ., k)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) dpre[rg] = cload(&Ad[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld]);
+        regs_to_cols(vg, S1);
+        regs_to_cols(va, S0);
+        __syncthreads();
+        v4d a0 = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(S1, p0, S0, q0, a0, p0 + 16);  // L(m = q0 + lr, c = p0 + lk + 4r)
+        double* Lo = tile(B.L, k1, k);
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) {
+          cstore(&Lo[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld], a0[rg]);
+          S2[(p0 + lk + 4 * rg) * LDL + q0 + lr] = a0[rg];  // S2[c][m] = L(m, c)
+        }
+        // L(k+1, k) published once every lane's stores are complete
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          dag::Wait m;
+          dag::mid_set(t, &m);
+          dag_store(B.ctr + m.ctr, m.value);
+        }
+        v4d u0 = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(S2, p0, S2, q0, u0);  // (L L^T)(m = q0 + lr, n = p0 + lk + 4r)
+        // the updated tile, column-major in S0 (read no more since the barrier)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) S0[(p0 + lk + 4 * rg) * LDL + q0 + lr] = dpre[rg] - u0[rg];
+        __syncthreads();
+        potrf_body<POTRF_CW, true, false>(S0, LDL, S1, S2, &s_bad, Ad, ld, nullptr,
+                                          B.logdiag + (int64_t)k1 * NB, B.info,
+                                          B.row0 + (int64_t)k1 * NB, 1);
         break;
       }
       case dag::T_S: {

@@ -189,6 +189,7 @@ def main(argv=None):
             F64 = float(ev(np.asarray(tr.theta[-1])[None])[0])
             row["mixed"] = {"exact_evals": evm.count + ev.count - 1,
                             "mixed_evals": evm.count, "fp64_evals": ev.count - 1,
+                            "mixed_not_spd": evm.count - len(evm.archive_f),
                             "wall_s": wall, "F_fp64": F64,
                             "iters": len(tr.f) - 1,
                             "mixed_steps": tr.kind.count("mixed"),

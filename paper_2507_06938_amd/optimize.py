@@ -129,7 +129,7 @@ def _line_search(ev: Evaluator, theta, F0, g, p, c1=1e-4, max_passes=4):
 
 def _bfgs_update(H, s, y, first=False):
     ys = float(y @ s)
-    if ys <= 1e-12:
+    if not (ys > 1e-12 and np.isfinite(ys) and np.all(np.isfinite(y))):
         return H
     if first:
         H = (ys / float(y @ y)) * np.eye(H.shape[0])
@@ -179,6 +179,8 @@ def fd_bfgs(ev: Evaluator, theta0, h=1e-3, ftol=1e-6, gtol=1e-4, max_iter=100,
 
     log("start")
     for _ in range(max_iter):
+        if not (np.isfinite(F) and np.all(np.isfinite(g))):
+            break  # a stencil point without a value (not positive definite there)
         if f_target is not None:
             tol = target_rtol * abs(f_target)
             if f_check is None:
@@ -245,7 +247,8 @@ def mixed_fd_bfgs(ev: Evaluator, ev64: Evaluator, theta0, h=1e-3, ftol=1e-6, gto
     x1 = t1.theta[-1]
     if f_target is not None and abs(check(x1) - f_target) <= target_rtol * abs(f_target):
         return t1
-    H1 = t1.H if len(t1.f) > 1 else None  # no accepted mixed step: no curvature yet
+    # no accepted mixed step: no curvature yet
+    H1 = t1.H if len(t1.f) > 1 and np.all(np.isfinite(t1.H)) else None
     t2 = fd_bfgs(ev64, x1, h=h, ftol=ftol, gtol=gtol, max_iter=max_iter,
                  f_target=f_target, target_rtol=target_rtol, max_step=max_step,
                  count=total, H0=H1)

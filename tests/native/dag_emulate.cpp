@@ -3,9 +3,11 @@
 // protocol -- each worker takes the next task of the list, waits for the
 // counters it needs, runs it and sets its counter -- with 1 to 512 workers
 // and runnable tasks finishing in random order, on plain arrays with tiles
-// of TS x TS, and checks that
+// of TS x TS, in the chained form (C tasks) and the unchained one, and
+// checks that
 //   * every value a task waits for is set by an earlier task of the list and
-//     every counter steps by one;
+//     every counter steps by one (C(k)'s final counter by two, past the value
+//     its own update would have set);
 //   * the workers never all wait with nothing runnable (no deadlock);
 //   * tasks runnable at the same time never conflict on a tile (one writes
 //     what the other reads or writes): the waits order every conflicting pair;
@@ -68,9 +70,19 @@ static void trinv(const std::vector<double>& Lm, std::vector<double>& G, int n) 
   }
 }
 
-static void run_task(Block& B, const Task& t) {
+static void run_task(Block& B, const Task& t, int phase = 0) {
   const int TS = B.TS;
   auto R0 = [&](int i) { return i * TS; };
+  if (t.type == T_C) {  // phase 0: S(k+1, k); phase 1: U(k+1, k+1, k), then F(k+1)
+    const int k = t.k;
+    if (phase == 0) {
+      run_task(B, Task{T_S, k + 1, k, k});
+    } else {
+      run_task(B, Task{T_U, k + 1, k + 1, k});
+      run_task(B, Task{T_F, k + 1, k + 1, k + 1});
+    }
+    return;
+  }
   switch (t.type) {
     case T_F: {
       const int k = t.k;
@@ -135,10 +147,21 @@ static void run_task(Block& B, const Task& t) {
 // Tiles a task reads and writes, as (kind, row, col): kind 0 = A (or G), 1 =
 // L, 2 = accumulator.
 struct Acc { int kind, r, c; };
-static void footprint(const Task& t, std::vector<Acc>& rd, std::vector<Acc>& wr) {
+static void footprint(const Task& t, std::vector<Acc>& rd, std::vector<Acc>& wr,
+                      int phase = 0) {
   rd.clear();
   wr.clear();
   switch (t.type) {
+    case T_C:  // phase 0 also reads tile (k+1, k+1), which the kernel loads up front
+      if (phase == 0) {
+        rd.push_back({0, t.k + 1, t.k}); rd.push_back({0, t.k, t.k});
+        rd.push_back({0, t.k + 1, t.k + 1});
+        wr.push_back({1, t.k + 1, t.k});
+      } else {
+        rd.push_back({1, t.k + 1, t.k}); rd.push_back({0, t.k + 1, t.k + 1});
+        wr.push_back({0, t.k + 1, t.k + 1});
+      }
+      break;
     case T_F: rd.push_back({0, t.k, t.k}); wr.push_back({0, t.k, t.k}); break;
     case T_S: rd.push_back({0, t.i, t.k}); rd.push_back({0, t.k, t.k}); wr.push_back({1, t.i, t.k}); break;
     case T_U:
@@ -172,8 +195,9 @@ static bool overlap(const std::vector<Acc>& a, const std::vector<Acc>& b) {
 // waits on earlier tasks, that the workers never all wait with nothing
 // runnable (deadlock), that tasks runnable at the same time never conflict
 // on a tile, and the numerical result.
-static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int workers) {
-  const std::vector<uint64_t> list = launch_list(nbks, true);
+static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int workers,
+                      bool chain) {
+  const std::vector<uint64_t> list = launch_list(nbks, true, chain);
   const size_t n = list.size();
   std::vector<std::vector<int>> ctr(nbks.size());
   for (size_t b = 0; b < nbks.size(); ++b) ctr[b].assign(counters_per_block(nbks[b]), 0);
@@ -182,11 +206,16 @@ static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int w
     for (size_t t = 0; t < n; ++t) {
       int b = 0;
       const Task task = unpack(list[t], &b);
-      Wait w[4], st;
+      Wait w[4], st, md;
       const int nw = waits_of(nbks[b], task, w, &st);
       for (int e = 0; e < nw; ++e)
         if (c2[b][w[e].ctr] < w[e].value) return fail("wait on a later task", nbks[b], t);
-      if (c2[b][st.ctr] + 1 != st.value) return fail("counter does not step by one", nbks[b], t);
+      if (mid_set(task, &md)) {
+        if (c2[b][md.ctr] + 1 != md.value) return fail("counter does not step by one", nbks[b], t);
+        c2[b][md.ctr] = md.value;
+      }
+      const int step = task.type == T_C ? 2 : 1;
+      if (c2[b][st.ctr] + step != st.value) return fail("counter does not step by one", nbks[b], t);
       c2[b][st.ctr] = st.value;
     }
   }
@@ -217,8 +246,12 @@ static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int w
   }
   size_t next = 0, done = 0;
   std::vector<size_t> held;  // list positions held by the workers
-  while ((int)held.size() < workers && next < n) held.push_back(next++);
-  size_t count[5] = {0, 0, 0, 0, 0};
+  std::vector<int> phase;    // 1: a C task past its published solve
+  while ((int)held.size() < workers && next < n) {
+    held.push_back(next++);
+    phase.push_back(0);
+  }
+  size_t count[6] = {0, 0, 0, 0, 0, 0};
   std::vector<Acc> rd1, wr1, rd2, wr2;
   std::vector<size_t> ready;
   while (done < n) {
@@ -229,7 +262,7 @@ static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int w
       Wait w[4], st;
       const int nw = waits_of(nbks[b], task, w, &st);
       bool ok = true;
-      for (int e = 0; e < nw; ++e) ok = ok && ctr[b][w[e].ctr] >= w[e].value;
+      for (int e = 0; e < nw && phase[h] == 0; ++e) ok = ok && ctr[b][w[e].ctr] >= w[e].value;
       if (ok) ready.push_back(h);
     }
     if (ready.empty()) return fail("deadlock: every worker waits", 0, done);
@@ -240,22 +273,34 @@ static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int w
         const Task t1 = unpack(list[held[ready[x]]], &b1);
         const Task t2 = unpack(list[held[ready[y]]], &b2);
         if (b1 != b2) continue;
-        footprint(t1, rd1, wr1);
-        footprint(t2, rd2, wr2);
+        footprint(t1, rd1, wr1, phase[ready[x]]);
+        footprint(t2, rd2, wr2, phase[ready[y]]);
         if (overlap(wr1, rd2) || overlap(wr1, wr2) || overlap(rd1, wr2))
           return fail("conflicting runnable tasks", nbks[b1], held[ready[x]]);
       }
     const size_t h = ready[(size_t)(rng() % ready.size())];
     int b = 0;
     const Task task = unpack(list[held[h]], &b);
-    Wait w[4], st;
+    Wait w[4], st, md;
     waits_of(nbks[b], task, w, &st);
-    run_task(blocks[b], task);
+    if (task.type == T_C && phase[h] == 0) {  // the solve, then its counter
+      run_task(blocks[b], task, 0);
+      mid_set(task, &md);
+      ctr[b][md.ctr] = md.value;
+      phase[h] = 1;
+      continue;
+    }
+    run_task(blocks[b], task, phase[h]);
     ctr[b][st.ctr] = st.value;
     ++count[task.type];
     ++done;
-    if (next < n) held[h] = next++;
-    else held.erase(held.begin() + h);
+    if (next < n) {
+      held[h] = next++;
+      phase[h] = 0;
+    } else {
+      held.erase(held.begin() + h);
+      phase.erase(phase.begin() + h);
+    }
   }
   for (size_t b = 0; b < nbks.size(); ++b) {
     Block& B = blocks[b];
@@ -273,8 +318,9 @@ static int check_case(const std::vector<int>& nbks, int TS, unsigned seed, int w
     if (!(err <= 1e-11 * gmax)) { std::printf("G error %g (max %g)\n", err, gmax); return fail("inverse", nbk, 0); }
     if (!(std::fabs(ld - B.logdet) <= 1e-11 * std::fabs(ld))) return fail("logdet", nbk, 0);
   }
-  std::printf("ok blocks=%zu workers=%d tasks=%zu F=%zu S=%zu U=%zu A=%zu R=%zu\n", nbks.size(),
-              workers, n, count[0], count[1], count[2], count[3], count[4]);
+  std::printf("ok %s blocks=%zu workers=%d tasks=%zu F=%zu S=%zu U=%zu A=%zu R=%zu C=%zu\n",
+              chain ? "chained" : "unchained", nbks.size(), workers, n, count[0], count[1],
+              count[2], count[3], count[4], count[5]);
   return 0;
 }
 
@@ -285,9 +331,10 @@ int main() {
     const int TS = cases[c][0] >= 16 ? 3 : 5;
     const bool big = cases[c].size() * cases[c][0] >= 32;
     for (int w : workers)
-      if (!(big && (w == 3 || w == 512)) &&
-          check_case(cases[c], TS, 17 + (unsigned)c * 7 + (unsigned)w, w))
-        return 1;
+      for (bool chain : {true, false})
+        if (!(big && (w == 3 || w == 512)) &&
+            check_case(cases[c], TS, 17 + (unsigned)c * 7 + (unsigned)w, w, chain))
+          return 1;
   }
   return 0;
 }
