@@ -1,6 +1,7 @@
 """Write the stored expected values of the full-size parity tests.
 
     python tests/golden/make_golden.py c1 [c2] [c1_diffusion] [c1_poisson] [c2_poisson]
+    python tests/golden/make_golden.py opt_tri
 
 Calls only the CPU oracle (``oracle/``) on the seeded workloads of
 ``workloads/``; nothing here touches the GPU path.  For each configuration it
@@ -9,7 +10,9 @@ the marginal variances diag(Q_c^{-1}) at seeded sample positions (BTA order,
 plus every fixed effect), computed with the RCM + banded LAPACK route.  For
 the Poisson workload the mean is the inner mode and the variances are those
 of the Laplace approximation, diag(Q_c(x*)^{-1}); the Newton step count is
-stored too.
+stored too.  ``opt_tri`` stores the mode of a small trivariate model
+(dim theta = 15, the surrogate's input width) found by the oracle's BFGS on
+its own f_obj with central differences (Eq. 9, 10), from a seeded start.
 """
 import json
 import os
@@ -67,6 +70,29 @@ def make(name):
           f"ld_c={out['logdet_c']:.6f} ({t1 - t0:.1f}s + {t2 - t1:.1f}s) -> {path}")
 
 
+def opt_tri_workload():
+    """The small trivariate model of the mode-search test (15 hyperparameters)."""
+    return W.scaled("opt_tri", 5, 4, 3, 2, 60, seed=11)
+
+
+def make_opt_tri():
+    from oracle import bfgs as OB
+    wl = opt_tri_workload()
+    theta0 = W.random_theta_near(wl.theta, 0.25, seed=3)
+    F = lambda t: -OF.fobj(wl, t)
+    fg = lambda t: (F(t), OB.central_gradient(F, t, 1e-3))
+    t0 = time.time()
+    x, f, hist = OB.bfgs_minimize(fg, theta0, max_iter=300, ftol=1e-13, gtol=1e-6)
+    out = dict(workload=wl.name, dim_theta=int(wl.dim_theta), theta0=theta0.tolist(),
+               theta_star=np.asarray(x).tolist(), F_star=float(f), iterations=len(hist) - 1,
+               oracle="BFGS on the oracle's f_obj, central differences h = 1e-3",
+               seconds=time.time() - t0)
+    path = os.path.join(HERE, "opt_tri_optimum.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"opt_tri: F*={out['F_star']:.12f} in {out['iterations']} iterations -> {path}")
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:] or ["c1"]:
-        make(n)
+        make_opt_tri() if n == "opt_tri" else make(n)

@@ -83,3 +83,34 @@ def test_mixed_fd_bfgs_reaches_oracle_optimum(problem):
           f"mixed evals={ev.count} fp64 evals={ev64.count}", flush=True)
     assert abs(F64 - fs) <= REL * abs(fs)
     assert ev.count > 0 and tr.kind.count("mixed") >= 1
+
+
+def test_c4_network_on_fifteen_hyperparameters():
+    """The surrogate at its configured width -- 15 -> 256 -> 256 -> 256 -> 1
+    (135,937 parameters) -- on a small trivariate model with 15
+    hyperparameters: plain FD-BFGS and the surrogate-guided driver both reach
+    the oracle's BFGS optimum (stored by tests/golden/make_golden.py opt_tri)
+    to 1e-6 from the same start; the exact-evaluation counts are printed."""
+    import json
+    import os
+    from paper_2507_06938_amd import dalia as D
+    from paper_2507_06938_amd import optimize as O
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "opt_tri_optimum.json")))
+    wl = W.scaled("opt_tri", 5, 4, 3, 2, 60, seed=11)
+    assert g["workload"] == wl.name and g["dim_theta"] == wl.dim_theta == 15
+    fs, theta0 = g["F_star"], np.asarray(g["theta0"])
+    model = D.Model.from_workload(wl)
+    ev = O.Evaluator(model, batch=2 * wl.dim_theta + 1)
+    tr = O.fd_bfgs(ev, theta0, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300)
+    fd_evals = ev.count
+    ev2 = O.Evaluator(model, batch=2 * wl.dim_theta + 1)
+    sur = O.Surrogate(wl.dim_theta, hidden=(256, 256, 256), max_batch=4096, seed=0)
+    assert sur.net.params.numel() == 135937
+    ts = O.surrogate_bfgs(ev2, theta0, sur, h=1e-3, ftol=1e-13, gtol=1e-6, max_iter=300,
+                          train_steps=100)
+    kinds = {k: ts.kind.count(k) for k in set(ts.kind)}
+    print(f"oracle F*={fs:.12f}  fd F={tr.f[-1]:.12f} ({fd_evals} exact evals)  "
+          f"surrogate F={ts.f[-1]:.12f} ({ev2.count} exact evals, steps {kinds})", flush=True)
+    assert abs(tr.f[-1] - fs) <= REL * abs(fs)
+    assert abs(ts.f[-1] - fs) <= REL * abs(fs)
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(ts.f, ts.f[1:]))
