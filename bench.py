@@ -127,7 +127,7 @@ def _events_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def fd_batch(D, W, wl, model, single_ms, tiles, two_sided=False):
+def fd_batch(D, W, wl, model, single_ms, tiles, two_sided=False, dag=False):
     """The 2 dim(theta) + 1 = 9 central-difference points of one gradient
     (Eq. 10, h = 1e-3) as one batched, graph-replayed evaluation."""
     import numpy as np
@@ -139,7 +139,7 @@ def fd_batch(D, W, wl, model, single_ms, tiles, two_sided=False):
         pts[1 + 2 * i, i] += h
         pts[2 + 2 * i, i] -= h
     th = torch.tensor(pts, dtype=torch.float64, device="cuda")
-    ws = D.Workspace([model] * (2 * d + 1), graph=True, two_sided=two_sided)
+    ws = D.Workspace([model] * (2 * d + 1), graph=True, two_sided=two_sided, dag=dag)
     if tiles:
         ws.autotune(tiles)
     ms = _events_ms(torch, lambda: ws.fobj(th), 3)
@@ -186,11 +186,11 @@ def poisson(D, W, tiles, two_sided=False):
     return out
 
 
-def mixed(D, wl, model, errors, tiles, two_sided=False):
+def mixed(D, wl, model, errors, tiles, two_sided=False, dag=False):
     """f_obj with FP32 off-diagonal blocks (FP64 diagonal blocks, tip and
     refinement of the mean) at the same theta."""
     import torch
-    ws = D.Workspace(model, mixed=True, two_sided=two_sided, fold_inverse=True)
+    ws = D.Workspace(model, mixed=True, two_sided=two_sided, fold_inverse=not dag, dag=dag)
     if tiles:
         ws.autotune(tiles)
     th = torch.tensor(wl.theta, dtype=torch.float64, device="cuda")
@@ -454,9 +454,11 @@ def main():
     del ws
     torch.cuda.empty_cache()
     if not args.no_extras:
+        # (the batch keeps the panel launches: with nine instances' blocks in
+        # each persistent launch it measured 7.5 evals/s against 8.8)
         out["fd_gradient_batch"] = fd_batch(D, W, wl, model, fobj_ms, args.tiles,
-                                            two_sided)
-        out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles, two_sided)
+                                            two_sided, dag=False)
+        out["mixed_precision"] = mixed(D, wl, model, errors, args.tiles, two_sided, dag)
         if args.model == "separable":
             out["poisson_likelihood"] = poisson(D, W, args.tiles, two_sided)
     if not args.no_cpu_baseline:
