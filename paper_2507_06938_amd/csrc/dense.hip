@@ -622,7 +622,14 @@ __global__ __launch_bounds__(POTRF_NT) void k_dag_chol(const uint64_t* __restric
           cstore(&Lo[(q0 + lr) + (int64_t)(p0 + lk + 4 * rg) * ld], a0[rg]);
           S2[(p0 + lk + 4 * rg) * LDL + q0 + lr] = a0[rg];  // S2[c][m] = L(m, c)
         }
-        // L(k+1, k) published once every lane's stores are complete
+        __syncthreads();
+        v4d u0 = {0.0, 0.0, 0.0, 0.0};
+        mfma1_k64(S2, p0, S2, q0, u0);  // (L L^T)(m = q0 + lr, n = p0 + lk + 4r)
+        // the updated tile, column-major in S0 (read no more since the barrier)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) S0[(p0 + lk + 4 * rg) * LDL + q0 + lr] = dpre[rg] - u0[rg];
+        // L(k+1, k) published once every lane's stores are complete (their
+        // latency overlaps the update above)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -630,12 +637,6 @@ __global__ __launch_bounds__(POTRF_NT) void k_dag_chol(const uint64_t* __restric
           dag::mid_set(t, &m);
           dag_store(B.ctr + m.ctr, m.value);
         }
-        v4d u0 = {0.0, 0.0, 0.0, 0.0};
-        mfma1_k64(S2, p0, S2, q0, u0);  // (L L^T)(m = q0 + lr, n = p0 + lk + 4r)
-        // the updated tile, column-major in S0 (read no more since the barrier)
-#pragma unroll
-        for (int rg = 0; rg < 4; ++rg) S0[(p0 + lk + 4 * rg) * LDL + q0 + lr] = dpre[rg] - u0[rg];
-        __syncthreads();
         potrf_body<POTRF_CW, true, false>(S0, LDL, S1, S2, &s_bad, Ad, ld, nullptr,
                                           B.logdiag + (int64_t)k1 * NB, B.info,
                                           B.row0 + (int64_t)k1 * NB, 1);
